@@ -1,0 +1,181 @@
+"""ctypes front end of the CPU oracle (``dpr1_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: a plain, slow implementation of Algorithm 1 of
+Jakovcevic Stor, Slapnicar and Barlow (forward-stable eigendecomposition of
+D + rho z z^T), in binary64 with binary128 where the paper asks for double the
+working precision.  Imported only by ``tests/``, ``__graft_entry__.smoke`` and
+the ``cpu_baseline`` leg of ``bench.py``.  It shares no code with the GPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dpr1_oracle.c")
+_LIB = os.path.join(_HERE, "libdpr1_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, OpenMP, libquadmath)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+            "-shared", "-Wall", "-o", tmp, _SRC, "-lquadmath", "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Opts(C.Structure):
+    _fields_ = [("mode_b", C.c_int32), ("polish", C.c_int32),
+                ("kappa_polish", C.c_double), ("nearzero", C.c_double)]
+
+
+class EigDiag(C.Structure):
+    _fields_ = [("i", C.c_int32), ("side", C.c_int32), ("used_ext_b", C.c_int32),
+                ("polished", C.c_int32), ("nearzero", C.c_int32), ("singular", C.c_int32),
+                ("bisect_iters", C.c_int32), ("polish_iters", C.c_int32),
+                ("sigma", C.c_double), ("mu", C.c_double), ("nu", C.c_double),
+                ("lam", C.c_double), ("b", C.c_double), ("Kb", C.c_double),
+                ("Kz", C.c_double), ("kappa_nu_bound", C.c_double), ("kappa_g", C.c_double),
+                ("xnorm", C.c_double)]
+
+
+DIAG_FIELDS = [f for f, _ in EigDiag._fields_]
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        L.oracle_dpr1eig.argtypes = [dp, dp, C.c_double, C.c_int64, C.c_int64,
+                                     C.POINTER(Opts), dp, dp, C.POINTER(EigDiag)]
+        L.oracle_dpr1eig_all.argtypes = [dp, dp, C.c_double, C.c_int64, C.POINTER(Opts),
+                                         dp, dp, C.c_int64, C.POINTER(EigDiag), C.c_int]
+        L.oracle_dpr1eig_some.argtypes = [dp, dp, C.c_double, C.c_int64, C.POINTER(C.c_int64),
+                                          C.c_int64, C.POINTER(Opts), dp, dp, C.c_int64,
+                                          C.POINTER(EigDiag), C.c_int]
+        L.oracle_dpr1_backward.argtypes = [dp, dp, C.c_double, C.c_int64, dp, dp, dp, dp, dp,
+                                           dp, dp, dp, C.c_int]
+        L.oracle_check.argtypes = [dp, dp, C.c_double, C.c_int64]
+        L.oracle_max_threads.restype = C.c_int
+        L.oracle_tip.argtypes = [dp, dp, C.c_double, C.c_int64, C.c_int64, C.c_int32, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def make_opts(mode_b=0, polish=1, kappa_polish=16.0, nearzero=10.0) -> Opts:
+    return Opts(mode_b, polish, kappa_polish, nearzero)
+
+
+def diag_to_dict(dg: np.ndarray | EigDiag):
+    return {f: getattr(dg, f) for f in DIAG_FIELDS}
+
+
+def eig(d, z, rho, vectors=True, opts: Opts | None = None, nthreads=0, diags=False):
+    """All eigenpairs.  Returns (lam[n], V[n,n] column k = v_k or None[, diag list])."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n = d.size
+    lam = np.empty(n)
+    # V stored column-major: column k contiguous -> use a (n, n) array indexed [k, j]
+    Vt = np.empty((n, n)) if vectors else None
+    dg = (EigDiag * n)() if diags else None
+    rc = lib().oracle_dpr1eig_all(_p(d), _p(z), float(rho), n,
+                                  C.byref(opts) if opts is not None else None,
+                                  _p(lam), _p(Vt), n, dg, int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_dpr1eig_all failed with code {rc}")
+    V = Vt.T if vectors else None
+    if diags:
+        return lam, V, [diag_to_dict(x) for x in dg]
+    return lam, V
+
+
+def eig_one(d, z, rho, k, vectors=True, opts: Opts | None = None):
+    """One eigenpair (0-based k); rho must be positive.  Returns (lam, v, diag)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n = d.size
+    lam = C.c_double()
+    v = np.empty(n) if vectors else None
+    dg = EigDiag()
+    rc = lib().oracle_dpr1eig(_p(d), _p(z), float(rho), n, int(k),
+                              C.byref(opts) if opts is not None else None,
+                              C.byref(lam), _p(v), C.byref(dg))
+    if rc != 0:
+        raise ValueError(f"oracle_dpr1eig failed with code {rc}")
+    return lam.value, v, diag_to_dict(dg)
+
+
+def eig_some(d, z, rho, ks, vectors=False, opts: Opts | None = None, nthreads=0):
+    """Eigenpairs for the listed 0-based indices only (rho > 0)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    n, nk = d.size, ks.size
+    lam = np.empty(nk)
+    Vt = np.empty((nk, n)) if vectors else None
+    dg = (EigDiag * nk)()
+    rc = lib().oracle_dpr1eig_some(_p(d), _p(z), float(rho), n,
+                                   ks.ctypes.data_as(C.POINTER(C.c_int64)), nk,
+                                   C.byref(opts) if opts is not None else None,
+                                   _p(lam), _p(Vt), n, dg, int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_dpr1eig_some failed with code {rc}")
+    return lam, (Vt.T if vectors else None), [diag_to_dict(x) for x in dg]
+
+
+def check(d, z, rho) -> int:
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    return lib().oracle_check(_p(d), _p(z), float(rho), d.size)
+
+
+def backward(d, z, rho, sigma, mu, V, lam_bar=None, V_bar=None, nthreads=0):
+    """Dense reverse-mode derivative (explicit Abar = V X V^T).  V[j, k] = v_k[j]."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n = d.size
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    Vc = np.asfortranarray(V, dtype=np.float64)
+    Vbc = np.asfortranarray(V_bar, dtype=np.float64) if V_bar is not None else None
+    lb = np.ascontiguousarray(lam_bar, dtype=np.float64) if lam_bar is not None else None
+    db, zb = np.empty(n), np.empty(n)
+    rb = C.c_double()
+    fp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+    rc = lib().oracle_dpr1_backward(_p(d), _p(z), float(rho), n, _p(sigma), _p(mu),
+                                    fp(Vc), _p(lb), fp(Vbc), _p(db), _p(zb), C.byref(rb),
+                                    int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_dpr1_backward failed with code {rc}")
+    return db, zb, rb.value
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
+
+
+def tip(d, z, rho, i, mode=0):
+    """(b, K_b) of A_i^{-1} for shift index i (0-based); mode 0 binary128, 2 binary64."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    b, kb = C.c_double(), C.c_double()
+    rc = lib().oracle_tip(_p(d), _p(z), float(rho), d.size, int(i), int(mode),
+                          C.byref(b), C.byref(kb))
+    if rc != 0:
+        raise ValueError(f"oracle_tip failed with code {rc}")
+    return b.value, kb.value

@@ -1,0 +1,126 @@
+"""Seeded synthetic DPR1 inputs.
+
+Pure input generation (NumPy PCG64 streams): no arithmetic of the eigensolver
+lives here.  Both the GPU path and the CPU oracle are fed from these arrays.
+
+Workload families (all float64):
+
+* ``uniform``  -- d sorted-descending distinct draws from U[-1, 1],
+  z ~ N(0, 1) (optionally scaled by 1/sqrt(n)), rho given;
+* ``graded``   -- d_i = 10^(-12 (i-1)/(n-1)), every 64th pole pushed to a
+  relative gap of 1e-10 from its predecessor, |z_i| = 10^U(-8, 0) with fair
+  random signs, rho = 1e-3;
+* ``batched``  -- many independent uniform problems with sizes log-uniform in
+  [16, 2048] and rho ~ U[0.1, 10], packed back to back with int64 offsets;
+* paper examples 1-4 (Sec. 3), built from their printed definitions.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _sorted_distinct_uniform(rng, n, lo=-1.0, hi=1.0):
+    while True:
+        d = np.sort(rng.uniform(lo, hi, n))[::-1].copy()
+        if n < 2 or np.all(d[:-1] > d[1:]):
+            return d
+
+
+def uniform(n, seed, rho=1.0, zscale=1.0):
+    rng = np.random.default_rng(seed)
+    d = _sorted_distinct_uniform(rng, n)
+    z = rng.standard_normal(n) * zscale
+    z[z == 0.0] = 1e-300
+    return d, z, float(rho)
+
+
+def graded(n, seed, rho=1e-3, pair_every=64, pair_gap=1e-10):
+    rng = np.random.default_rng(seed)
+    i = np.arange(n, dtype=np.float64)
+    d = 10.0 ** (-12.0 * i / (n - 1))
+    for p in range(pair_every, n, pair_every):          # 1-based p = 64, 128, ...
+        d[p] = d[p - 1] * (1.0 - pair_gap)               # d_{p+1} = d_p (1 - gap)
+    mag = 10.0 ** rng.uniform(-8.0, 0.0, n)
+    sgn = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    z = mag * sgn
+    assert np.all(d[:-1] > d[1:])
+    return d, z, float(rho)
+
+
+def batched_sizes(nprob, seed, nmin=16, nmax=2048):
+    rng = np.random.default_rng(seed)
+    return np.round(np.exp(rng.uniform(math.log(nmin), math.log(nmax), nprob))).astype(np.int64), rng
+
+
+def batched(nprob, seed, nmin=16, nmax=2048, rho_lo=0.1, rho_hi=10.0, sizes=None):
+    """Packed ragged batch: returns (d, z, rho[nprob], offs[nprob+1])."""
+    if sizes is None:
+        sizes, rng = batched_sizes(nprob, seed, nmin, nmax)
+    else:
+        sizes = np.asarray(sizes, dtype=np.int64)
+        rng = np.random.default_rng(seed)
+    offs = np.zeros(nprob + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    d = np.empty(offs[-1])
+    z = np.empty(offs[-1])
+    rho = np.empty(nprob)
+    for p in range(nprob):
+        a, b = offs[p], offs[p + 1]
+        d[a:b] = _sorted_distinct_uniform(rng, b - a)
+        zz = rng.standard_normal(b - a)
+        zz[zz == 0.0] = 1e-300
+        z[a:b] = zz
+        rho[p] = rng.uniform(rho_lo, rho_hi)
+    return d, z, rho, offs
+
+
+def uniform_batch(nprob, n, seed, rho=1.0):
+    """nprob problems of equal size n, d U[-1,1] sorted, z ~ N(0,1): arrays [nprob, n]."""
+    rng = np.random.default_rng(seed)
+    d = np.empty((nprob, n))
+    z = np.empty((nprob, n))
+    for p in range(nprob):
+        d[p] = _sorted_distinct_uniform(rng, n)
+        z[p] = rng.standard_normal(n)
+    z[z == 0.0] = 1e-300
+    return d, z, np.full(nprob, float(rho))
+
+
+# ----------------------------------------------------------- paper examples
+def example1():
+    """Sec. 3, Example 1: D = diag(1e10, 5, 4e-3, 0, -4e-3, -5), z = (1e10,1,1,1e-7,1,1), rho = 1."""
+    d = np.array([1e10, 5.0, 4e-3, 0.0, -4e-3, -5.0])
+    z = np.array([1e10, 1.0, 1.0, 1e-7, 1.0, 1.0])
+    return d, z, 1.0
+
+
+def example2():
+    """Sec. 3, Example 2: D = 1 + (40, 30, 20, 10) * 2^-52, z = (1, 2, 2, 1), rho = 1."""
+    e = 2.0 ** -52
+    d = np.array([1 + 40 * e, 1 + 30 * e, 1 + 20 * e, 1 + 10 * e])
+    z = np.array([1.0, 2.0, 2.0, 1.0])
+    return d, z, 1.0
+
+
+def example3(beta=1e-7):
+    """Sec. 3, Example 3: D = diag(10/3, 2+beta, 2-beta, 1), z = (2, beta, beta, 2), rho = 1."""
+    d = np.array([10.0 / 3.0, 2.0 + beta, 2.0 - beta, 1.0])
+    z = np.array([2.0, beta, beta, 2.0])
+    return d, z, 1.0
+
+
+def example4(beta, m=100):
+    """Sec. 3, Example 4: D = {1, 2 +- j beta (j = 1..m), 10/3}, z = (2, beta, ..., beta, 2),
+    put in decreasing order of D (symmetric permutation, Sec. 1)."""
+    dd = [1.0]
+    zz = [2.0]
+    for j in range(1, m + 1):
+        dd += [2.0 + j * beta, 2.0 - j * beta]
+        zz += [beta, beta]
+    dd.append(10.0 / 3.0)
+    zz.append(2.0)
+    dd, zz = np.array(dd), np.array(zz)
+    order = np.argsort(-dd, kind="stable")
+    return dd[order].copy(), zz[order].copy(), 1.0
