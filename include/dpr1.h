@@ -1,0 +1,178 @@
+/*
+ * dpr1.h -- C ABI of libdpr1.so: forward-stable eigendecomposition of
+ * diagonal-plus-rank-one (DPR1) matrices  A = D + rho * z * z^T  on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Jakovcevic Stor, Slapnicar, Barlow, "Forward stable eigenvalue
+ * decomposition of rank-one modifications of diagonal matrices", Algorithm 1.
+ * Every eigenpair is computed independently in O(n): shift to the nearest pole
+ * d_i (Alg. 1, shift test), form the arrowhead inverse of A - d_i I
+ * (eq. invAi) with its tip b (eq. b_ob) in double-double arithmetic, find the
+ * extreme eigenvalue nu of that inverse (eq. secAi), set mu = 1/nu,
+ * lambda = d_i + mu (eq. 8) and x = (D - d_i I - mu I)^{-1} z
+ * (eq. eigenvecAi), v = x/||x||_2.
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers unless the name ends in _host.
+ *    The caller owns every buffer.  The library allocates no device memory:
+ *    it uses the caller's workspace, whose size the *_workspace_size queries
+ *    return.  Workspace contents need not be initialised.
+ *  - All work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *    void*; NULL = the default stream).  No call synchronises the host, so the
+ *    launches may be captured into a hipGraph.  Only dpr1_batched_plan copies
+ *    from host memory.
+ *  - Inputs (Sec. 1 of the paper): n >= 1, d strictly decreasing, every
+ *    z_j != 0, rho != 0 and finite.  rho < 0 is reduced to rho > 0 as in
+ *    Sec. 1 by solving with (-d reversed, z reversed, -rho) and mapping back.
+ *    Sorting and deflation are the caller's job (reducible problems are
+ *    reported, not solved).
+ *  - Outputs: lambda[k] decreasing (strict interlacing, eq. interlace);
+ *    V column-major, column k (k = 0..n-1) = v_k at V + k*ldv, with the sign
+ *    of eq. (Aeigenvec): v_k has the direction of (D - lambda_k I)^{-1} z.
+ *  - Synchronous return codes: 0 success; -p argument p (1-based) invalid
+ *    (null pointer, n < 1, ldv < n, non-finite or zero rho, workspace too
+ *    small); DPR1_EHIP a HIP launch failed.
+ *  - Asynchronous per-problem device `info` (int32, set by the library on the
+ *    stream): 0 ok; DPR1_INFO_UNSORTED d not strictly decreasing;
+ *    DPR1_INFO_ZERO_Z some z_j == 0 (reducible, Sec. 1); DPR1_INFO_NONFINITE
+ *    a non-finite input; DPR1_INFO_BAD_RHO zero or non-finite rho (batched).
+ *    When info != 0 the outputs of that problem are unspecified.
+ */
+#ifndef DPR1_H
+#define DPR1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPR1_OK 0
+#define DPR1_EHIP (-1000)
+
+#define DPR1_INFO_OK 0
+#define DPR1_INFO_UNSORTED 1
+#define DPR1_INFO_ZERO_Z 2
+#define DPR1_INFO_NONFINITE 3
+#define DPR1_INFO_BAD_RHO 4
+
+/* Counters written to the optional device `stats` array (int32, length
+ * DPR1_NSTATS; the library zeroes it before counting).                      */
+#define DPR1_STAT_KB_GT_100 0 /* eigenvalues with K_b > 100 (eq. knu2): the
+                                 paper's test for double-precision b        */
+#define DPR1_STAT_POLISHED 1  /* roots polished by double-double Newton     */
+#define DPR1_STAT_NEARZERO 2  /* lambda recomputed from A^{-1} (eq. gamma)  */
+#define DPR1_STAT_SINGULAR 3  /* f(0) rounded to 0: lambda set to 0         */
+#define DPR1_STAT_ITERS_MAX 4 /* most root-finder passes for one eigenvalue */
+#define DPR1_STAT_ITERS_SUM 5 /* root-finder passes summed over eigenvalues */
+#define DPR1_NSTATS 8
+
+/* Options.  dpr1_default_opts fills the defaults noted below.               */
+typedef struct dpr1_opts {
+  int32_t mode_b;      /* tip b of A_i^{-1}: 0 double-double always (default);
+                          1 double-double only when K_b > 100 (the paper's
+                          gate); 2 never (the paper's dpr1eig_nd)            */
+  int32_t root;        /* 0 bisection (Alg. 1); 1 safeguarded rational
+                          secular solver (Sec. 2.2; default)                */
+  int32_t polish;      /* 1 (default): double-double Newton polish of roots
+                          whose rounding amplification is large; 0 off     */
+  int32_t split;       /* waves that share one block of 64 eigenvalues by
+                          splitting the inner sum; 0 = chosen from n        */
+  double kappa_polish; /* polish threshold on kappa_g*max(1,|mu/lambda|);
+                          default 16                                        */
+  double nearzero;     /* near-zero rule factor: recompute lambda from
+                          A^{-1} when factor*|lambda| < distance to the
+                          neighbouring poles; default 10, 0 disables        */
+  void* events;        /* profiling hook, NULL (default) = off: a host array
+                          of 4 hipEvent_t that the solve records on `stream`
+                          right before and after the eigenvalue kernel
+                          ([0], [1]) and the eigenvector kernel ([2], [3]) */
+} dpr1_opts;
+
+void dpr1_default_opts(dpr1_opts* opts);
+
+/* Bytes of device workspace dpr1_eig needs for a problem of order n.       */
+size_t dpr1_workspace_size(int64_t n);
+
+/* All eigenpairs of one DPR1 matrix (Alg. 1 for k = 1..n).
+ *   d, z          [n]  input (device, float64)
+ *   rho           scalar (host)
+ *   lambda        [n]  output eigenvalues, decreasing
+ *   V             [ldv*n] output eigenvectors (column-major) or NULL for
+ *                 eigenvalues only
+ *   ldv           leading dimension of V (>= n; ignored when V == NULL)
+ *   shift_idx     [n] optional output: index i of the pole d_i used as shift
+ *   mu            [n] optional output: mu_k = lambda_k - d_{i_k}; the pair
+ *                 (d_i, mu) represents lambda to about twice the working
+ *                 precision (Example 2)
+ *   xnorm         [n] optional output: ||x_k||_2 of eq. (eigenvecAi)
+ *   info          [1] device int32 (see above)
+ *   stats         [DPR1_NSTATS] optional device int32 counters
+ *   opts          NULL = defaults
+ *   work, work_bytes  device workspace (>= dpr1_workspace_size(n))          */
+int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* lambda,
+             double* V, int64_t ldv, int32_t* shift_idx, double* mu, double* xnorm,
+             int32_t* info, int32_t* stats, const dpr1_opts* opts, void* work,
+             size_t work_bytes, void* stream);
+
+/* Batched: nprob independent problems of sizes n_p packed back to back
+ * (problem p occupies [offs[p], offs[p+1]) of d, z, lambda, shift_idx, mu,
+ * xnorm; its V block starts at voffs[p] with leading dimension n_p).  As in
+ * divide-and-conquer merges the sizes are ragged; all problems are solved by
+ * one persistent launch whose blocks take (problem, 64 eigenvalues) items
+ * from a device work queue, larger problems first.
+ *
+ * dpr1_batched_workspace_size(nprob, ntotal): bytes for a batch whose sizes
+ *   sum to ntotal.
+ * dpr1_batched_plan: reads the host offsets (offs_host[0] = 0, sizes >= 1),
+ *   builds the work queue and the launch shape, copies the queue into the
+ *   workspace and synchronises `stream` (the only host->device copy and the
+ *   only synchronisation of the batched path).  The plan struct (host memory,
+ *   caller-owned) is then passed to every solve of that batch shape; the
+ *   solve can be repeated or captured in a hipGraph with the same workspace.
+ * dpr1_eig_batched: the solve, kernel launches only.  offs [nprob+1] and
+ *   voffs [nprob] are device arrays (the same offsets as planned; voffs may be
+ *   NULL when V is NULL); rho is a device array [nprob]; info is [nprob].   */
+typedef struct dpr1_plan {
+  int64_t nprob, ntotal, nitems, nmax;
+  int32_t split, grid;
+  dpr1_opts opts;
+} dpr1_plan;
+
+size_t dpr1_batched_workspace_size(int64_t nprob, int64_t ntotal);
+int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* opts,
+                      dpr1_plan* plan, void* work, size_t work_bytes, void* stream);
+int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d,
+                     const double* z, const double* rho, double* lambda, double* V,
+                     const int64_t* voffs, int32_t* shift_idx, double* mu, double* xnorm,
+                     int32_t* info, int32_t* stats, void* work, size_t work_bytes,
+                     void* stream);
+
+/* Reverse mode (not in the paper; standard eigenvalue perturbation theory).
+ * For L(Lambda, V) with lambda_bar = dL/dlambda, V_bar = dL/dV:
+ *   Abar = V X V^T,  X = diag(lambda_bar) + F o (V^T V_bar),
+ *   F_lk = 1/(lambda_k - lambda_l) (l != k) with the gaps taken from the
+ *   shifted representation (d_{i_k} + mu_k) - (d_{i_l} + mu_l);
+ *   d_bar_j = Abar_jj, rho_bar = z^T Abar z, z_bar = rho (Abar + Abar^T) z,
+ * evaluated as d_bar_j = sum_k (V X)_jk V_jk, y_k = v_k^T z = -1/(rho ||x_k||),
+ * rho_bar = y^T X y, z_bar = rho V (X + X^T) y.  The two n^3 products use
+ * FP64 matrix cores.  Problems of one batch have equal size n and are stored
+ * with strides n (vectors) and n*n (matrices, column-major, ld = n).
+ *   shift_idx, mu, xnorm: as returned by the forward call.
+ *   lambda_bar, V_bar: either may be NULL (treated as zero).
+ *   d_bar, z_bar [nbatch*n], rho_bar [nbatch]: outputs.                    */
+size_t dpr1_backward_workspace_size(int64_t n, int64_t nbatch);
+int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const double* z,
+                              const double* rho, const int32_t* shift_idx, const double* mu,
+                              const double* xnorm, const double* V, const double* lambda_bar,
+                              const double* V_bar, double* d_bar, double* z_bar,
+                              double* rho_bar, void* work, size_t work_bytes, void* stream);
+
+/* Text for a return code or an info code.                                   */
+const char* dpr1_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPR1_H */

@@ -358,7 +358,7 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
     double cur = nu;
     if (!(cur >= lo && cur <= hi)) cur = nu0;
     int pit = 0;
-    for (; pit < 8; ++pit) {
+    for (; pit < 100; ++pit) {
       quad gq, gpq;
       g_quad(d, z, &A, cur, &gq, &gpq);
       if (gq == 0) break;

@@ -1,0 +1,1075 @@
+// Forward-stable DPR1 eigensolver: gfx950 kernels and the C ABI.
+//
+// Paper: Jakovcevic Stor, Slapnicar, Barlow, "Forward stable eigenvalue
+// decomposition of rank-one modifications of diagonal matrices" (Alg. 1).
+//
+// Kernels (all FP64; double-double where the paper asks for double the
+// working precision):
+//   k_prep  -- per problem: checks of Sec. 1, the rho < 0 reduction, staging
+//              of (d_j, zeta_j^2) pairs and the low parts of zeta_j^2.
+//   k_eig   -- one lane per eigenvalue, 64 eigenvalues per block; W waves of
+//              a block split the inner index j.  All lanes of a wave read the
+//              same (d_j, zeta_j^2) at the same time, so the data arrive
+//              through scalar loads and feed the FP64 VALU as SGPR operands.
+//              Per eigenvalue: shift test, tip b in double-double, extreme
+//              root of the arrowhead secular function, compensated Newton
+//              step, near-zero test, ||x||.
+//   k_fix   -- one wave per flagged eigenpair: double-double Newton polish
+//              and the near-zero recomputation of eq. (gamma).
+//   k_out   -- user outputs in the caller's index order.
+//   k_vec   -- V, one block per column, coalesced non-temporal stores.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/dpr1.h"
+#include "dd.h"
+
+namespace dpr1 {
+
+constexpr int WAVE = 64;
+constexpr int MAXW = 16;
+constexpr double GROW = 1.0 + 0x1p-40;
+
+typedef const __attribute__((address_space(4))) double cdouble;
+
+// Wave-uniform load through the scalar data cache (idx must be uniform).
+__device__ __forceinline__ double ldu(const double* base, int64_t idx) {
+  return ((cdouble*)base)[idx];
+}
+
+struct Meta {
+  int64_t off;   // first element of the problem in the packed arrays
+  int32_t n;
+  int32_t neg;   // rho < 0: solved as (-d reversed, z reversed, -rho)
+  int32_t info;
+  int32_t pad;
+  double rho;    // |rho|
+  double zz;     // sum zeta_j^2
+};
+
+enum : int32_t { FIX_POLISH = 1, FIX_NEARZERO = 2 };
+
+struct FixItem {
+  int32_t p, k, i, flags;
+  double nu0, nu1, bhi, blo, lo, hi;
+};
+
+struct KArgs {
+  const Meta* meta;
+  const double* pairs;  // [2N]: (d'_j, zeta'_j^2)
+  const double* z2lo;   // [N]  low part of zeta'_j^2
+  const double* sd;     // [N]  d'
+  const double* sz;     // [N]  zeta'
+  int32_t* ii;          // [N]  shift index (within the problem)
+  double* mu;           // [N]
+  double* xs;           // [N]  |mu| * ||x||_2
+  double* lam;          // [N]
+  FixItem* fix;         // [N]
+  int32_t* ctr;         // [0] fix count, [1] queue head
+  int32_t* stats;       // nullable
+  const int2* items;    // batched queue (p, k0) or nullptr
+  int32_t nitems;
+  int32_t W;
+  int32_t mode_b, root, polish, want_v;
+  double kappa_polish, nearzero;
+};
+
+// ------------------------------------------------------------ bit helpers
+__device__ __forceinline__ uint64_t bits(double x) { return (uint64_t)__double_as_longlong(x); }
+__device__ __forceinline__ double unbits(uint64_t u) { return __longlong_as_double((long long)u); }
+
+// midpoint in the order of binary64 numbers, 0 < lo < hi
+__device__ __forceinline__ double fmid(double lo, double hi) {
+  uint64_t a = bits(lo), b = bits(hi);
+  return unbits(a + (b - a) / 2);
+}
+__device__ __forceinline__ bool adjacent(double lo, double hi) { return bits(hi) - bits(lo) <= 1; }
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); }
+__device__ __forceinline__ int lane_id() { return threadIdx.x % WAVE; }
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
+
+// ------------------------------------------------- cross-wave reductions
+// Every wave of the block ends with the same sums, added in the same order,
+// so all waves keep identical per-lane state.
+template <int NV>
+__device__ __forceinline__ void wg_sum(double (&v)[NV], int W, int wv, int lane, double* red) {
+  if (W == 1) return;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) red[(q * W + wv) * WAVE + lane] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = red[(q * W) * WAVE + lane];
+    for (int w = 1; w < W; ++w) s += red[(q * W + w) * WAVE + lane];
+    v[q] = s;
+  }
+  __syncthreads();
+}
+
+// (s, c) Neumaier partials -> combined with TwoSum in wave order.
+__device__ __forceinline__ void wg_sum_comp(double& s, double& c, int W, int wv, int lane, double* red) {
+  if (W == 1) return;
+  red[(0 * W + wv) * WAVE + lane] = s;
+  red[(1 * W + wv) * WAVE + lane] = c;
+  __syncthreads();
+  double S = red[lane], C = red[W * WAVE + lane];
+  for (int w = 1; w < W; ++w) {
+    dd t = two_sum(S, red[w * WAVE + lane]);
+    S = t.hi;
+    C += red[(W + w) * WAVE + lane] + t.lo;
+  }
+  s = S;
+  c = C;
+  __syncthreads();
+}
+
+// same-signed double-double partials
+__device__ __forceinline__ void wg_sum_dd(dd& a, int W, int wv, int lane, double* red) {
+  if (W == 1) return;
+  red[(0 * W + wv) * WAVE + lane] = a.hi;
+  red[(1 * W + wv) * WAVE + lane] = a.lo;
+  __syncthreads();
+  dd s = {red[lane], red[W * WAVE + lane]};
+  for (int w = 1; w < W; ++w) s = dd_add_same(s, dd{red[w * WAVE + lane], red[(W + w) * WAVE + lane]});
+  a = s;
+  __syncthreads();
+}
+
+// Walk the wave's slice [j0, j1) of the inner index in three segments:
+// below the window of shift indices this wave can own (seg 0: every lane has
+// j < i), inside it (seg 1: per-lane test), above it (seg 2: every lane has
+// j > i).  j is wave-uniform in all three loops.
+template <class F>
+__device__ __forceinline__ void sweep(int j0, int j1, int wlo, int whi, F&& f) {
+  int a = j0, b = min(j1, wlo);
+#pragma unroll 4
+  for (int j = a; j < b; ++j) f(j, 0);
+  a = max(j0, wlo);
+  b = min(j1, whi);
+  for (int j = a; j < b; ++j) f(j, 1);
+  a = max(j0, whi);
+#pragma unroll 4
+  for (int j = a; j < j1; ++j) f(j, 2);
+}
+
+// ------------------------------------------------------------------ prep
+__global__ void __launch_bounds__(256) k_prep(int nprob, const int64_t* __restrict__ offs, int64_t n_single,
+                                              const double* __restrict__ d, const double* __restrict__ z,
+                                              const double* __restrict__ rho_dev, double rho_host,
+                                              Meta* __restrict__ meta, double* __restrict__ sd,
+                                              double* __restrict__ sz, double* __restrict__ pairs,
+                                              double* __restrict__ z2lo, int32_t* __restrict__ info) {
+  int p = blockIdx.x;
+  if (p >= nprob) return;
+  int64_t off = offs ? offs[p] : 0;
+  int64_t n = offs ? offs[p + 1] - offs[p] : n_single;
+  double rho = rho_dev ? rho_dev[p] : rho_host;
+  int neg = rho < 0;
+  __shared__ double red[256];
+  __shared__ int flags;
+  if (threadIdx.x == 0) flags = 0;
+  __syncthreads();
+  int f = 0;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    int64_t src = neg ? n - 1 - j : j;
+    double dj = d[off + src], zj = z[off + src];
+    if (!isfinite(dj) || !isfinite(zj)) f |= 4;
+    if (zj == 0.0) f |= 2;
+    if (j + 1 < n) {
+      double dn = d[off + src + (neg ? -1 : 1)];
+      // staged order must be strictly decreasing: d_j > d_{j+1} (or -d reversed)
+      if (!(neg ? (-dj > -dn) : (dj > dn))) f |= 1;
+    }
+    double ds = neg ? -dj : dj;
+    double z2 = zj * zj;
+    sd[off + j] = ds;
+    sz[off + j] = zj;
+    pairs[2 * (off + j)] = ds;
+    pairs[2 * (off + j) + 1] = z2;
+    z2lo[off + j] = __builtin_fma(zj, zj, -z2);
+    acc += z2;
+  }
+  if (f) atomicOr(&flags, f);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int code = 0;
+    if (!isfinite(rho) || rho == 0.0) code = DPR1_INFO_BAD_RHO;
+    else if (flags & 4) code = DPR1_INFO_NONFINITE;
+    else if (flags & 1) code = DPR1_INFO_UNSORTED;
+    else if (flags & 2) code = DPR1_INFO_ZERO_Z;
+    Meta m;
+    m.off = off;
+    m.n = (int32_t)n;
+    m.neg = neg;
+    m.info = code;
+    m.pad = 0;
+    m.rho = fabs(rho);
+    m.zz = red[0];
+    meta[p] = m;
+    if (info) info[p] = code;
+  }
+}
+
+__global__ void k_zero(int32_t* __restrict__ a, int n) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) a[t] = 0;
+}
+
+// ------------------------------------------------------------------- eig
+// One block of 64 eigenvalues (k0 .. k0+63) of problem p, W waves.
+__device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
+  const int W = A.W;
+  const int wv = wave_id();
+  const int lane = lane_id();
+  const Meta M = A.meta[p];
+  if (M.info != 0) return;
+  const int n = M.n;
+  const int64_t off = M.off;
+  const double* P = A.pairs + 2 * off;
+  const double* Zl = A.z2lo + off;
+  const double* Dv = A.sd + off;
+  const double* Zv = A.sz + off;
+  const double rho = M.rho;
+  const int k = k0 + lane;
+  const bool valid = k < n;
+  const int kk = valid ? k : n - 1;
+
+  // wave slice of the inner index and the window of possible shift indices
+  const int chunk = (n + W - 1) / W;
+  const int j0 = min(n, wv * chunk);
+  const int j1 = min(n, j0 + chunk);
+  const int wlo = max(0, k0 - 1);
+  const int whi = min(n, k0 + WAVE);
+
+  if (n == 1) {
+    // 1x1: lambda = d_1 + rho zeta_1^2, x = zeta_1/(d_1 - lambda)
+    if (wv == 0 && lane == 0) {
+      double z0 = Zv[0];
+      double m = rho * (z0 * z0);
+      A.ii[off] = 0;
+      A.mu[off] = m;
+      A.xs[off] = fabs(z0);
+      A.lam[off] = Dv[0] + m;
+    }
+    return;
+  }
+
+  const double dk = Dv[kk];
+  const double dkm1 = kk > 0 ? Dv[kk - 1] : 0.0;
+
+  // ---- shift (Alg. 1): F = 1 + rho sum zeta_j^2/((d_j - d_k) - tau)
+  const double tau = (dkm1 - dk) / 2;
+  double Fs[1] = {0.0};
+  sweep(j0, j1, wlo, whi, [&](int j, int) {
+    double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+    Fs[0] += z2 / ((dj - dk) - tau);
+  });
+  wg_sum<1>(Fs, W, wv, lane, red);
+  const double F = 1.0 + rho * Fs[0];
+  const bool right = (kk == 0) || (F > 0);
+  const int i = right ? kk : kk - 1;
+  const double s = right ? 1.0 : -1.0;
+  const double sigma = right ? dk : dkm1;
+  const double zi = Zv[i];
+  const double zi2 = zi * zi;
+
+  // ---- tip b of A_i^{-1} (eq. b_ob) in double-double, plus the binary64 sums
+  // of eq. (knu2).  P collects j < i (delta > 0), N collects j > i.
+  dd Pd = {0.0, 0.0}, Nd = {0.0, 0.0};
+  sweep(j0, j1, wlo, whi, [&](int j, int seg) {
+    double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1), z2l = ldu(Zl, j);
+    dd dl = two_sum(dj, -sigma);  // exact d_j - sigma
+    dd q = dd_div(dd{z2, z2l}, dl);
+    if (seg == 0) {
+      Pd = dd_add_same(Pd, q);
+    } else if (seg == 2) {
+      Nd = dd_add_same(Nd, q);
+    } else {
+      dd pn = dd_add_same(Pd, q), nn = dd_add_same(Nd, q);
+      if (j < i) Pd = pn;
+      if (j > i) Nd = nn;
+    }
+  });
+  wg_sum_dd(Pd, W, wv, lane, red);
+  wg_sum_dd(Nd, W, wv, lane, red);
+  const dd rr = dd_div(dd{1.0, 0.0}, dd{rho, 0.0});
+  const dd num = dd_add(dd_add_same(rr, Pd), Nd);
+  const dd bdd = dd_div(num, two_prod(zi, zi));
+  const double Pr = rho * Pd.hi, Nr = rho * Nd.hi;
+  const double Kb64 = (1.0 + Pr - Nr) / fabs(1.0 + Pr + Nr);
+  bool use_ext = A.mode_b == 0 || (A.mode_b == 1 && Kb64 > 100.0);
+  const double rzi = 1.0 / zi;
+  const double b64 = ((1.0 / rho + Pd.hi) + Nd.hi) * (rzi * rzi);
+  const double bh = use_ext ? bdd.hi : b64;
+  const double bl = use_ext ? bdd.lo : 0.0;
+  const double bp = s * bh;  // b' of the mirrored (rightmost) problem
+
+  // ---- extreme root nu' > 0 of g(nu') = b' - nu' + S(nu')/zeta_i^2,
+  // S(nu') = sum_{j!=i} zeta_j^2/(delta'_j (nu' delta'_j - 1)), delta' = s (d_j - sigma).
+  const double nss = -s * sigma;
+  const bool interior = kk > 0;
+  const double xm = interior ? 1.0 / (dkm1 - dk) : 0.0;  // pole nearest to the root (model pole)
+  double L, U, nu;
+  if (interior) {
+    L = xm;
+    U = INFINITY;
+    nu = 2.0 * xm;  // mu at the midpoint of the gap: the nearest-pole bound
+  } else {
+    L = (1.0 / (rho * M.zz)) / GROW;  // lambda_1 <= d_1 + rho ||z||^2
+    U = (1.0 / (rho * zi2)) * GROW;   // lambda_1 >= d_1 + rho zeta_1^2
+    nu = A.root ? U : fmid(L, U);
+  }
+  // rigorous bracket, kept for the double-double polish (the signs of g seen
+  // by the binary64 iteration can be wrong when g is badly conditioned)
+  const double L0 = L, U0 = U;
+  bool done = !valid;
+  int iters = 0;
+  double nu0 = nu, prevstep = INFINITY;
+  const double rz2 = 1.0 / zi2;
+
+  if (A.root == 0) {
+    // -------- bisection in the order of the binary64 numbers
+    bool first = true;
+    while (wave_any(!done)) {
+      double m = nu;
+      double S[1] = {0.0};
+      sweep(j0, j1, wlo, whi, [&](int j, int seg) {
+        double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+        double dl = __builtin_fma(s, dj, nss);
+        double pp = __builtin_fma(m, dl, -1.0);
+        double t = z2 / (dl * pp);
+        if (seg == 1 && j == i) t = 0.0;
+        S[0] += t;
+      });
+      wg_sum<1>(S, W, wv, lane, red);
+      if (!done) {
+        double Sz = S[0] * rz2;
+        double g = (bp - m) + Sz;
+        if (first && interior) {
+          if (g > 0) {
+            L = m;
+            U = (bp + Sz) * GROW;
+            if (!(U > L)) U = L * (1.0 + 0x1p-30);
+          } else {
+            U = m;
+          }
+        } else {
+          if (g > 0) L = m; else U = m;
+        }
+        ++iters;
+        if (adjacent(L, U) || iters >= 200) {
+          done = true;
+          nu0 = U;
+        } else {
+          nu = fmid(L, U);
+        }
+      }
+      first = false;
+    }
+  } else {
+    // -------- safeguarded rational iteration: at nu the sum term of g is
+    // modelled by A/(t - xm) + B (value and slope matched), whose root with
+    // the linear part b' - t is the next iterate.  Since all poles of S lie
+    // left of the model pole, the model lies above S, so the iterates come
+    // down monotonically onto the root after the first step.
+    bool first = true;
+    while (wave_any(!done)) {
+      double m = nu;
+      double S[2] = {0.0, 0.0};
+      sweep(j0, j1, wlo, whi, [&](int j, int seg) {
+        double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+        double dl = __builtin_fma(s, dj, nss);
+        double pp = __builtin_fma(m, dl, -1.0);
+        double rq = 1.0 / (dl * pp);
+        double t = z2 * rq;
+        double tp = (t * dl) * (dl * rq);  // zeta_j^2/pp^2
+        if (seg == 1 && j == i) {
+          t = 0.0;
+          tp = 0.0;
+        }
+        S[0] += t;
+        S[1] += tp;
+      });
+      wg_sum<2>(S, W, wv, lane, red);
+      if (!done) {
+        double Sz = S[0] * rz2;
+        double Spz = S[1] * rz2;  // -dS/dnu / zeta_i^2
+        double g = (bp - m) + Sz;
+        if (first && interior) {
+          if (g > 0) {
+            L = m;
+            U = (bp + Sz) * GROW;
+            if (!(U > L)) U = L * (1.0 + 0x1p-30);
+          } else {
+            U = m;
+          }
+        } else {
+          if (g > 0) L = m; else U = m;
+        }
+        ++iters;
+        if (g == 0.0) {
+          done = true;
+          nu0 = m;
+        } else {
+          double x = m - xm;
+          double Am = Spz * x * x;
+          double Bm = Sz - Spz * x;
+          double C = (bp + Bm) - xm;
+          double disc = sqrt(C * C + 4.0 * Am);
+          double u = C >= 0 ? (C + disc) * 0.5 : (2.0 * Am) / (disc - C);
+          double nn = xm + u;
+          double step = fabs(nn - m);
+          if (step <= 0x1p-40 * m) {
+            done = true;  // converged: the model root sits on the last point
+            nu0 = (nn >= L && nn <= U) ? nn : m;
+          } else if (!(nn > L && nn < U)) {
+            if (adjacent(L, U)) {
+              done = true;
+              nu0 = U;
+            } else {
+              nn = fmid(L, U);  // safeguard: bisect in the order of the numbers
+            }
+          } else if (iters >= 8 && step > 0.5 * prevstep) {
+            done = true;  // rounding noise dominates g: leave it to the checks below
+            nu0 = nn;
+          }
+          if (!done) {
+            if (iters >= 40) {
+              done = true;
+              nu0 = nn;
+            }
+            prevstep = fabs(nn - m);
+            nu = nn;
+          }
+        }
+      }
+      first = false;
+    }
+  }
+
+  // ---- one Newton step with a compensated sum, and the amplification
+  // estimate kappa_g = (|b| + |nu| + S)/(|nu| |g'|).
+  double cs = 0.0, cc = 0.0;
+  double Sp[1] = {0.0};
+  {
+    const double m = nu0;
+    sweep(j0, j1, wlo, whi, [&](int j, int seg) {
+      double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+      double dl = __builtin_fma(s, dj, nss);
+      double pp = __builtin_fma(m, dl, -1.0);
+      double q = dl * pp;
+      double t = z2 / q;
+      double tp = (t * dl) * (dl / q);
+      if (seg == 1 && j == i) {
+        t = 0.0;
+        tp = 0.0;
+      }
+      double y = cs + t;
+      cc += (fabs(cs) >= fabs(t)) ? ((cs - y) + t) : ((t - y) + cs);
+      cs = y;
+      Sp[0] += tp;
+    });
+    wg_sum_comp(cs, cc, W, wv, lane, red);
+    wg_sum<1>(Sp, W, wv, lane, red);
+  }
+  const double Sz = (cs + cc) / zi2;
+  const double g = (bp - nu0) + Sz;
+  const double gp = -1.0 - Sp[0] / zi2;
+  const double nu1 = nu0 - g / gp;
+  const double kap = (fabs(bp) + nu0 + Sz) / (nu0 * fabs(gp));
+  double muv = s / nu1;
+  double lam = sigma + muv;
+  double amp = fabs(muv / lam);
+  if (!(amp > 1.0)) amp = 1.0;
+  const bool pol = valid && A.polish && (kap * amp > A.kappa_polish);
+  bool nz = false;
+  if (valid && !pol && A.nearzero > 0) {
+    double gap = fabs(lam - dk);
+    if (kk > 0) gap = fmin(gap, fabs(lam - dkm1));
+    nz = A.nearzero * fabs(lam) < gap;
+  }
+
+  // ---- ||x|| scaled by |mu|: sum zeta_j^2 (mu/(delta_j - mu))^2 (j = i gives zeta_i^2)
+  double Nx[1] = {0.0};
+  if (A.want_v) {
+    sweep(j0, j1, wlo, whi, [&](int j, int) {
+      double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+      double r = muv / ((dj - sigma) - muv);
+      Nx[0] = __builtin_fma(z2 * r, r, Nx[0]);
+    });
+    wg_sum<1>(Nx, W, wv, lane, red);
+  }
+
+  if (wv == 0 && valid) {
+    A.ii[off + k] = i;
+    A.mu[off + k] = muv;
+    A.xs[off + k] = sqrt(Nx[0]);
+    A.lam[off + k] = lam;
+    if (pol || nz) {
+      int e = atomicAdd(&A.ctr[0], 1);
+      FixItem it;
+      it.p = p;
+      it.k = k;
+      it.i = i;
+      it.flags = (pol ? FIX_POLISH : 0) | (nz ? FIX_NEARZERO : 0);
+      it.nu0 = nu0;
+      it.nu1 = nu1;
+      it.bhi = bp;
+      it.blo = s * bl;
+      it.lo = L0;
+      it.hi = U0;
+      A.fix[e] = it;
+    }
+  }
+  if (A.stats && wv == 0) {
+    bool kb = valid && Kb64 > 100.0;
+    unsigned long long bal = __ballot(kb);
+    int itv = valid ? iters : 0;
+    int imax = itv, isum = itv;
+    for (int o = 32; o > 0; o >>= 1) {
+      imax = max(imax, __shfl_xor(imax, o));
+      isum += __shfl_xor(isum, o);
+    }
+    if (lane == 0) {
+      if (bal) atomicAdd(&A.stats[DPR1_STAT_KB_GT_100], __popcll(bal));
+      atomicMax(&A.stats[DPR1_STAT_ITERS_MAX], imax);
+      atomicAdd(&A.stats[DPR1_STAT_ITERS_SUM], isum);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_eig(KArgs A) {
+  extern __shared__ double red[];
+  if (A.items == nullptr) {
+    eig_block(A, 0, blockIdx.x * WAVE, red);
+    return;
+  }
+  // persistent: take (problem, first eigenvalue) items from the queue
+  __shared__ int item;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(&A.ctr[1], 1);
+    __syncthreads();
+    int it = item;
+    __syncthreads();
+    if (it >= A.nitems) break;
+    int2 pk = A.items[it];
+    eig_block(A, pk.x, pk.y, red);
+  }
+}
+
+// ------------------------------------------------------------------- fix
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ dd wave_sum_same(dd a) {
+  for (int o = 32; o > 0; o >>= 1) {
+    dd b = {__shfl_xor(a.hi, o), __shfl_xor(a.lo, o)};
+    a = dd_add_same(a, b);
+  }
+  return a;
+}
+__device__ __forceinline__ dd wave_sum_dd(dd a) {
+  for (int o = 32; o > 0; o >>= 1) {
+    dd b = {__shfl_xor(a.hi, o), __shfl_xor(a.lo, o)};
+    a = dd_add(a, b);
+  }
+  return a;
+}
+// Neumaier partials of the lanes, combined in a fixed butterfly order
+__device__ __forceinline__ double wave_sum_comp(double s, double c) {
+  for (int o = 32; o > 0; o >>= 1) {
+    double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
+    dd t = two_sum(s, s2);
+    s = t.hi;
+    c = c + c2 + t.lo;
+  }
+  return s + c;
+}
+
+__global__ void __launch_bounds__(64) k_fix(KArgs A) {
+  const int lane = threadIdx.x;
+  const int cnt = A.ctr[0];
+  for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+    const FixItem it = A.fix[e];
+    const Meta M = A.meta[it.p];
+    const int n = M.n;
+    const int64_t off = M.off;
+    const double* Dv = A.sd + off;
+    const double* Zv = A.sz + off;
+    const double* Z2 = A.pairs + 2 * off;
+    const double* Zl = A.z2lo + off;
+    const double rho = M.rho;
+    const int k = it.k, i = it.i;
+    const double s = (i == k) ? 1.0 : -1.0;
+    const double sigma = Dv[i];
+    const double zi = Zv[i];
+    const double zi2 = zi * zi;
+    const dd zi2d = two_prod(zi, zi);
+    double muv = A.mu[off + k];
+    double lam = A.lam[off + k];
+    bool nz = (it.flags & FIX_NEARZERO) != 0;
+    bool polished = false;
+    int singular = 0;
+
+    if (it.flags & FIX_POLISH) {
+      // Safeguarded iteration with g evaluated in double-double: far from the
+      // root the rational model step of the main solver, close to it Newton
+      // (g exact to ~2^-100, so the last step lands on the rounded root).
+      const dd bdd = {it.bhi, it.blo};
+      const double xm = (k > 0) ? 1.0 / (Dv[k - 1] - Dv[k]) : 0.0;
+      double lo = it.lo, hi = it.hi;
+      double cur = it.nu1;
+      if (!(cur > lo && cur < hi)) cur = it.nu0;
+      if (!(cur > lo && cur < hi)) cur = fmid(lo, hi);
+      for (int pit = 0; pit < 48; ++pit) {
+        dd acc = {0.0, 0.0};
+        double sp = 0.0;
+        for (int j = lane; j < n; j += WAVE) {
+          if (j == i) continue;
+          double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
+          dd dl = two_sum(s * dj, -s * sigma);                   // delta'_j exactly
+          dd pp = dd_add(dd_mul_d(dl, cur), dd{-1.0, 0.0});       // nu delta' - 1
+          dd q = dd_mul(dl, pp);
+          dd t = dd_div(dd{z2, Zl[j]}, q);
+          acc = dd_add_same(acc, t);
+          sp += z2 / (pp.hi * pp.hi);
+        }
+        acc = wave_sum_same(acc);
+        sp = wave_sum(sp);
+        dd Sdd = dd_div(acc, zi2d);
+        dd gd = dd_add(dd_add(bdd, dd{-cur, 0.0}), Sdd);
+        double Spz = sp / zi2;
+        double gpv = -1.0 - Spz;
+        if (gd.hi == 0.0) break;
+        if (gd.hi > 0) lo = cur; else hi = cur;
+        double newton = -(gd.hi + gd.lo) / gpv;
+        double t;
+        if (fabs(newton) <= 0x1p-30 * cur) {
+          t = cur + newton;
+        } else {
+          double x = cur - xm;
+          double Am = Spz * x * x;
+          double C = (bdd.hi + (Sdd.hi - Spz * x)) - xm;
+          double disc = sqrt(C * C + 4.0 * Am);
+          double u = C >= 0 ? (C + disc) * 0.5 : (2.0 * Am) / (disc - C);
+          t = xm + u;
+        }
+        // stay inside the sign bracket and off the pole / rigorous lower end
+        if (!(t >= lo && t <= hi) || !(t > it.lo) || !(t < INFINITY)) t = fmid(lo, hi);
+        if (t == cur) break;
+        cur = t;
+      }
+      muv = s / cur;
+      lam = sigma + muv;
+      polished = true;
+      if (A.nearzero > 0) {
+        double gap = fabs(lam - Dv[k]);
+        if (k > 0) gap = fmin(gap, fabs(lam - Dv[k - 1]));
+        nz = A.nearzero * fabs(lam) < gap;
+      }
+    }
+
+    if (nz) {
+      // eq. (gamma): f(0) = 1 + rho z^T D^{-1} z in double-double
+      dd f0 = {0.0, 0.0};
+      double uu = 0.0, dmin = INFINITY;
+      for (int j = lane; j < n; j += WAVE) {
+        double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
+        dd t = dd_div(dd{z2, Zl[j]}, dd{dj, 0.0});
+        f0 = dd_add(f0, t);
+        double u = Zv[j] / dj;
+        uu += u * u;
+        dmin = fmin(dmin, fabs(dj));
+      }
+      f0 = wave_sum_dd(f0);
+      uu = wave_sum(uu);
+      dmin = wave_min(dmin);
+      f0 = dd_add(dd{1.0, 0.0}, dd_mul_d(f0, rho));
+      double f0d = f0.hi + f0.lo;
+      if (f0d == 0.0) {
+        lam = 0.0;
+        singular = 1;
+      } else {
+        const double gam = -rho / f0d;
+        const double sh = (f0d < 0) ? 1.0 : -1.0;  // sign of lambda
+        const double gt = sh * gam;
+        // eta~ = sh/lambda > 0 on the right branch of
+        // h(eta~) = 1 + gt sum zeta_j^2/(d~_j (1 - eta~ d~_j)),  d~ = sh d
+        double lo;
+        if (sh > 0) lo = (k > 0) ? 1.0 / Dv[k - 1] : 4.9406564584124654e-324;
+        else lo = -1.0 / Dv[k];
+        double hi = (1.0 / dmin + fabs(gam) * uu) * GROW;
+        if (!(lo > 0)) lo = 4.9406564584124654e-324;
+        if (!(hi > lo)) hi = lo * 2.0;
+        for (int hit = 0; hit < 200 && !adjacent(lo, hi); ++hit) {
+          double m = fmid(lo, hi);
+          double acc = 0.0;
+          for (int j = lane; j < n; j += WAVE) {
+            double dt = sh * Z2[2 * j], z2 = Z2[2 * j + 1];
+            acc += z2 / (dt * __builtin_fma(-m, dt, 1.0));
+          }
+          acc = wave_sum(acc);
+          double hv = 1.0 + gt * acc;
+          if (hv < 0) lo = m; else hi = m;
+        }
+        const double e0 = hi;
+        double cs = 0.0, cc = 0.0, sp = 0.0;
+        for (int j = lane; j < n; j += WAVE) {
+          double dt = sh * Z2[2 * j], z2 = Z2[2 * j + 1];
+          double om = __builtin_fma(-e0, dt, 1.0);
+          double t = z2 / (dt * om);
+          double y = cs + t;
+          cc += (fabs(cs) >= fabs(t)) ? ((cs - y) + t) : ((t - y) + cs);
+          cs = y;
+          sp += z2 / (om * om);
+        }
+        double S = wave_sum_comp(cs, cc);
+        sp = wave_sum(sp);
+        double hv = 1.0 + gt * S;
+        double hp = gt * sp;
+        double e1 = e0 - hv / hp;
+        lam = sh / e1;
+      }
+    }
+
+    double xsv = 0.0;
+    if (polished && A.want_v) {
+      double acc = 0.0;
+      for (int j = lane; j < n; j += WAVE) {
+        double r = muv / ((Dv[j] - sigma) - muv);
+        double z2 = Z2[2 * j + 1];
+        acc = __builtin_fma(z2 * r, r, acc);
+      }
+      xsv = sqrt(wave_sum(acc));
+    }
+    if (lane == 0) {
+      A.lam[off + k] = lam;
+      if (polished) {
+        A.mu[off + k] = muv;
+        if (A.want_v) A.xs[off + k] = xsv;
+      }
+      if (A.stats) {
+        if (polished) atomicAdd(&A.stats[DPR1_STAT_POLISHED], 1);
+        if (nz) atomicAdd(&A.stats[DPR1_STAT_NEARZERO], 1);
+        if (singular) atomicAdd(&A.stats[DPR1_STAT_SINGULAR], 1);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------- out
+// user outputs in the caller's order (rho < 0 maps k -> n-1-k, lambda -> -lambda)
+__global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int nprob,
+                                             const int32_t* __restrict__ ii, const double* __restrict__ mu,
+                                             const double* __restrict__ xs, const double* __restrict__ lam,
+                                             double* __restrict__ lam_out, int32_t* __restrict__ idx_out,
+                                             double* __restrict__ mu_out, double* __restrict__ xn_out) {
+  int p = blockIdx.y;
+  if (p >= nprob) return;
+  const Meta M = meta[p];
+  const int n = M.n;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    int ko = M.neg ? n - 1 - k : k;
+    int64_t a = M.off + k, b = M.off + ko;
+    double sg = M.neg ? -1.0 : 1.0;
+    lam_out[b] = sg * lam[a];
+    if (idx_out) idx_out[b] = M.neg ? n - 1 - ii[a] : ii[a];
+    if (mu_out) mu_out[b] = sg * mu[a];
+    if (xn_out) xn_out[b] = xs[a] / fabs(mu[a]);
+  }
+}
+
+// ------------------------------------------------------------------- vec
+// v_j = zeta_j r_j / (|mu| ||x||), r_j = mu/(delta_j - mu): one block per
+// column, consecutive threads on consecutive rows.
+__global__ void __launch_bounds__(256) k_vec(const Meta* __restrict__ meta, int nprob, int64_t ncols,
+                                             const double* __restrict__ sd, const double* __restrict__ sz,
+                                             const int32_t* __restrict__ ii, const double* __restrict__ mu,
+                                             const double* __restrict__ xs, double* __restrict__ V,
+                                             const int64_t* __restrict__ voffs, int64_t ldv) {
+  for (int64_t c = blockIdx.x; c < ncols; c += gridDim.x) {
+    int p = 0;
+    if (nprob > 1) {
+      int lo = 0, hi = nprob - 1;  // last problem with off <= c
+      while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (meta[mid].off <= c) lo = mid; else hi = mid - 1;
+      }
+      p = lo;
+    }
+    const Meta M = meta[p];
+    if (M.info != 0) continue;
+    const int n = M.n;
+    const int k = (int)(c - M.off);
+    const double sigma = sd[M.off + ii[c]];
+    const double m = mu[c];
+    const double inv = 1.0 / copysign(xs[c], m);  // v = x/||x|| = zeta r/(sign(mu) |mu| ||x||)
+    const int64_t ld = voffs ? (int64_t)n : ldv;
+    const int64_t base = voffs ? voffs[p] : 0;
+    const int ko = M.neg ? n - 1 - k : k;
+    const double sg = M.neg ? -1.0 : 1.0;
+    double* col = V + base + (int64_t)ko * ld;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      double dj = sd[M.off + j], zj = sz[M.off + j];
+      double r = m / ((dj - sigma) - m);
+      double v = sg * (zj * r) * inv;
+      int jo = M.neg ? n - 1 - j : j;
+      __builtin_nontemporal_store(v, &col[jo]);
+    }
+  }
+}
+
+// ===================================================================== host
+struct Layout {
+  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, fix, items, ctr, total;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+static Layout layout(int64_t nprob, int64_t N, int64_t nitems) {
+  Layout L;
+  size_t o = 0;
+  L.meta = o; o = al(o + sizeof(Meta) * nprob);
+  L.sd = o; o = al(o + 8 * N);
+  L.sz = o; o = al(o + 8 * N);
+  L.pairs = o; o = al(o + 16 * N);
+  L.z2lo = o; o = al(o + 8 * N);
+  L.ii = o; o = al(o + 4 * N);
+  L.mu = o; o = al(o + 8 * N);
+  L.xs = o; o = al(o + 8 * N);
+  L.lam = o; o = al(o + 8 * N);
+  L.fix = o; o = al(o + sizeof(FixItem) * N);
+  L.items = o; o = al(o + sizeof(int2) * nitems);
+  L.ctr = o; o = al(o + 64);
+  L.total = o;
+  return L;
+}
+
+static void fill_opts(const dpr1_opts* in, dpr1_opts* o) {
+  dpr1_default_opts(o);
+  if (in) {
+    *o = *in;
+    if (!(o->kappa_polish > 0)) o->kappa_polish = 16.0;
+    if (o->nearzero < 0) o->nearzero = 10.0;
+  }
+}
+
+static int pick_split(int64_t nblocks, int64_t nmax) {
+  // enough waves for 256 CUs x 8, without slices shorter than 256 terms
+  int64_t w = (2048 + nblocks - 1) / std::max<int64_t>(nblocks, 1);
+  w = std::min<int64_t>(w, MAXW);
+  while (w > 1 && nmax / w < 256) --w;
+  return (int)std::max<int64_t>(w, 1);
+}
+
+static size_t red_bytes(int W) { return W > 1 ? sizeof(double) * 2 * W * WAVE : 0; }
+
+}  // namespace dpr1
+
+using namespace dpr1;
+
+extern "C" {
+
+void dpr1_default_opts(dpr1_opts* o) {
+  o->mode_b = 0;
+  o->root = 1;
+  o->polish = 1;
+  o->split = 0;
+  o->kappa_polish = 16.0;
+  o->nearzero = 10.0;
+  o->events = nullptr;
+}
+
+size_t dpr1_workspace_size(int64_t n) {
+  if (n < 1) return 0;
+  return layout(1, n, 0).total;
+}
+
+#define HIPCHECK(x)                           \
+  do {                                        \
+    if ((x) != hipSuccess) return DPR1_EHIP;  \
+  } while (0)
+
+static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, const int64_t* offs,
+                        int64_t n_single, const double* d, const double* z, const double* rho_dev,
+                        double rho_host, double* lambda, double* V, const int64_t* voffs, int64_t ldv,
+                        int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, int32_t* stats,
+                        const dpr1_opts& o, int W, int64_t nitems, int persistent_grid, hipStream_t st) {
+  Meta* meta = (Meta*)(w + L.meta);
+  KArgs A;
+  A.meta = meta;
+  A.pairs = (const double*)(w + L.pairs);
+  A.z2lo = (const double*)(w + L.z2lo);
+  A.sd = (const double*)(w + L.sd);
+  A.sz = (const double*)(w + L.sz);
+  A.ii = (int32_t*)(w + L.ii);
+  A.mu = (double*)(w + L.mu);
+  A.xs = (double*)(w + L.xs);
+  A.lam = (double*)(w + L.lam);
+  A.fix = (FixItem*)(w + L.fix);
+  A.ctr = (int32_t*)(w + L.ctr);
+  A.stats = stats;
+  A.items = persistent_grid ? (const int2*)(w + L.items) : nullptr;
+  A.nitems = (int32_t)nitems;
+  A.W = W;
+  A.mode_b = o.mode_b;
+  A.root = o.root;
+  A.polish = o.polish;
+  A.want_v = V != nullptr;
+  A.kappa_polish = o.kappa_polish;
+  A.nearzero = o.nearzero;
+
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, A.ctr, 16);
+  if (stats) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, stats, DPR1_NSTATS);
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)nprob), dim3(256), 0, st, (int)nprob, offs, n_single, d, z,
+                     rho_dev, rho_host, meta, (double*)A.sd, (double*)A.sz, (double*)A.pairs,
+                     (double*)A.z2lo, info);
+  HIPCHECK(hipGetLastError());
+  hipEvent_t* ev = (hipEvent_t*)o.events;
+  unsigned grid = persistent_grid ? (unsigned)persistent_grid : (unsigned)nitems;
+  if (ev) HIPCHECK(hipEventRecord(ev[0], st));
+  hipLaunchKernelGGL(k_eig, dim3(grid), dim3(64 * W), red_bytes(W), st, A);
+  HIPCHECK(hipGetLastError());
+  if (ev) HIPCHECK(hipEventRecord(ev[1], st));
+  unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 4096);
+  hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(64), 0, st, A);
+  HIPCHECK(hipGetLastError());
+  int64_t nmax = n_single;
+  (void)nmax;
+  hipLaunchKernelGGL(k_out, dim3(offs ? 1 : (unsigned)std::min<int64_t>((N + 255) / 256, 1024), (unsigned)nprob),
+                     dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, lambda, shift_idx, mu,
+                     xnorm);
+  HIPCHECK(hipGetLastError());
+  if (V) {
+    unsigned vgrid = (unsigned)std::min<int64_t>(N, 1 << 20);
+    if (ev) HIPCHECK(hipEventRecord(ev[2], st));
+    hipLaunchKernelGGL(k_vec, dim3(vgrid), dim3(256), 0, st, meta, (int)nprob, N, A.sd, A.sz, A.ii, A.mu,
+                       A.xs, V, voffs, ldv);
+    HIPCHECK(hipGetLastError());
+    if (ev) HIPCHECK(hipEventRecord(ev[3], st));
+  }
+  return DPR1_OK;
+}
+
+int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V, int64_t ldv,
+             int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, int32_t* stats,
+             const dpr1_opts* opts, void* work, size_t work_bytes, void* stream) {
+  if (!d) return -1;
+  if (!z) return -2;
+  if (!(rho == rho) || rho == 0.0 || rho == INFINITY || rho == -INFINITY) return -3;
+  if (n < 1 || n > (int64_t)INT32_MAX / 2) return -4;
+  if (!lambda) return -5;
+  if (V && ldv < n) return -7;
+  if (!info) return -11;
+  Layout L = layout(1, n, 0);
+  if (!work) return -14;
+  if (work_bytes < L.total) return -15;
+  dpr1_opts o;
+  fill_opts(opts, &o);
+  int64_t nblocks = (n + WAVE - 1) / WAVE;
+  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
+  return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
+                      mu, xnorm, info, stats, o, W, nblocks, 0, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------ batched
+size_t dpr1_batched_workspace_size(int64_t nprob, int64_t ntotal) {
+  if (nprob < 1 || ntotal < nprob) return 0;
+  int64_t nitems = ntotal / WAVE + nprob;  // upper bound of sum ceil(n_p/64)
+  return layout(nprob, ntotal, nitems).total;
+}
+
+int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* opts, dpr1_plan* plan,
+                      void* work, size_t work_bytes, void* stream) {
+  if (nprob < 1 || nprob > (1 << 24)) return -1;
+  if (!offs_host) return -2;
+  if (!plan) return -4;
+  if (!work) return -5;
+  if (offs_host[0] != 0) return -2;
+  int64_t nmax = 0;
+  for (int64_t p = 0; p < nprob; ++p) {
+    int64_t np = offs_host[p + 1] - offs_host[p];
+    if (np < 1 || np > (int64_t)INT32_MAX / 2) return -2;
+    nmax = std::max(nmax, np);
+  }
+  int64_t N = offs_host[nprob];
+  if (N > (int64_t)INT32_MAX) return -2;
+  Layout L0 = layout(nprob, N, N / WAVE + nprob);
+  if (work_bytes < L0.total) return -6;
+  dpr1_opts o;
+  fill_opts(opts, &o);
+  // longest-processing-time order: larger problems first
+  std::vector<int32_t> order(nprob);
+  for (int64_t p = 0; p < nprob; ++p) order[p] = (int32_t)p;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return offs_host[a + 1] - offs_host[a] > offs_host[b + 1] - offs_host[b];
+  });
+  std::vector<int2> items;
+  for (int32_t p : order) {
+    int64_t np = offs_host[p + 1] - offs_host[p];
+    for (int64_t k0 = 0; k0 < np; k0 += WAVE) items.push_back(make_int2(p, (int)k0));
+  }
+  int64_t nitems = (int64_t)items.size();
+  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nitems, nmax);
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(hipMemcpyAsync((char*)work + L0.items, items.data(), sizeof(int2) * nitems, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  plan->nprob = nprob;
+  plan->ntotal = N;
+  plan->nitems = nitems;
+  plan->nmax = nmax;
+  plan->split = W;
+  plan->grid = (int32_t)std::min<int64_t>(nitems, std::max<int64_t>(1, (int64_t)(256 * 16) / W));
+  plan->opts = o;
+  return DPR1_OK;
+}
+
+int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d, const double* z,
+                     const double* rho, double* lambda, double* V, const int64_t* voffs, int32_t* shift_idx,
+                     double* mu, double* xnorm, int32_t* info, int32_t* stats, void* work, size_t work_bytes,
+                     void* stream) {
+  if (!plan || plan->nprob < 1) return -1;
+  if (!offs) return -2;
+  if (!d) return -3;
+  if (!z) return -4;
+  if (!rho) return -5;
+  if (!lambda) return -6;
+  if (V && !voffs) return -8;
+  if (!info) return -12;
+  if (!work) return -14;
+  Layout L = layout(plan->nprob, plan->ntotal, plan->ntotal / WAVE + plan->nprob);
+  if (work_bytes < L.total) return -15;
+  return launch_solve(L, (char*)work, plan->nprob, plan->ntotal, offs, 0, d, z, rho, 0.0, lambda, V, voffs, 0,
+                      shift_idx, mu, xnorm, info, stats, plan->opts, plan->split, plan->nitems, plan->grid,
+                      (hipStream_t)stream);
+}
+
+const char* dpr1_strerror(int code) {
+  switch (code) {
+    case DPR1_OK: return "ok";
+    case DPR1_EHIP: return "a HIP runtime call or kernel launch failed";
+    case DPR1_INFO_UNSORTED: return "info: d is not strictly decreasing";
+    case DPR1_INFO_ZERO_Z: return "info: some z_j is zero (reducible problem)";
+    case DPR1_INFO_NONFINITE: return "info: non-finite input";
+    case DPR1_INFO_BAD_RHO: return "info: rho is zero or not finite";
+    default: return code < 0 ? "invalid argument (see the argument position -code)" : "unknown code";
+  }
+}
+
+}  // extern "C"

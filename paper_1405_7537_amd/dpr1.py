@@ -1,0 +1,238 @@
+"""Python binding of libdpr1.so (argument marshalling only).
+
+Device memory and streams come from PyTorch; every step of the eigensolver
+runs in the HIP kernels behind the C ABI declared in include/dpr1.h.  There is
+no CPU fallback: the calls raise if the library is not built or no GPU is
+present.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpr1.so")
+
+INFO_TEXT = {0: "ok", 1: "d is not strictly decreasing", 2: "some z_j is zero (reducible)",
+             3: "non-finite input", 4: "rho is zero or not finite"}
+NSTATS = 8
+STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "iters_sum", "r6", "r7"]
+
+
+class Opts(C.Structure):
+    _fields_ = [("mode_b", C.c_int32), ("root", C.c_int32), ("polish", C.c_int32),
+                ("split", C.c_int32), ("kappa_polish", C.c_double), ("nearzero", C.c_double),
+                ("events", C.c_void_p)]
+
+
+class Plan(C.Structure):
+    _fields_ = [("nprob", C.c_int64), ("ntotal", C.c_int64), ("nitems", C.c_int64),
+                ("nmax", C.c_int64), ("split", C.c_int32), ("grid", C.c_int32), ("opts", Opts)]
+
+
+_lib = None
+vp = C.c_void_p
+i64 = C.c_int64
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        L.dpr1_default_opts.argtypes = [C.POINTER(Opts)]
+        L.dpr1_workspace_size.argtypes = [i64]
+        L.dpr1_workspace_size.restype = C.c_size_t
+        L.dpr1_eig.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, vp, vp, vp, vp,
+                               C.POINTER(Opts), vp, C.c_size_t, vp]
+        L.dpr1_batched_workspace_size.argtypes = [i64, i64]
+        L.dpr1_batched_workspace_size.restype = C.c_size_t
+        L.dpr1_batched_plan.argtypes = [i64, C.POINTER(C.c_int64), C.POINTER(Opts), C.POINTER(Plan),
+                                        vp, C.c_size_t, vp]
+        L.dpr1_eig_batched.argtypes = [C.POINTER(Plan), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                       vp, vp, C.c_size_t, vp]
+        if hasattr(L, "dpr1_backward_workspace_size"):
+            L.dpr1_backward_workspace_size.argtypes = [i64, i64]
+            L.dpr1_backward_workspace_size.restype = C.c_size_t
+            L.dpr1_eig_backward_batched.argtypes = [i64, i64] + [vp] * 11 + [vp, C.c_size_t, vp]
+        L.dpr1_strerror.argtypes = [C.c_int]
+        L.dpr1_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def opts(mode_b=0, root=1, polish=1, split=0, kappa_polish=16.0, nearzero=10.0, events=None) -> Opts:
+    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, events)
+
+
+class HipEvents:
+    """Four hipEvent_t handles for the solve's profiling hook (opts.events)."""
+
+    def __init__(self):
+        self.rt = C.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.rt.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.rt.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [C.c_void_p]
+        self.arr = (C.c_void_p * 4)()
+        for t in range(4):
+            h = C.c_void_p()
+            if self.rt.hipEventCreate(C.byref(h)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.arr[t] = h
+
+    @property
+    def ptr(self):
+        return C.cast(self.arr, C.c_void_p)
+
+    def ms(self, a, b):
+        self.rt.hipEventSynchronize(self.arr[b])
+        out = C.c_float()
+        if self.rt.hipEventElapsedTime(C.byref(out), self.arr[a], self.arr[b]) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(out.value)
+
+    def eig_ms(self):
+        return self.ms(0, 1)
+
+    def vec_ms(self):
+        return self.ms(2, 3)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, device):
+    t = torch.as_tensor(x, dtype=torch.float64)
+    return t.to(device).contiguous()
+
+
+def _rc(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed: {rc} ({lib().dpr1_strerror(rc).decode()})")
+
+
+class Result:
+    """Outputs of one solve; V[:, k] is the eigenvector of lam[k]."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    def stats_dict(self):
+        s = self.stats.cpu().tolist()
+        return dict(zip(STAT_NAMES, s))
+
+
+def workspace_bytes(n):
+    return int(lib().dpr1_workspace_size(int(n)))
+
+
+def eig(d, z, rho, vectors=True, opts: Opts | None = None, check=True, want_stats=False,
+        work=None, out=None, device="cuda"):
+    """All eigenpairs of D + rho z z^T.  d, z: 1-D float64 (device tensors or host data).
+
+    Returns a Result with lam [n], V [n, n] (V[:, k] = v_k, column-major storage), shift_idx,
+    mu, xnorm, info and (optionally) stats."""
+    d = _dev(d, device)
+    z = _dev(z, device)
+    n = d.numel()
+    dev = d.device
+    if out is None:
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        Vt = torch.empty((n, n), dtype=torch.float64, device=dev) if vectors else None
+        idx = torch.empty(n, dtype=torch.int32, device=dev)
+        mu = torch.empty(n, dtype=torch.float64, device=dev)
+        xn = torch.empty(n, dtype=torch.float64, device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+    else:
+        lam, Vt, idx, mu, xn, info = out
+    stats = torch.empty(NSTATS, dtype=torch.int32, device=dev) if want_stats else None
+    wb = workspace_bytes(n)
+    if work is None or work.numel() < wb:
+        work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    rc = lib().dpr1_eig(_ptr(d), _ptr(z), float(rho), n, _ptr(lam), _ptr(Vt), n, _ptr(idx), _ptr(mu),
+                        _ptr(xn), _ptr(info), _ptr(stats), C.byref(opts) if opts is not None else None,
+                        _ptr(work), wb, _stream())
+    _rc(rc, "dpr1_eig")
+    r = Result(lam=lam, V=Vt.t() if Vt is not None else None, shift_idx=idx, mu=mu, xnorm=xn,
+               info=info, stats=stats, work=work)
+    if check:
+        code = int(info.item())
+        if code != 0:
+            raise ValueError(f"dpr1_eig: info = {code} ({INFO_TEXT.get(code, '?')})")
+    return r
+
+
+class Batch:
+    """A planned ragged batch (sizes fixed); solve() can be called repeatedly."""
+
+    def __init__(self, offs, opts: Opts | None = None, vectors=True, device="cuda"):
+        offs = np.ascontiguousarray(offs, dtype=np.int64)
+        self.offs_host = offs
+        self.nprob = offs.size - 1
+        self.ntotal = int(offs[-1])
+        sizes = np.diff(offs)
+        self.sizes = sizes
+        self.vectors = vectors
+        voffs = np.zeros(self.nprob, dtype=np.int64)
+        voffs[1:] = np.cumsum(sizes[:-1] ** 2)
+        self.voffs_host = voffs
+        self.vtotal = int(np.sum(sizes ** 2))
+        self.dev = torch.device(device)
+        self.offs = torch.as_tensor(offs).to(self.dev)
+        self.voffs = torch.as_tensor(voffs).to(self.dev)
+        self.wb = int(lib().dpr1_batched_workspace_size(self.nprob, self.ntotal))
+        self.work = torch.empty(self.wb, dtype=torch.uint8, device=self.dev)
+        self.plan = Plan()
+        rc = lib().dpr1_batched_plan(self.nprob, offs.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     C.byref(opts) if opts is not None else None, C.byref(self.plan),
+                                     _ptr(self.work), self.wb, _stream())
+        _rc(rc, "dpr1_batched_plan")
+        N = self.ntotal
+        self.lam = torch.empty(N, dtype=torch.float64, device=self.dev)
+        self.V = torch.empty(self.vtotal, dtype=torch.float64, device=self.dev) if vectors else None
+        self.shift_idx = torch.empty(N, dtype=torch.int32, device=self.dev)
+        self.mu = torch.empty(N, dtype=torch.float64, device=self.dev)
+        self.xnorm = torch.empty(N, dtype=torch.float64, device=self.dev)
+        self.info = torch.empty(self.nprob, dtype=torch.int32, device=self.dev)
+        self.stats = torch.empty(NSTATS, dtype=torch.int32, device=self.dev)
+
+    def solve(self, d, z, rho, want_stats=False):
+        """Enqueue the solve on the current stream (no synchronisation)."""
+        rc = lib().dpr1_eig_batched(C.byref(self.plan), _ptr(self.offs), _ptr(d), _ptr(z), _ptr(rho),
+                                    _ptr(self.lam), _ptr(self.V), _ptr(self.voffs) if self.V is not None else None,
+                                    _ptr(self.shift_idx), _ptr(self.mu), _ptr(self.xnorm), _ptr(self.info),
+                                    _ptr(self.stats) if want_stats else None, _ptr(self.work), self.wb,
+                                    _stream())
+        _rc(rc, "dpr1_eig_batched")
+        return self
+
+    def vblock(self, p):
+        """V of problem p as an [n_p, n_p] view (V[:, k] = v_k)."""
+        n = int(self.sizes[p])
+        o = int(self.voffs_host[p])
+        return self.V[o:o + n * n].view(n, n).t()
+
+    def check(self):
+        info = self.info.cpu().numpy()
+        bad = np.nonzero(info)[0]
+        if bad.size:
+            raise ValueError(f"dpr1_eig_batched: problem {bad[0]} info = {info[bad[0]]}")
+
+
+def eig_batched(d, z, rho, offs, vectors=True, opts: Opts | None = None, check=True, want_stats=False,
+                device="cuda"):
+    b = Batch(offs, opts=opts, vectors=vectors, device=device)
+    b.solve(_dev(d, device), _dev(z, device), _dev(rho, device), want_stats=want_stats)
+    if check:
+        b.check()
+    return b

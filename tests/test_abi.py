@@ -1,0 +1,68 @@
+"""The C-ABI library builds for gfx950, loads, and exports every declared entry point (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "dpr1.h")
+LIB = os.path.join(ROOT, "paper_1405_7537_amd", "libdpr1.so")
+
+
+def declared_functions():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(dpr1_[a-z_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["dpr1_eig", "dpr1_eig_batched", "dpr1_batched_plan", "dpr1_workspace_size",
+                 "dpr1_batched_workspace_size", "dpr1_eig_backward_batched",
+                 "dpr1_backward_workspace_size", "dpr1_default_opts", "dpr1_strerror"]:
+        assert must in names, must
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libdpr1.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_library_has_gfx950_code_object():
+    data = open(LIB, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_host_side_queries(lib):
+    lib.dpr1_workspace_size.argtypes = [ctypes.c_int64]
+    lib.dpr1_workspace_size.restype = ctypes.c_size_t
+    assert lib.dpr1_workspace_size(0) == 0
+    a = lib.dpr1_workspace_size(1000)
+    b = lib.dpr1_workspace_size(2000)
+    assert 0 < a < b
+    lib.dpr1_strerror.argtypes = [ctypes.c_int]
+    lib.dpr1_strerror.restype = ctypes.c_char_p
+    assert lib.dpr1_strerror(0) == b"ok"
+
+
+def test_argument_errors_need_no_gpu(lib):
+    """Synchronous argument checks return -p before anything touches the device."""
+    vp = ctypes.c_void_p
+    lib.dpr1_eig.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64, vp, vp, vp,
+                             vp, vp, vp, vp, ctypes.c_size_t, vp]
+    fake = vp(0x1000)
+    assert lib.dpr1_eig(None, fake, 1.0, 4, fake, None, 4, None, None, None, fake, None, None, fake, 1 << 20, None) == -1
+    assert lib.dpr1_eig(fake, fake, 0.0, 4, fake, None, 4, None, None, None, fake, None, None, fake, 1 << 20, None) == -3
+    assert lib.dpr1_eig(fake, fake, float("nan"), 4, fake, None, 4, None, None, None, fake, None, None, fake, 1 << 20, None) == -3
+    assert lib.dpr1_eig(fake, fake, 1.0, 0, fake, None, 4, None, None, None, fake, None, None, fake, 1 << 20, None) == -4
+    assert lib.dpr1_eig(fake, fake, 1.0, 8, fake, fake, 4, None, None, None, fake, None, None, fake, 1 << 20, None) == -7
+    assert lib.dpr1_eig(fake, fake, 1.0, 8, fake, None, 8, None, None, None, fake, None, None, fake, 16, None) == -15

@@ -1,0 +1,113 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Bar (from the design): eigenvalue relative error <= 1e-13 and eigenvector componentwise
+relative error <= 1e-12, element by element.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1405_7537_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+LAM_TOL = 1e-13
+VEC_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1405_7537_amd.dpr1 as D
+    D.lib()
+    return D
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = np.abs(b)
+    out = np.abs(a - b) / np.where(den == 0, 1.0, den)
+    return out
+
+
+def compare(D, orc, d, z, rho, opts=None, oopts=None, tag=""):
+    print(f"[parity] {tag} n={len(d)} rho={rho}", flush=True)
+    r = D.eig(d, z, rho, opts=opts, want_stats=True)
+    lam = r.lam.cpu().numpy()
+    V = r.V.cpu().numpy()
+    lo, Vo, dg = orc.eig(d, z, rho, opts=oopts, diags=True)
+    el = rel(lam, lo)
+    ev = rel(V, Vo)
+    print(f"[parity] {tag}: max rel lam {el.max():.3e} V {ev.max():.3e} stats {r.stats_dict()}", flush=True)
+    assert el.max() <= LAM_TOL, (np.argmax(el), el.max())
+    assert ev.max() <= VEC_TOL, (np.unravel_index(np.argmax(ev), ev.shape), ev.max())
+    return r, lo, Vo, dg
+
+
+def test_examples(D, orc):
+    for tag, (d, z, rho) in [("ex1", W.example1()), ("ex2", W.example2()), ("ex3", W.example3())]:
+        compare(D, orc, d, z, rho, tag=tag)
+
+
+def test_config_small_uniform(D, orc):
+    compare(D, orc, *W.uniform(256, 0), tag="n256")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 63, 64, 65, 127, 129, 300])
+def test_ragged_sizes(D, orc, n):
+    compare(D, orc, *W.uniform(n, 40 + n), tag=f"ragged{n}")
+
+
+def test_bisection_root(D, orc):
+    compare(D, orc, *W.uniform(200, 3), opts=D.opts(root=0), tag="bisect")
+
+
+def test_negative_rho(D, orc):
+    d, z, _ = W.uniform(150, 8)
+    compare(D, orc, d, z, -0.8, tag="negrho")
+
+
+def test_large_rho_exterior(D, orc):
+    compare(D, orc, *W.uniform(512, 11, rho=10.0), tag="rho10")
+
+
+def test_graded_clustered(D, orc):
+    r, *_ = compare(D, orc, *W.graded(1024, 1, pair_every=64), tag="graded1024")
+    assert r.stats_dict()["polished"] >= 1
+
+
+def test_example4_kb_counts(D, orc):
+    for beta, count in [(1e-3, 25), (1e-8, 201), (1e-15, 201)]:
+        d, z, rho = W.example4(beta)
+        r, *_ = compare(D, orc, d, z, rho, opts=D.opts(mode_b=1), oopts=orc.make_opts(mode_b=1),
+                        tag=f"ex4 beta={beta}")
+        assert r.stats_dict()["kb_gt_100"] == count
+
+
+def test_near_zero_and_singular(D, orc):
+    d = np.array([2.0, 1.0, -1.0, -2.0])
+    z = np.array([0.7, -1.1, 0.9, 0.0])
+    rho = 1.3
+    s = 1 + rho * sum(z[j] ** 2 / d[j] for j in range(3))
+    z[3] = math.sqrt(s * 2.0 / rho)
+    r, *_ = compare(D, orc, d, z, rho, tag="nearzero")
+    assert r.stats_dict()["nearzero"] == 1
+    r = D.eig([1.0, -1.0], [0.75, 1.25], 1.0, want_stats=True)
+    assert r.lam.cpu().numpy()[1] == 0.0
+
+
+def test_info_codes(D):
+    d, z, rho = W.uniform(16, 2)
+    assert int(D.eig(d[::-1].copy(), z, rho, check=False).info.item()) == 1
+    z0 = z.copy()
+    z0[5] = 0.0
+    assert int(D.eig(d, z0, rho, check=False).info.item()) == 2
+    dn = d.copy()
+    dn[3] = np.inf
+    assert int(D.eig(dn, z, rho, check=False).info.item()) == 3
+    with pytest.raises(RuntimeError):
+        D.eig(d, z, 0.0)
