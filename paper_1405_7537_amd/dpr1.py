@@ -58,7 +58,7 @@ def lib():
         if hasattr(L, "dpr1_backward_workspace_size"):
             L.dpr1_backward_workspace_size.argtypes = [i64, i64]
             L.dpr1_backward_workspace_size.restype = C.c_size_t
-            L.dpr1_eig_backward_batched.argtypes = [i64, i64] + [vp] * 11 + [vp, C.c_size_t, vp]
+            L.dpr1_eig_backward_batched.argtypes = [i64, i64] + [vp] * 12 + [vp, C.c_size_t, vp]
         L.dpr1_strerror.argtypes = [C.c_int]
         L.dpr1_strerror.restype = C.c_char_p
         _lib = L
@@ -236,3 +236,120 @@ def eig_batched(d, z, rho, offs, vectors=True, opts: Opts | None = None, check=T
     if check:
         b.check()
     return b
+
+
+# --------------------------------------------------------------- backward
+def backward_batched(d, z, rho, shift_idx, mu, xnorm, V, lam_bar=None, V_bar=None, work=None):
+    """Reverse mode for nb problems of equal size n.
+
+    d, z, shift_idx, mu, xnorm, lam_bar: [nb, n]; rho: [nb]; V, V_bar: column-major storage of
+    [nb] n x n matrices (tensors whose memory is V[b] with element (j, k) at j + k n).
+    Returns (d_bar [nb, n], z_bar [nb, n], rho_bar [nb])."""
+    nb, n = d.shape
+    dev = d.device
+    d_bar = torch.empty((nb, n), dtype=torch.float64, device=dev)
+    z_bar = torch.empty((nb, n), dtype=torch.float64, device=dev)
+    rho_bar = torch.empty(nb, dtype=torch.float64, device=dev)
+    wb = int(lib().dpr1_backward_workspace_size(n, nb))
+    if work is None or work.numel() < wb:
+        work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    for t in (d, z, rho, shift_idx, mu, xnorm, V, lam_bar, V_bar):
+        if t is not None:
+            assert t.is_contiguous() and t.device == dev
+    rc = lib().dpr1_eig_backward_batched(nb, n, _ptr(d), _ptr(z), _ptr(rho), _ptr(shift_idx), _ptr(mu),
+                                         _ptr(xnorm), _ptr(V), _ptr(lam_bar), _ptr(V_bar), _ptr(d_bar),
+                                         _ptr(z_bar), _ptr(rho_bar), _ptr(work), wb, _stream())
+    _rc(rc, "dpr1_eig_backward_batched")
+    return d_bar, z_bar, rho_bar
+
+
+class DPR1Eig(torch.autograd.Function):
+    """(lam, V) = eig(D + rho z z^T) with a hand-written adjoint.
+
+    Forward: dpr1_eig.  Backward: dpr1_eig_backward_batched with nb = 1, which needs only
+    V and the shifted representation (shift_idx, mu, ||x||) saved by the forward."""
+
+    @staticmethod
+    def forward(ctx, d, z, rho):
+        rho_t = rho if torch.is_tensor(rho) else torch.tensor(float(rho), dtype=torch.float64, device=d.device)
+        r = eig(d.detach(), z.detach(), float(rho_t), vectors=True)
+        ctx.save_for_backward(d.detach(), z.detach(), rho_t.detach().reshape(1).to(d.device), r.shift_idx, r.mu,
+                              r.xnorm, r.V)
+        return r.lam, r.V
+
+    @staticmethod
+    def backward(ctx, lam_bar, V_bar):
+        d, z, rho, idx, mu, xn, V = ctx.saved_tensors
+        n = d.numel()
+        lb = lam_bar.contiguous().view(1, n) if lam_bar is not None else None
+        # V is the transpose view of a row-major [k, j] buffer: column-major storage
+        Vs = V.t().contiguous()
+        Vb = V_bar.t().contiguous() if V_bar is not None else None
+        db, zb, rb = backward_batched(d.view(1, n), z.view(1, n), rho, idx.view(1, n), mu.view(1, n),
+                                      xn.view(1, n), Vs, lb, Vb)
+        return db.view(n), zb.view(n), rb.view(())
+
+
+class DPR1EigBatched(torch.autograd.Function):
+    """Uniform batch: d, z [nb, n], rho [nb] -> lam [nb, n], V [nb, n, n] (V[b][:, k] = v_k)."""
+
+    @staticmethod
+    def forward(ctx, d, z, rho):
+        nb, n = d.shape
+        offs = np.arange(nb + 1, dtype=np.int64) * n
+        b = Batch(offs, device=d.device)
+        b.solve(d.detach().contiguous(), z.detach().contiguous(), rho.detach().contiguous())
+        Vst = b.V.view(nb, n, n)          # [b, k, j] = v_k[j] (column-major blocks)
+        ctx.save_for_backward(d.detach(), z.detach(), rho.detach(), b.shift_idx.view(nb, n), b.mu.view(nb, n),
+                              b.xnorm.view(nb, n), Vst)
+        return b.lam.view(nb, n), Vst.transpose(1, 2)
+
+    @staticmethod
+    def backward(ctx, lam_bar, V_bar):
+        d, z, rho, idx, mu, xn, Vst = ctx.saved_tensors
+        lb = lam_bar.contiguous() if lam_bar is not None else None
+        Vb = V_bar.transpose(1, 2).contiguous() if V_bar is not None else None
+        return backward_batched(d.contiguous(), z.contiguous(), rho.contiguous(), idx, mu, xn, Vst, lb, Vb)
+
+
+def bench_fwd_bwd(torch_mod, dev, steps, nb=256, n=512, seed=4):
+    """Forward + backward of nb problems of order n: L = sum(w * lam) + sum(W o V)."""
+    from . import workloads as W
+    d_h, z_h, rho_h = W.uniform_batch(nb, n, seed)
+    rng = np.random.default_rng(seed + 100)
+    d = torch.as_tensor(d_h, device=dev)
+    z = torch.as_tensor(z_h, device=dev)
+    rho = torch.as_tensor(rho_h, device=dev)
+    w = torch.as_tensor(rng.standard_normal((nb, n)), device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    Wb = torch.randn((nb, n, n), generator=g, dtype=torch.float64, device=dev)   # column-major V_bar blocks
+    offs = np.arange(nb + 1, dtype=np.int64) * n
+    b = Batch(offs, device=dev)
+    wb = int(lib().dpr1_backward_workspace_size(n, nb))
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+
+    def one():
+        b.solve(d, z, rho)
+        return backward_batched(d, z, rho, b.shift_idx.view(nb, n), b.mu.view(nb, n), b.xnorm.view(nb, n),
+                                b.V, w, Wb, work=work)
+
+    import time
+    for _ in range(2):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.solve(d, z, rho)
+    torch.cuda.synchronize()
+    ms_f = (time.perf_counter() - t0) * 1e3 / steps
+    flops = 2 * 2 * n ** 3 * nb
+    return {"workload": f"{nb} DPR1 problems of n={n} (seed {seed}), L = sum(w*lam) + sum(W o V)",
+            "value": nb / (ms / 1e3), "unit": "problems/s (forward+backward)", "ms_per_step": ms,
+            "forward_ms": ms_f, "backward_ms": ms - ms_f,
+            "gemm_TFLOPs": flops / ((ms - ms_f) / 1e3) / 1e12}
