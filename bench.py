@@ -55,7 +55,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip batched / fwd+bwd / eigenvalues-only lines")
+    ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
+                    help="copy: a plain device copy of known size, to calibrate HBM byte counters")
     args = ap.parse_args()
+    if args.mode == "copy":
+        return copy_calibration()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -188,6 +192,21 @@ def main():
             result["fwd_bwd"] = fb
 
     print(json.dumps(result), flush=True)
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """y <- x for 1 GiB float64 buffers: each dispatch reads and writes exactly nbytes."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    print(json.dumps({"mode": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "reps": reps,
+                      "ms": ms, "GB/s": 2 * nbytes / (ms / 1e3) / 1e9}), flush=True)
 
 
 def source_sha():

@@ -89,6 +89,28 @@ __device__ __forceinline__ double fmid(double lo, double hi) {
 }
 __device__ __forceinline__ bool adjacent(double lo, double hi) { return bits(hi) - bits(lo) <= 1; }
 
+// Reciprocal from the hardware estimate refined by two Newton steps (within
+// about one ulp) and a quotient with one residual correction (within about
+// half an ulp more than correct rounding).  Used where the iteration only
+// needs the value, not the correctly rounded one; the IEEE divide costs about
+// twice as many instructions on this ISA.
+// v_rcp_f64 is good to 2^-24.4 relative (measured on gfx950 over random
+// normal inputs); one Newton step gives 2^-48.7, two give full precision.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+// one Newton step: enough where only the sign or a model step is needed, and
+// as the seed of a quotient that is corrected by its residual
+__device__ __forceinline__ double rcp_1nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); }
 __device__ __forceinline__ int lane_id() { return threadIdx.x % WAVE; }
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
@@ -269,13 +291,19 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   const double dkm1 = kk > 0 ? Dv[kk - 1] : 0.0;
 
   // ---- shift (Alg. 1): F = 1 + rho sum zeta_j^2/((d_j - d_k) - tau)
+  // The same pass also sums |terms| and terms/den (f' at the midpoint): the
+  // midpoint is the first probe of the root finder, so its evaluation is reused.
   const double tau = (dkm1 - dk) / 2;
-  double Fs[1] = {0.0};
+  double Fs[3] = {0.0, 0.0, 0.0};
   sweep(j0, j1, wlo, whi, [&](int j, int) {
     double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
-    Fs[0] += z2 / ((dj - dk) - tau);
+    double r = rcp_1nr((dj - dk) - tau);
+    double t = z2 * r;
+    Fs[0] += t;
+    Fs[1] += fabs(t);
+    Fs[2] = __builtin_fma(t, r, Fs[2]);
   });
-  wg_sum<1>(Fs, W, wv, lane, red);
+  wg_sum<3>(Fs, W, wv, lane, red);
   const double F = 1.0 + rho * Fs[0];
   const bool right = (kk == 0) || (F > 0);
   const int i = right ? kk : kk - 1;
@@ -286,19 +314,33 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
 
   // ---- tip b of A_i^{-1} (eq. b_ob) in double-double, plus the binary64 sums
   // of eq. (knu2).  P collects j < i (delta > 0), N collects j > i.
+  // Each term zeta_j^2/(d_j - sigma) is formed as q1 + q2 from the exact
+  // difference (TwoSum), the exact square (hi + lo) and one residual
+  // correction, relative error about 2^-100; P and N each add terms of one
+  // sign only, so their double-double sums do not cancel.
   dd Pd = {0.0, 0.0}, Nd = {0.0, 0.0};
+  auto add_to = [](dd& a, double q1, double q2) {
+    dd t = two_sum(a.hi, q1);
+    t.lo += a.lo + q2;
+    a = fast_two_sum(t.hi, t.lo);
+  };
   sweep(j0, j1, wlo, whi, [&](int j, int seg) {
     double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1), z2l = ldu(Zl, j);
     dd dl = two_sum(dj, -sigma);  // exact d_j - sigma
-    dd q = dd_div(dd{z2, z2l}, dl);
+    double r = rcp_1nr(dl.hi);
+    double q1 = z2 * r;
+    double e = __builtin_fma(-q1, dl.hi, z2);
+    e = __builtin_fma(-q1, dl.lo, e + z2l);
+    double q2 = e * r;
     if (seg == 0) {
-      Pd = dd_add_same(Pd, q);
+      add_to(Pd, q1, q2);
     } else if (seg == 2) {
-      Nd = dd_add_same(Nd, q);
-    } else {
-      dd pn = dd_add_same(Pd, q), nn = dd_add_same(Nd, q);
-      if (j < i) Pd = pn;
-      if (j > i) Nd = nn;
+      add_to(Nd, q1, q2);
+    } else if (j != i) {
+      dd pn = Pd, nn = Nd;
+      add_to(pn, q1, q2);
+      add_to(nn, q1, q2);
+      if (j < i) Pd = pn; else Nd = nn;
     }
   });
   wg_sum_dd(Pd, W, wv, lane, red);
@@ -330,44 +372,57 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     U = (1.0 / (rho * zi2)) * GROW;   // lambda_1 >= d_1 + rho zeta_1^2
     nu = A.root ? U : fmid(L, U);
   }
-  // rigorous bracket, kept for the double-double polish (the signs of g seen
-  // by the binary64 iteration can be wrong when g is badly conditioned)
-  const double L0 = L, U0 = U;
+  // the rigorous bracket [L0, U0] (set below) is kept for the double-double
+  // polish: the signs of g seen by the binary64 iteration can be wrong when g
+  // is badly conditioned
   bool done = !valid;
   int iters = 0;
   double nu0 = nu, prevstep = INFINITY;
   const double rz2 = 1.0 / zi2;
 
+  // First probe of interior roots from the shift pass: g(nu') = f(lambda)/(rho
+  // zeta_i^2) up to the sign s (eqs. secAi, Pick), lambda the midpoint, so
+  // g >= 0 there by the choice of the shift; b' + S/zeta_i^2 = g + nu' is an
+  // upper bound of the root.  If rounding leaves the sign of g open the pole
+  // is kept as the lower end.
+  bool pre = interior && valid;
+  double pre_Sz = 0.0, pre_Spz = 0.0, pre_g = 0.0;
+  if (pre) {
+    const double gerr = 8.0 * 2.220446049250313e-16 * (1.0 + rho * Fs[1]) / (rho * zi2);
+    pre_g = s * (1.0 + rho * Fs[0]) / (rho * zi2);
+    pre_Sz = (pre_g - bp) + nu;
+    pre_Spz = fmax(Fs[2] / (zi2 * nu * nu) - 1.0, 0.0);
+    U = (nu + fmax(pre_g, 0.0) + gerr) * GROW;
+    if (pre_g > gerr) L = nu;
+  }
+  const double L0 = L, U0 = U;
+
   if (A.root == 0) {
     // -------- bisection in the order of the binary64 numbers
-    bool first = true;
     while (wave_any(!done)) {
       double m = nu;
       double S[1] = {0.0};
-      sweep(j0, j1, wlo, whi, [&](int j, int seg) {
-        double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
-        double dl = __builtin_fma(s, dj, nss);
-        double pp = __builtin_fma(m, dl, -1.0);
-        double t = z2 / (dl * pp);
-        if (seg == 1 && j == i) t = 0.0;
-        S[0] += t;
-      });
-      wg_sum<1>(S, W, wv, lane, red);
+      if (wave_any(!done && !pre)) {
+        sweep(j0, j1, wlo, whi, [&](int j, int seg) {
+          double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+          double dl = __builtin_fma(s, dj, nss);
+          double pp = __builtin_fma(m, dl, -1.0);
+          double t = z2 * rcp_1nr(dl * pp);
+          if (seg == 1 && j == i) t = 0.0;
+          S[0] += t;
+        });
+        wg_sum<1>(S, W, wv, lane, red);
+        ++iters;
+      }
       if (!done) {
         double Sz = S[0] * rz2;
         double g = (bp - m) + Sz;
-        if (first && interior) {
-          if (g > 0) {
-            L = m;
-            U = (bp + Sz) * GROW;
-            if (!(U > L)) U = L * (1.0 + 0x1p-30);
-          } else {
-            U = m;
-          }
+        if (pre) {
+          g = pre_g;
+          pre = false;  // bracket already set from the probe
         } else {
           if (g > 0) L = m; else U = m;
         }
-        ++iters;
         if (adjacent(L, U) || iters >= 200) {
           done = true;
           nu0 = U;
@@ -375,7 +430,6 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
           nu = fmid(L, U);
         }
       }
-      first = false;
     }
   } else {
     // -------- safeguarded rational iteration: at nu the sum term of g is
@@ -383,15 +437,15 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     // the linear part b' - t is the next iterate.  Since all poles of S lie
     // left of the model pole, the model lies above S, so the iterates come
     // down monotonically onto the root after the first step.
-    bool first = true;
     while (wave_any(!done)) {
       double m = nu;
       double S[2] = {0.0, 0.0};
+      if (wave_any(!done && !pre)) {
       sweep(j0, j1, wlo, whi, [&](int j, int seg) {
         double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
         double dl = __builtin_fma(s, dj, nss);
         double pp = __builtin_fma(m, dl, -1.0);
-        double rq = 1.0 / (dl * pp);
+        double rq = rcp_1nr(dl * pp);
         double t = z2 * rq;
         double tp = (t * dl) * (dl * rq);  // zeta_j^2/pp^2
         if (seg == 1 && j == i) {
@@ -402,22 +456,20 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
         S[1] += tp;
       });
       wg_sum<2>(S, W, wv, lane, red);
+      ++iters;
+      }
       if (!done) {
         double Sz = S[0] * rz2;
         double Spz = S[1] * rz2;  // -dS/dnu / zeta_i^2
         double g = (bp - m) + Sz;
-        if (first && interior) {
-          if (g > 0) {
-            L = m;
-            U = (bp + Sz) * GROW;
-            if (!(U > L)) U = L * (1.0 + 0x1p-30);
-          } else {
-            U = m;
-          }
+        if (pre) {
+          Sz = pre_Sz;
+          Spz = pre_Spz;
+          g = pre_g;
+          pre = false;  // bracket already set from the probe
         } else {
           if (g > 0) L = m; else U = m;
         }
-        ++iters;
         if (g == 0.0) {
           done = true;
           nu0 = m;
@@ -430,8 +482,12 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
           double u = C >= 0 ? (C + disc) * 0.5 : (2.0 * Am) / (disc - C);
           double nn = xm + u;
           double step = fabs(nn - m);
-          if (step <= 0x1p-40 * m) {
-            done = true;  // converged: the model root sits on the last point
+          // Quadratic convergence: a step below 2^-26 leaves nn within about
+          // 2^-52 of the root, and the compensated Newton step that follows
+          // finishes the job; waiting for smaller steps would only chase the
+          // rounding noise of g (about kappa_g sqrt(n) eps).
+          if (step <= 0x1p-26 * m) {
+            done = true;
             nu0 = (nn >= L && nn <= U) ? nn : m;
           } else if (!(nn > L && nn < U)) {
             if (adjacent(L, U)) {
@@ -454,14 +510,13 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
           }
         }
       }
-      first = false;
     }
   }
 
   // ---- one Newton step with a compensated sum, and the amplification
   // estimate kappa_g = (|b| + |nu| + S)/(|nu| |g'|).
   double cs = 0.0, cc = 0.0;
-  double Sp[1] = {0.0};
+  double Sp[2] = {0.0, 0.0};
   {
     const double m = nu0;
     sweep(j0, j1, wlo, whi, [&](int j, int seg) {
@@ -469,19 +524,25 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double dl = __builtin_fma(s, dj, nss);
       double pp = __builtin_fma(m, dl, -1.0);
       double q = dl * pp;
-      double t = z2 / q;
-      double tp = (t * dl) * (dl / q);
+      double r = rcp_nr(q);
+      double t = z2 * r;
+      t = __builtin_fma(__builtin_fma(-t, q, z2), r, t);  // corrected quotient
+      double ir = dl * r;                                 // 1/pp
+      double tp = (t * dl) * ir;                          // zeta_j^2/pp^2
+      double tp3 = (tp * ir) * dl;                        // zeta_j^2 delta'_j/pp^3
       if (seg == 1 && j == i) {
         t = 0.0;
         tp = 0.0;
+        tp3 = 0.0;
       }
       double y = cs + t;
       cc += (fabs(cs) >= fabs(t)) ? ((cs - y) + t) : ((t - y) + cs);
       cs = y;
       Sp[0] += tp;
+      Sp[1] += tp3;
     });
     wg_sum_comp(cs, cc, W, wv, lane, red);
-    wg_sum<1>(Sp, W, wv, lane, red);
+    wg_sum<2>(Sp, W, wv, lane, red);
   }
   const double Sz = (cs + cc) / zi2;
   const double g = (bp - nu0) + Sz;
@@ -500,17 +561,12 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     nz = A.nearzero * fabs(lam) < gap;
   }
 
-  // ---- ||x|| scaled by |mu|: sum zeta_j^2 (mu/(delta_j - mu))^2 (j = i gives zeta_i^2)
-  double Nx[1] = {0.0};
-  if (A.want_v) {
-    sweep(j0, j1, wlo, whi, [&](int j, int) {
-      double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
-      double r = muv / ((dj - sigma) - muv);
-      Nx[0] = __builtin_fma(z2 * r, r, Nx[0]);
-    });
-    wg_sum<1>(Nx, W, wv, lane, red);
-  }
-
+  // ---- ||x|| scaled by |mu|: with delta_j - mu = s (delta'_j - 1/nu) one has
+  // mu/(delta_j - mu) = 1/(nu delta'_j - 1), so |mu|^2 ||x||^2 =
+  // zeta_i^2 + sum_{j != i} zeta_j^2/pp_j^2, the S' sum of the Newton pass.
+  // That sum is taken at nu0; carried to nu1 to first order with its
+  // derivative -2 sum zeta_j^2 delta'_j/pp_j^3 (error O((nu1 - nu0)^2)).
+  double Nx[1] = {zi2 + (Sp[0] - 2.0 * (nu1 - nu0) * Sp[1])};
   if (wv == 0 && valid) {
     A.ii[off + k] = i;
     A.mu[off + k] = muv;
@@ -602,8 +658,80 @@ __device__ __forceinline__ double wave_sum_comp(double s, double c) {
   return s + c;
 }
 
-__global__ void __launch_bounds__(64) k_fix(KArgs A) {
-  const int lane = threadIdx.x;
+// Block-wide sums over FIXT threads (4 waves) in a fixed order; every thread
+// receives the total.
+constexpr int FIXT = 256;
+__device__ __forceinline__ double block_sum(double v, double* sm) {
+  v = wave_sum(v);
+  const int wv = threadIdx.x / WAVE;
+  __syncthreads();
+  if (threadIdx.x % WAVE == 0) sm[wv] = v;
+  __syncthreads();
+  return (sm[0] + sm[1]) + (sm[2] + sm[3]);
+}
+__device__ __forceinline__ double block_min(double v, double* sm) {
+  v = wave_min(v);
+  const int wv = threadIdx.x / WAVE;
+  __syncthreads();
+  if (threadIdx.x % WAVE == 0) sm[wv] = v;
+  __syncthreads();
+  return fmin(fmin(sm[0], sm[1]), fmin(sm[2], sm[3]));
+}
+__device__ __forceinline__ dd block_sum_same(dd a, double* sm) {
+  a = wave_sum_same(a);
+  const int wv = threadIdx.x / WAVE;
+  __syncthreads();
+  if (threadIdx.x % WAVE == 0) {
+    sm[wv] = a.hi;
+    sm[4 + wv] = a.lo;
+  }
+  __syncthreads();
+  dd r = dd_add_same(dd{sm[0], sm[4]}, dd{sm[1], sm[5]});
+  r = dd_add_same(r, dd{sm[2], sm[6]});
+  return dd_add_same(r, dd{sm[3], sm[7]});
+}
+__device__ __forceinline__ dd block_sum_dd(dd a, double* sm) {
+  a = wave_sum_dd(a);
+  const int wv = threadIdx.x / WAVE;
+  __syncthreads();
+  if (threadIdx.x % WAVE == 0) {
+    sm[wv] = a.hi;
+    sm[4 + wv] = a.lo;
+  }
+  __syncthreads();
+  dd r = dd_add(dd{sm[0], sm[4]}, dd{sm[1], sm[5]});
+  r = dd_add(r, dd{sm[2], sm[6]});
+  return dd_add(r, dd{sm[3], sm[7]});
+}
+__device__ __forceinline__ double block_sum_comp(double s, double c, double* sm) {
+  // Neumaier partials: wave butterflies, then the four wave results in order
+  for (int o = 32; o > 0; o >>= 1) {
+    double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
+    dd t = two_sum(s, s2);
+    s = t.hi;
+    c = c + c2 + t.lo;
+  }
+  const int wv = threadIdx.x / WAVE;
+  __syncthreads();
+  if (threadIdx.x % WAVE == 0) {
+    sm[wv] = s;
+    sm[4 + wv] = c;
+  }
+  __syncthreads();
+  double S = sm[0], C = sm[4];
+  for (int w = 1; w < 4; ++w) {
+    dd t = two_sum(S, sm[w]);
+    S = t.hi;
+    C += sm[4 + w] + t.lo;
+  }
+  return S + C;
+}
+
+// One block of FIXT threads per flagged eigenpair; the inner index is strided
+// over the block and every pass ends in a block-wide sum.
+__global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
+  __shared__ double sm[8];
+  const int tid = threadIdx.x;
   const int cnt = A.ctr[0];
   for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
     const FixItem it = A.fix[e];
@@ -640,7 +768,7 @@ __global__ void __launch_bounds__(64) k_fix(KArgs A) {
       for (int pit = 0; pit < 48; ++pit) {
         dd acc = {0.0, 0.0};
         double sp = 0.0;
-        for (int j = lane; j < n; j += WAVE) {
+        for (int j = tid; j < n; j += FIXT) {
           if (j == i) continue;
           double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
           dd dl = two_sum(s * dj, -s * sigma);                   // delta'_j exactly
@@ -650,8 +778,8 @@ __global__ void __launch_bounds__(64) k_fix(KArgs A) {
           acc = dd_add_same(acc, t);
           sp += z2 / (pp.hi * pp.hi);
         }
-        acc = wave_sum_same(acc);
-        sp = wave_sum(sp);
+        acc = block_sum_same(acc, sm);
+        sp = block_sum(sp, sm);
         dd Sdd = dd_div(acc, zi2d);
         dd gd = dd_add(dd_add(bdd, dd{-cur, 0.0}), Sdd);
         double Spz = sp / zi2;
@@ -689,7 +817,7 @@ __global__ void __launch_bounds__(64) k_fix(KArgs A) {
       // eq. (gamma): f(0) = 1 + rho z^T D^{-1} z in double-double
       dd f0 = {0.0, 0.0};
       double uu = 0.0, dmin = INFINITY;
-      for (int j = lane; j < n; j += WAVE) {
+      for (int j = tid; j < n; j += FIXT) {
         double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
         dd t = dd_div(dd{z2, Zl[j]}, dd{dj, 0.0});
         f0 = dd_add(f0, t);
@@ -697,9 +825,9 @@ __global__ void __launch_bounds__(64) k_fix(KArgs A) {
         uu += u * u;
         dmin = fmin(dmin, fabs(dj));
       }
-      f0 = wave_sum_dd(f0);
-      uu = wave_sum(uu);
-      dmin = wave_min(dmin);
+      f0 = block_sum_dd(f0, sm);
+      uu = block_sum(uu, sm);
+      dmin = block_min(dmin, sm);
       f0 = dd_add(dd{1.0, 0.0}, dd_mul_d(f0, rho));
       double f0d = f0.hi + f0.lo;
       if (f0d == 0.0) {
@@ -720,17 +848,17 @@ __global__ void __launch_bounds__(64) k_fix(KArgs A) {
         for (int hit = 0; hit < 200 && !adjacent(lo, hi); ++hit) {
           double m = fmid(lo, hi);
           double acc = 0.0;
-          for (int j = lane; j < n; j += WAVE) {
+          for (int j = tid; j < n; j += FIXT) {
             double dt = sh * Z2[2 * j], z2 = Z2[2 * j + 1];
             acc += z2 / (dt * __builtin_fma(-m, dt, 1.0));
           }
-          acc = wave_sum(acc);
+          acc = block_sum(acc, sm);
           double hv = 1.0 + gt * acc;
           if (hv < 0) lo = m; else hi = m;
         }
         const double e0 = hi;
         double cs = 0.0, cc = 0.0, sp = 0.0;
-        for (int j = lane; j < n; j += WAVE) {
+        for (int j = tid; j < n; j += FIXT) {
           double dt = sh * Z2[2 * j], z2 = Z2[2 * j + 1];
           double om = __builtin_fma(-e0, dt, 1.0);
           double t = z2 / (dt * om);
@@ -739,8 +867,8 @@ __global__ void __launch_bounds__(64) k_fix(KArgs A) {
           cs = y;
           sp += z2 / (om * om);
         }
-        double S = wave_sum_comp(cs, cc);
-        sp = wave_sum(sp);
+        double S = block_sum_comp(cs, cc, sm);
+        sp = block_sum(sp, sm);
         double hv = 1.0 + gt * S;
         double hp = gt * sp;
         double e1 = e0 - hv / hp;
@@ -751,14 +879,14 @@ __global__ void __launch_bounds__(64) k_fix(KArgs A) {
     double xsv = 0.0;
     if (polished && A.want_v) {
       double acc = 0.0;
-      for (int j = lane; j < n; j += WAVE) {
+      for (int j = tid; j < n; j += FIXT) {
         double r = muv / ((Dv[j] - sigma) - muv);
         double z2 = Z2[2 * j + 1];
         acc = __builtin_fma(z2 * r, r, acc);
       }
-      xsv = sqrt(wave_sum(acc));
+      xsv = sqrt(block_sum(acc, sm));
     }
-    if (lane == 0) {
+    if (tid == 0) {
       A.lam[off + k] = lam;
       if (polished) {
         A.mu[off + k] = muv;
@@ -770,6 +898,7 @@ __global__ void __launch_bounds__(64) k_fix(KArgs A) {
         if (singular) atomicAdd(&A.stats[DPR1_STAT_SINGULAR], 1);
       }
     }
+    __syncthreads();
   }
 }
 
@@ -871,8 +1000,9 @@ static void fill_opts(const dpr1_opts* in, dpr1_opts* o) {
 }
 
 static int pick_split(int64_t nblocks, int64_t nmax) {
-  // enough waves for 256 CUs x 8, without slices shorter than 256 terms
-  int64_t w = (2048 + nblocks - 1) / std::max<int64_t>(nblocks, 1);
+  // enough waves for 256 CUs x 16 (4 per SIMD at this kernel's register
+  // use), without slices shorter than 256 terms
+  int64_t w = (4096 + nblocks - 1) / std::max<int64_t>(nblocks, 1);
   w = std::min<int64_t>(w, MAXW);
   while (w > 1 && nmax / w < 256) --w;
   return (int)std::max<int64_t>(w, 1);
@@ -947,8 +1077,8 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   hipLaunchKernelGGL(k_eig, dim3(grid), dim3(64 * W), red_bytes(W), st, A);
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[1], st));
-  unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 4096);
-  hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(64), 0, st, A);
+  unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048);
+  hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(FIXT), 0, st, A);
   HIPCHECK(hipGetLastError());
   int64_t nmax = n_single;
   (void)nmax;
