@@ -32,13 +32,14 @@ FLOPS_SHIFT = 4           # (d_j - d_k) - tau, zeta^2/den, add
 FLOPS_TIP = 30            # exact difference, DD quotient, DD sum
 FLOPS_ROOT_RATIONAL = 11  # per pass: delta', nu delta' - 1, q, 1/q, t, S' term (3), 2 adds
 FLOPS_ROOT_BISECT = 6     # per pass: delta', fma, mul, div, add
-FLOPS_NEWTON = 13         # compensated pass: term (6), Neumaier (4), S' term (3)
-FLOPS_NORM = 6            # (d_j - sigma) - mu, mu/den, zeta^2 r^2 (fma)
+FLOPS_NEWTON = 16         # compensated pass: term (6), Neumaier (4), S' term (3), S'' term (3)
 
 
-def flops_per_pair(root, iters_mean, with_norm):
+def flops_per_pair(root, passes_mean):
+    """Algorithmic flops per (k, j) pair done by the eigenvalue kernel (k_eig): ||x|| comes
+    from the Newton pass, so there is no separate norm pass."""
     per = FLOPS_ROOT_RATIONAL if root == 1 else FLOPS_ROOT_BISECT
-    return FLOPS_SHIFT + FLOPS_TIP + per * iters_mean + FLOPS_NEWTON + (FLOPS_NORM if with_norm else 0)
+    return FLOPS_SHIFT + FLOPS_TIP + per * passes_mean + FLOPS_NEWTON
 
 
 def log(msg):
@@ -110,7 +111,7 @@ def main():
     vec_ms = float(np.mean([e.vec_ms() for e in ev]))
     value = n / (ms_step / 1e3)
     iters_mean = st["iters_sum"] / n
-    fpp = flops_per_pair(args.root, iters_mean, True)
+    fpp = flops_per_pair(args.root, iters_mean)
     achieved = fpp * n * n / (eig_ms / 1e3) / 1e12
     vec_gbs = n * n * 8 / (vec_ms / 1e3) / 1e9
     log(f"[bench] {ms_step:.3f} ms/step, k_eig {eig_ms:.3f} ms, k_vec {vec_ms:.3f} ms ({vec_gbs:.0f} GB/s), "

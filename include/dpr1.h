@@ -66,6 +66,8 @@ extern "C" {
 #define DPR1_STAT_SINGULAR 3  /* f(0) rounded to 0: lambda set to 0         */
 #define DPR1_STAT_ITERS_MAX 4 /* most root-finder passes for one eigenvalue */
 #define DPR1_STAT_ITERS_SUM 5 /* root-finder passes summed over eigenvalues */
+#define DPR1_STAT_CONTINUED 6 /* rational iterations finished by the
+                                 cooperative kernel after the pass budget   */
 #define DPR1_NSTATS 8
 
 /* Options.  dpr1_default_opts fills the defaults noted below.               */
@@ -84,6 +86,10 @@ typedef struct dpr1_opts {
   double nearzero;     /* near-zero rule factor: recompute lambda from
                           A^{-1} when factor*|lambda| < distance to the
                           neighbouring poles; default 10, 0 disables        */
+  int32_t main_passes; /* rational solver: passes the eigenvalue kernel runs
+                          before it hands an unconverged eigenpair to the
+                          cooperative kernel; 0 = default (4)              */
+  int32_t reserved;
   void* events;        /* profiling hook, NULL (default) = off: a host array
                           of 4 hipEvent_t that the solve records on `stream`
                           right before and after the eigenvalue kernel

@@ -51,11 +51,16 @@ struct Meta {
   double zz;     // sum zeta_j^2
 };
 
-enum : int32_t { FIX_POLISH = 1, FIX_NEARZERO = 2 };
+enum : int32_t { FIX_POLISH = 1, FIX_NEARZERO = 2, FIX_CONTINUE = 4 };
 
+// A flagged eigenpair: polish, near-zero rule, or a rational iteration still
+// running when the eigenvalue kernel reached its pass budget (then cnu, cL,
+// cU, cprev, iters hold the iteration's state).
 struct FixItem {
   int32_t p, k, i, flags;
+  int32_t iters, pad;
   double nu0, nu1, bhi, blo, lo, hi;
+  double cnu, cL, cU, cprev;
 };
 
 struct KArgs {
@@ -75,6 +80,7 @@ struct KArgs {
   int32_t nitems;
   int32_t W;
   int32_t mode_b, root, polish, want_v;
+  int32_t main_passes;
   double kappa_polish, nearzero;
 };
 
@@ -249,6 +255,58 @@ __global__ void k_zero(int32_t* __restrict__ a, int n) {
 }
 
 // ------------------------------------------------------------------- eig
+// One step of the safeguarded rational iteration for the rightmost root of
+// g(t) = b' - t + S(t)/zeta_i^2 from its value g and the sum term's value Sz
+// and slope -Spz at m (the bracket [L, U] already updated with the sign of g):
+// the sum term is modelled by A/(t - xm) + B with the same value and slope;
+// all poles of S lie left of the model pole xm, so the model lies above S and
+// its root never undershoots: after the first step the iterates descend
+// monotonically.  A model root outside (L, U) is replaced by the bit midpoint.
+__device__ __forceinline__ void rational_step(double m, double g, double Sz, double Spz, double bp, double xm,
+                                              int iters, double L, double U, double& nu, double& nu0,
+                                              double& prevstep, bool& done) {
+  if (g == 0.0) {
+    done = true;
+    nu0 = m;
+    return;
+  }
+  double x = m - xm;
+  double Am = Spz * x * x;
+  double Bm = Sz - Spz * x;
+  double C = (bp + Bm) - xm;
+  double disc = sqrt(C * C + 4.0 * Am);
+  double u = C >= 0 ? (C + disc) * 0.5 : (2.0 * Am) / (disc - C);
+  double nn = xm + u;
+  double step = fabs(nn - m);
+  // Quadratic convergence: a step below 2^-26 leaves nn within about 2^-52
+  // of the root and the compensated Newton step that follows finishes the
+  // job; smaller steps would only chase the rounding noise of g.
+  if (step <= 0x1p-26 * m) {
+    done = true;
+    nu0 = (nn >= L && nn <= U) ? nn : m;
+    return;
+  }
+  if (!(nn > L && nn < U)) {
+    if (adjacent(L, U)) {
+      done = true;
+      nu0 = U;
+      return;
+    }
+    nn = fmid(L, U);
+  } else if (iters >= 8 && step > 0.5 * prevstep) {
+    done = true;  // rounding noise dominates g: leave it to the checks after
+    nu0 = nn;
+    return;
+  }
+  if (iters >= 40) {
+    done = true;
+    nu0 = nn;
+    return;
+  }
+  prevstep = fabs(nn - m);
+  nu = nn;
+}
+
 // One block of 64 eigenvalues (k0 .. k0+63) of problem p, W waves.
 __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   const int W = A.W;
@@ -437,26 +495,30 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     // the linear part b' - t is the next iterate.  Since all poles of S lie
     // left of the model pole, the model lies above S, so the iterates come
     // down monotonically onto the root after the first step.
+    const int budget = A.main_passes;
+    int passes = 0;
     while (wave_any(!done)) {
+      if (passes >= budget) break;  // the rest continue in the cooperative kernel
       double m = nu;
       double S[2] = {0.0, 0.0};
       if (wave_any(!done && !pre)) {
-      sweep(j0, j1, wlo, whi, [&](int j, int seg) {
-        double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
-        double dl = __builtin_fma(s, dj, nss);
-        double pp = __builtin_fma(m, dl, -1.0);
-        double rq = rcp_1nr(dl * pp);
-        double t = z2 * rq;
-        double tp = (t * dl) * (dl * rq);  // zeta_j^2/pp^2
-        if (seg == 1 && j == i) {
-          t = 0.0;
-          tp = 0.0;
-        }
-        S[0] += t;
-        S[1] += tp;
-      });
-      wg_sum<2>(S, W, wv, lane, red);
-      ++iters;
+        sweep(j0, j1, wlo, whi, [&](int j, int seg) {
+          double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+          double dl = __builtin_fma(s, dj, nss);
+          double pp = __builtin_fma(m, dl, -1.0);
+          double rq = rcp_1nr(dl * pp);
+          double t = z2 * rq;
+          double tp = (t * dl) * (dl * rq);  // zeta_j^2/pp^2
+          if (seg == 1 && j == i) {
+            t = 0.0;
+            tp = 0.0;
+          }
+          S[0] += t;
+          S[1] += tp;
+        });
+        wg_sum<2>(S, W, wv, lane, red);
+        ++iters;
+        ++passes;
       }
       if (!done) {
         double Sz = S[0] * rz2;
@@ -470,48 +532,11 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
         } else {
           if (g > 0) L = m; else U = m;
         }
-        if (g == 0.0) {
-          done = true;
-          nu0 = m;
-        } else {
-          double x = m - xm;
-          double Am = Spz * x * x;
-          double Bm = Sz - Spz * x;
-          double C = (bp + Bm) - xm;
-          double disc = sqrt(C * C + 4.0 * Am);
-          double u = C >= 0 ? (C + disc) * 0.5 : (2.0 * Am) / (disc - C);
-          double nn = xm + u;
-          double step = fabs(nn - m);
-          // Quadratic convergence: a step below 2^-26 leaves nn within about
-          // 2^-52 of the root, and the compensated Newton step that follows
-          // finishes the job; waiting for smaller steps would only chase the
-          // rounding noise of g (about kappa_g sqrt(n) eps).
-          if (step <= 0x1p-26 * m) {
-            done = true;
-            nu0 = (nn >= L && nn <= U) ? nn : m;
-          } else if (!(nn > L && nn < U)) {
-            if (adjacent(L, U)) {
-              done = true;
-              nu0 = U;
-            } else {
-              nn = fmid(L, U);  // safeguard: bisect in the order of the numbers
-            }
-          } else if (iters >= 8 && step > 0.5 * prevstep) {
-            done = true;  // rounding noise dominates g: leave it to the checks below
-            nu0 = nn;
-          }
-          if (!done) {
-            if (iters >= 40) {
-              done = true;
-              nu0 = nn;
-            }
-            prevstep = fabs(nn - m);
-            nu = nn;
-          }
-        }
+        rational_step(m, g, Sz, Spz, bp, xm, iters, L, U, nu, nu0, prevstep, done);
       }
     }
   }
+  const bool cont = valid && !done;  // unfinished: continued in k_fix
 
   // ---- one Newton step with a compensated sum, and the amplification
   // estimate kappa_g = (|b| + |nu| + S)/(|nu| |g'|).
@@ -553,9 +578,9 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   double lam = sigma + muv;
   double amp = fabs(muv / lam);
   if (!(amp > 1.0)) amp = 1.0;
-  const bool pol = valid && A.polish && (kap * amp > A.kappa_polish);
+  const bool pol = valid && !cont && A.polish && (kap * amp > A.kappa_polish);
   bool nz = false;
-  if (valid && !pol && A.nearzero > 0) {
+  if (valid && !cont && !pol && A.nearzero > 0) {
     double gap = fabs(lam - dk);
     if (kk > 0) gap = fmin(gap, fabs(lam - dkm1));
     nz = A.nearzero * fabs(lam) < gap;
@@ -572,19 +597,25 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     A.mu[off + k] = muv;
     A.xs[off + k] = sqrt(Nx[0]);
     A.lam[off + k] = lam;
-    if (pol || nz) {
+    if (pol || nz || cont) {
       int e = atomicAdd(&A.ctr[0], 1);
       FixItem it;
       it.p = p;
       it.k = k;
       it.i = i;
-      it.flags = (pol ? FIX_POLISH : 0) | (nz ? FIX_NEARZERO : 0);
+      it.flags = (pol ? FIX_POLISH : 0) | (nz ? FIX_NEARZERO : 0) | (cont ? FIX_CONTINUE : 0);
+      it.iters = iters;
+      it.pad = 0;
       it.nu0 = nu0;
       it.nu1 = nu1;
       it.bhi = bp;
       it.blo = s * bl;
       it.lo = L0;
       it.hi = U0;
+      it.cnu = nu;
+      it.cL = L;
+      it.cU = U;
+      it.cprev = prevstep;
       A.fix[e] = it;
     }
   }
@@ -752,18 +783,91 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
     double muv = A.mu[off + k];
     double lam = A.lam[off + k];
     bool nz = (it.flags & FIX_NEARZERO) != 0;
+    bool pol = (it.flags & FIX_POLISH) != 0;
     bool polished = false;
     int singular = 0;
+    double nu0 = it.nu0, nu1 = it.nu1;
+    double xsv = 0.0;
+    bool have_xs = false;
 
-    if (it.flags & FIX_POLISH) {
+    if (it.flags & FIX_CONTINUE) {
+      // the rational iteration, continued with block-wide sums
+      const double xm = (k > 0) ? 1.0 / (Dv[k - 1] - Dv[k]) : 0.0;
+      const double bp = it.bhi, rz2 = 1.0 / zi2;
+      double nu = it.cnu, L = it.cL, U = it.cU, prevstep = it.cprev;
+      int iters = it.iters;
+      bool done = false;
+      while (!done) {
+        const double m = nu;
+        double S = 0.0, Sq = 0.0;
+        for (int j = tid; j < n; j += FIXT) {
+          if (j == i) continue;
+          double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
+          double dl = __builtin_fma(s, dj, -s * sigma);
+          double pp = __builtin_fma(m, dl, -1.0);
+          double rq = rcp_1nr(dl * pp);
+          double t = z2 * rq;
+          S += t;
+          Sq += (t * dl) * (dl * rq);
+        }
+        S = block_sum(S, sm);
+        Sq = block_sum(Sq, sm);
+        ++iters;
+        double Sz = S * rz2, Spz = Sq * rz2;
+        double g = (bp - m) + Sz;
+        if (g > 0) L = m; else U = m;
+        rational_step(m, g, Sz, Spz, bp, xm, iters, L, U, nu, nu0, prevstep, done);
+      }
+      // compensated Newton step, kappa_g and ||x|| as in the eigenvalue kernel
+      double cs = 0.0, cc = 0.0, sp = 0.0, sp3 = 0.0;
+      for (int j = tid; j < n; j += FIXT) {
+        if (j == i) continue;
+        double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
+        double dl = __builtin_fma(s, dj, -s * sigma);
+        double pp = __builtin_fma(nu0, dl, -1.0);
+        double q = dl * pp;
+        double r = rcp_nr(q);
+        double t = z2 * r;
+        t = __builtin_fma(__builtin_fma(-t, q, z2), r, t);
+        double ir = dl * r;
+        double tp = (t * dl) * ir;
+        double y = cs + t;
+        cc += (fabs(cs) >= fabs(t)) ? ((cs - y) + t) : ((t - y) + cs);
+        cs = y;
+        sp += tp;
+        sp3 += (tp * ir) * dl;
+      }
+      double S = block_sum_comp(cs, cc, sm);
+      sp = block_sum(sp, sm);
+      sp3 = block_sum(sp3, sm);
+      const double Sz = S / zi2;
+      const double g = (bp - nu0) + Sz;
+      const double gp = -1.0 - sp / zi2;
+      nu1 = nu0 - g / gp;
+      const double kap = (fabs(bp) + nu0 + Sz) / (nu0 * fabs(gp));
+      muv = s / nu1;
+      lam = sigma + muv;
+      double amp = fabs(muv / lam);
+      if (!(amp > 1.0)) amp = 1.0;
+      pol = A.polish && (kap * amp > A.kappa_polish);
+      if (!pol && A.nearzero > 0) {
+        double gap = fabs(lam - Dv[k]);
+        if (k > 0) gap = fmin(gap, fabs(lam - Dv[k - 1]));
+        nz = A.nearzero * fabs(lam) < gap;
+      }
+      xsv = sqrt(zi2 + (sp - 2.0 * (nu1 - nu0) * sp3));
+      have_xs = true;
+    }
+
+    if (pol) {
       // Safeguarded iteration with g evaluated in double-double: far from the
       // root the rational model step of the main solver, close to it Newton
       // (g exact to ~2^-100, so the last step lands on the rounded root).
       const dd bdd = {it.bhi, it.blo};
       const double xm = (k > 0) ? 1.0 / (Dv[k - 1] - Dv[k]) : 0.0;
       double lo = it.lo, hi = it.hi;
-      double cur = it.nu1;
-      if (!(cur > lo && cur < hi)) cur = it.nu0;
+      double cur = nu1;
+      if (!(cur > lo && cur < hi)) cur = nu0;
       if (!(cur > lo && cur < hi)) cur = fmid(lo, hi);
       for (int pit = 0; pit < 48; ++pit) {
         dd acc = {0.0, 0.0};
@@ -876,7 +980,6 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
       }
     }
 
-    double xsv = 0.0;
     if (polished && A.want_v) {
       double acc = 0.0;
       for (int j = tid; j < n; j += FIXT) {
@@ -888,12 +991,13 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
     }
     if (tid == 0) {
       A.lam[off + k] = lam;
-      if (polished) {
+      if (polished || have_xs) {
         A.mu[off + k] = muv;
         if (A.want_v) A.xs[off + k] = xsv;
       }
       if (A.stats) {
         if (polished) atomicAdd(&A.stats[DPR1_STAT_POLISHED], 1);
+        if (it.flags & FIX_CONTINUE) atomicAdd(&A.stats[DPR1_STAT_CONTINUED], 1);
         if (nz) atomicAdd(&A.stats[DPR1_STAT_NEARZERO], 1);
         if (singular) atomicAdd(&A.stats[DPR1_STAT_SINGULAR], 1);
       }
@@ -1023,6 +1127,8 @@ void dpr1_default_opts(dpr1_opts* o) {
   o->split = 0;
   o->kappa_polish = 16.0;
   o->nearzero = 10.0;
+  o->main_passes = 0;
+  o->reserved = 0;
   o->events = nullptr;
 }
 
@@ -1064,6 +1170,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   A.want_v = V != nullptr;
   A.kappa_polish = o.kappa_polish;
   A.nearzero = o.nearzero;
+  A.main_passes = o.main_passes > 0 ? o.main_passes : 4;
 
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, A.ctr, 16);
   if (stats) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, stats, DPR1_NSTATS);

@@ -19,13 +19,13 @@ LIB_PATH = os.path.join(HERE, "libdpr1.so")
 INFO_TEXT = {0: "ok", 1: "d is not strictly decreasing", 2: "some z_j is zero (reducible)",
              3: "non-finite input", 4: "rho is zero or not finite"}
 NSTATS = 8
-STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "iters_sum", "r6", "r7"]
+STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "iters_sum", "continued", "r7"]
 
 
 class Opts(C.Structure):
     _fields_ = [("mode_b", C.c_int32), ("root", C.c_int32), ("polish", C.c_int32),
                 ("split", C.c_int32), ("kappa_polish", C.c_double), ("nearzero", C.c_double),
-                ("events", C.c_void_p)]
+                ("main_passes", C.c_int32), ("reserved", C.c_int32), ("events", C.c_void_p)]
 
 
 class Plan(C.Structure):
@@ -65,8 +65,9 @@ def lib():
     return _lib
 
 
-def opts(mode_b=0, root=1, polish=1, split=0, kappa_polish=16.0, nearzero=10.0, events=None) -> Opts:
-    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, events)
+def opts(mode_b=0, root=1, polish=1, split=0, kappa_polish=16.0, nearzero=10.0, main_passes=0,
+         events=None) -> Opts:
+    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, main_passes, 0, events)
 
 
 class HipEvents:
