@@ -141,7 +141,7 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
  *   voffs [nprob] are device arrays (the same offsets as planned; voffs may be
  *   NULL when V is NULL); rho is a device array [nprob]; info is [nprob].   */
 typedef struct dpr1_plan {
-  int64_t nprob, ntotal, nitems, nmax;
+  int64_t nprob, ntotal, nitems, nmax, ngroups;
   int32_t split, grid;
   dpr1_opts opts;
 } dpr1_plan;

@@ -173,16 +173,21 @@ __device__ __forceinline__ void wg_sum_dd(dd& a, int W, int wv, int lane, double
 // j < i), inside it (seg 1: per-lane test), above it (seg 2: every lane has
 // j > i).  j is wave-uniform in all three loops.
 template <class F>
-__device__ __forceinline__ void sweep(int j0, int j1, int wlo, int whi, F&& f) {
+__device__ __forceinline__ void sweep(const double* P, int j0, int j1, int wlo, int whi, F&& f) {
+  // q walks the (d_j, zeta_j^2) pairs so that the unrolled loads share one
+  // base address with immediate offsets
   int a = j0, b = min(j1, wlo);
-#pragma unroll 4
-  for (int j = a; j < b; ++j) f(j, 0);
+  const double* q = P + 2 * (int64_t)a;
+#pragma unroll 8
+  for (int j = a; j < b; ++j, q += 2) f(j, 0, q);
   a = max(j0, wlo);
   b = min(j1, whi);
-  for (int j = a; j < b; ++j) f(j, 1);
+  q = P + 2 * (int64_t)a;
+  for (int j = a; j < b; ++j, q += 2) f(j, 1, q);
   a = max(j0, whi);
-#pragma unroll 4
-  for (int j = a; j < j1; ++j) f(j, 2);
+  q = P + 2 * (int64_t)a;
+#pragma unroll 8
+  for (int j = a; j < j1; ++j, q += 2) f(j, 2, q);
 }
 
 // ------------------------------------------------------------------ prep
@@ -353,8 +358,8 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // midpoint is the first probe of the root finder, so its evaluation is reused.
   const double tau = (dkm1 - dk) / 2;
   double Fs[3] = {0.0, 0.0, 0.0};
-  sweep(j0, j1, wlo, whi, [&](int j, int) {
-    double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+  sweep(P, j0, j1, wlo, whi, [&](int j, int, const double* pq) {
+    double dj = ldu(pq, 0), z2 = ldu(pq, 1);
     double r = rcp_1nr((dj - dk) - tau);
     double t = z2 * r;
     Fs[0] += t;
@@ -382,8 +387,8 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     t.lo += a.lo + q2;
     a = fast_two_sum(t.hi, t.lo);
   };
-  sweep(j0, j1, wlo, whi, [&](int j, int seg) {
-    double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1), z2l = ldu(Zl, j);
+  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
+    double dj = ldu(pq, 0), z2 = ldu(pq, 1), z2l = ldu(Zl, j);
     dd dl = two_sum(dj, -sigma);  // exact d_j - sigma
     double r = rcp_1nr(dl.hi);
     double q1 = z2 * r;
@@ -461,8 +466,8 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double m = nu;
       double S[1] = {0.0};
       if (wave_any(!done && !pre)) {
-        sweep(j0, j1, wlo, whi, [&](int j, int seg) {
-          double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
+          double dj = ldu(pq, 0), z2 = ldu(pq, 1);
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
           double t = z2 * rcp_1nr(dl * pp);
@@ -502,8 +507,8 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double m = nu;
       double S[2] = {0.0, 0.0};
       if (wave_any(!done && !pre)) {
-        sweep(j0, j1, wlo, whi, [&](int j, int seg) {
-          double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
+          double dj = ldu(pq, 0), z2 = ldu(pq, 1);
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
           double rq = rcp_1nr(dl * pp);
@@ -544,8 +549,8 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   double Sp[2] = {0.0, 0.0};
   {
     const double m = nu0;
-    sweep(j0, j1, wlo, whi, [&](int j, int seg) {
-      double dj = ldu(P, 2 * j), z2 = ldu(P, 2 * j + 1);
+    sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
+      double dj = ldu(pq, 0), z2 = ldu(pq, 1);
       double dl = __builtin_fma(s, dj, nss);
       double pp = __builtin_fma(m, dl, -1.0);
       double q = dl * pp;
@@ -1029,53 +1034,87 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
 }
 
 // ------------------------------------------------------------------- vec
-// v_j = zeta_j r_j / (|mu| ||x||), r_j = mu/(delta_j - mu): one block per
-// column, consecutive threads on consecutive rows.
-__global__ void __launch_bounds__(256) k_vec(const Meta* __restrict__ meta, int nprob, int64_t ncols,
-                                             const double* __restrict__ sd, const double* __restrict__ sz,
-                                             const int32_t* __restrict__ ii, const double* __restrict__ mu,
-                                             const double* __restrict__ xs, double* __restrict__ V,
-                                             const int64_t* __restrict__ voffs, int64_t ldv) {
-  for (int64_t c = blockIdx.x; c < ncols; c += gridDim.x) {
-    int p = 0;
-    if (nprob > 1) {
-      int lo = 0, hi = nprob - 1;  // last problem with off <= c
-      while (lo < hi) {
-        int mid = (lo + hi + 1) / 2;
-        if (meta[mid].off <= c) lo = mid; else hi = mid - 1;
+// v_j = zeta_j r_j / (|mu| ||x||), r_j = mu/(delta_j - mu).  A block owns a
+// segment of up to VEC_ROWS rows of VEC_C columns of one problem: every
+// thread keeps the (d_j, zeta_j) of its VEC_R rows in registers and the block
+// writes the columns one after the other, each segment contiguous (consecutive
+// threads on consecutive rows, non-temporal stores).
+constexpr int VEC_C = 8;
+constexpr int VEC_T = 256;
+constexpr int VEC_R = 16;
+constexpr int VEC_ROWS = VEC_T * VEC_R;
+
+__global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, const int2* __restrict__ groups,
+                                               int64_t ncolgroups, const double* __restrict__ sd,
+                                               const double* __restrict__ sz, const int32_t* __restrict__ ii,
+                                               const double* __restrict__ mu, const double* __restrict__ xs,
+                                               double* __restrict__ V, const int64_t* __restrict__ voffs,
+                                               int64_t ldv) {
+  __shared__ double csig[VEC_C], cmu[VEC_C], cinv[VEC_C];
+  int p, c0;
+  int64_t r0;
+  if (groups) {
+    int2 g = groups[blockIdx.x];  // batched: (problem, first column), rows from 0
+    p = g.x;
+    c0 = g.y;
+    r0 = 0;
+  } else {
+    p = 0;
+    c0 = (int)(blockIdx.x % ncolgroups) * VEC_C;
+    r0 = (int64_t)(blockIdx.x / ncolgroups) * VEC_ROWS;
+  }
+  const Meta M = meta[p];
+  if (M.info != 0) return;
+  const int n = M.n;
+  const int nc = min(VEC_C, n - c0);
+  if (threadIdx.x < VEC_C) {
+    int c = threadIdx.x;
+    if (c < nc) {
+      int64_t a = M.off + c0 + c;
+      double m = mu[a];
+      csig[c] = sd[M.off + ii[a]];
+      cmu[c] = m;
+      cinv[c] = 1.0 / copysign(xs[a], m);  // v = x/||x|| = zeta r/(sign(mu) |mu| ||x||)
+    }
+  }
+  __syncthreads();
+  const int64_t ld = voffs ? (int64_t)n : ldv;
+  const int64_t base = voffs ? voffs[p] : 0;
+  const double sg = M.neg ? -1.0 : 1.0;
+  for (int64_t rb = r0; rb < n; rb += VEC_ROWS) {
+    double dj[VEC_R], zj[VEC_R];
+#pragma unroll
+    for (int r = 0; r < VEC_R; ++r) {
+      int64_t j = rb + threadIdx.x + (int64_t)r * VEC_T;
+      dj[r] = j < n ? sd[M.off + j] : 0.0;
+      zj[r] = j < n ? sg * sz[M.off + j] : 0.0;
+    }
+    for (int c = 0; c < nc; ++c) {
+      const double m = cmu[c], sc = csig[c], iv = cinv[c];
+      const int ko = M.neg ? n - 1 - (c0 + c) : c0 + c;
+      double* col = V + base + (int64_t)ko * ld;
+#pragma unroll
+      for (int r = 0; r < VEC_R; ++r) {
+        int64_t j = rb + threadIdx.x + (int64_t)r * VEC_T;
+        const double den = (dj[r] - sc) - m;
+        double q = m * rcp_nr(den);
+        q = __builtin_fma(__builtin_fma(-q, den, m), rcp_1nr(den), q);  // corrected quotient
+        const double v = (zj[r] * q) * iv;
+        if (j < n) __builtin_nontemporal_store(v, &col[M.neg ? n - 1 - j : j]);
       }
-      p = lo;
     }
-    const Meta M = meta[p];
-    if (M.info != 0) continue;
-    const int n = M.n;
-    const int k = (int)(c - M.off);
-    const double sigma = sd[M.off + ii[c]];
-    const double m = mu[c];
-    const double inv = 1.0 / copysign(xs[c], m);  // v = x/||x|| = zeta r/(sign(mu) |mu| ||x||)
-    const int64_t ld = voffs ? (int64_t)n : ldv;
-    const int64_t base = voffs ? voffs[p] : 0;
-    const int ko = M.neg ? n - 1 - k : k;
-    const double sg = M.neg ? -1.0 : 1.0;
-    double* col = V + base + (int64_t)ko * ld;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      double dj = sd[M.off + j], zj = sz[M.off + j];
-      double r = m / ((dj - sigma) - m);
-      double v = sg * (zj * r) * inv;
-      int jo = M.neg ? n - 1 - j : j;
-      __builtin_nontemporal_store(v, &col[jo]);
-    }
+    if (groups == nullptr) break;  // single problem: one row segment per block
   }
 }
 
 // ===================================================================== host
 struct Layout {
-  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, fix, items, ctr, total;
+  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, fix, items, groups, ctr, total;
 };
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-static Layout layout(int64_t nprob, int64_t N, int64_t nitems) {
+static Layout layout(int64_t nprob, int64_t N, int64_t nitems, int64_t ngroups = 0) {
   Layout L;
   size_t o = 0;
   L.meta = o; o = al(o + sizeof(Meta) * nprob);
@@ -1089,6 +1128,7 @@ static Layout layout(int64_t nprob, int64_t N, int64_t nitems) {
   L.lam = o; o = al(o + 8 * N);
   L.fix = o; o = al(o + sizeof(FixItem) * N);
   L.items = o; o = al(o + sizeof(int2) * nitems);
+  L.groups = o; o = al(o + sizeof(int2) * ngroups);
   L.ctr = o; o = al(o + 64);
   L.total = o;
   return L;
@@ -1146,7 +1186,8 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
                         int64_t n_single, const double* d, const double* z, const double* rho_dev,
                         double rho_host, double* lambda, double* V, const int64_t* voffs, int64_t ldv,
                         int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, int32_t* stats,
-                        const dpr1_opts& o, int W, int64_t nitems, int persistent_grid, hipStream_t st) {
+                        const dpr1_opts& o, int W, int64_t nitems, int persistent_grid, int64_t ngroups,
+                        hipStream_t st) {
   Meta* meta = (Meta*)(w + L.meta);
   KArgs A;
   A.meta = meta;
@@ -1194,10 +1235,15 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
                      xnorm);
   HIPCHECK(hipGetLastError());
   if (V) {
-    unsigned vgrid = (unsigned)std::min<int64_t>(N, 1 << 20);
     if (ev) HIPCHECK(hipEventRecord(ev[2], st));
-    hipLaunchKernelGGL(k_vec, dim3(vgrid), dim3(256), 0, st, meta, (int)nprob, N, A.sd, A.sz, A.ii, A.mu,
-                       A.xs, V, voffs, ldv);
+    if (persistent_grid) {
+      hipLaunchKernelGGL(k_vec, dim3((unsigned)ngroups), dim3(VEC_T), 0, st, meta, (const int2*)(w + L.groups),
+                         ngroups, A.sd, A.sz, A.ii, A.mu, A.xs, V, voffs, ldv);
+    } else {
+      int64_t cg = (N + VEC_C - 1) / VEC_C, rt = (N + VEC_ROWS - 1) / VEC_ROWS;
+      hipLaunchKernelGGL(k_vec, dim3((unsigned)(cg * rt)), dim3(VEC_T), 0, st, meta, (const int2*)nullptr, cg,
+                         A.sd, A.sz, A.ii, A.mu, A.xs, V, voffs, ldv);
+    }
     HIPCHECK(hipGetLastError());
     if (ev) HIPCHECK(hipEventRecord(ev[3], st));
   }
@@ -1222,14 +1268,14 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
   int64_t nblocks = (n + WAVE - 1) / WAVE;
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
   return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
-                      mu, xnorm, info, stats, o, W, nblocks, 0, (hipStream_t)stream);
+                      mu, xnorm, info, stats, o, W, nblocks, 0, 0, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------ batched
 size_t dpr1_batched_workspace_size(int64_t nprob, int64_t ntotal) {
   if (nprob < 1 || ntotal < nprob) return 0;
   int64_t nitems = ntotal / WAVE + nprob;  // upper bound of sum ceil(n_p/64)
-  return layout(nprob, ntotal, nitems).total;
+  return layout(nprob, ntotal, nitems, ntotal / VEC_C + nprob).total;
 }
 
 int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* opts, dpr1_plan* plan,
@@ -1247,7 +1293,7 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   }
   int64_t N = offs_host[nprob];
   if (N > (int64_t)INT32_MAX) return -2;
-  Layout L0 = layout(nprob, N, N / WAVE + nprob);
+  Layout L0 = layout(nprob, N, N / WAVE + nprob, N / VEC_C + nprob);
   if (work_bytes < L0.total) return -6;
   dpr1_opts o;
   fill_opts(opts, &o);
@@ -1264,9 +1310,18 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   }
   int64_t nitems = (int64_t)items.size();
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nitems, nmax);
+  // column groups of the eigenvector kernel, one per (problem, VEC_C columns)
+  std::vector<int2> groups;
+  for (int32_t p : order) {
+    int64_t np = offs_host[p + 1] - offs_host[p];
+    for (int64_t c0 = 0; c0 < np; c0 += VEC_C) groups.push_back(make_int2(p, (int)c0));
+  }
   hipStream_t st = (hipStream_t)stream;
   HIPCHECK(hipMemcpyAsync((char*)work + L0.items, items.data(), sizeof(int2) * nitems, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync((char*)work + L0.groups, groups.data(), sizeof(int2) * groups.size(),
+                          hipMemcpyHostToDevice, st));
   HIPCHECK(hipStreamSynchronize(st));
+  plan->ngroups = (int64_t)groups.size();
   plan->nprob = nprob;
   plan->ntotal = N;
   plan->nitems = nitems;
@@ -1290,11 +1345,11 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
   if (V && !voffs) return -8;
   if (!info) return -12;
   if (!work) return -14;
-  Layout L = layout(plan->nprob, plan->ntotal, plan->ntotal / WAVE + plan->nprob);
+  Layout L = layout(plan->nprob, plan->ntotal, plan->ntotal / WAVE + plan->nprob, plan->ntotal / VEC_C + plan->nprob);
   if (work_bytes < L.total) return -15;
   return launch_solve(L, (char*)work, plan->nprob, plan->ntotal, offs, 0, d, z, rho, 0.0, lambda, V, voffs, 0,
                       shift_idx, mu, xnorm, info, stats, plan->opts, plan->split, plan->nitems, plan->grid,
-                      (hipStream_t)stream);
+                      plan->ngroups, (hipStream_t)stream);
 }
 
 const char* dpr1_strerror(int code) {

@@ -30,7 +30,8 @@ class Opts(C.Structure):
 
 class Plan(C.Structure):
     _fields_ = [("nprob", C.c_int64), ("ntotal", C.c_int64), ("nitems", C.c_int64),
-                ("nmax", C.c_int64), ("split", C.c_int32), ("grid", C.c_int32), ("opts", Opts)]
+                ("nmax", C.c_int64), ("ngroups", C.c_int64), ("split", C.c_int32), ("grid", C.c_int32),
+                ("opts", Opts)]
 
 
 _lib = None
