@@ -58,9 +58,19 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip batched / fwd+bwd / eigenvalues-only lines")
     ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
                     help="copy: a plain device copy of known size, to calibrate HBM byte counters")
+    ap.add_argument("--only", default=None, choices=["batched", "fwd_bwd"],
+                    help="run only this workload (for profiler runs); prints its JSON")
     args = ap.parse_args()
     if args.mode == "copy":
         return copy_calibration()
+    if args.only:
+        import torch
+        import paper_1405_7537_amd.dpr1 as D
+        from paper_1405_7537_amd import workloads as W
+        dev = torch.device("cuda:0")
+        fn = bench_batched if args.only == "batched" else bench_fwd_bwd
+        print(json.dumps(fn(D, W, torch, dev, args)), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

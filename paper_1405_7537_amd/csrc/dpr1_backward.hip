@@ -17,10 +17,10 @@
 // Kernels:
 //   k_gemm<EPI_X>  P = V^T V_bar on FP64 matrix cores, epilogue X = F o P +
 //                  diag(lambda_bar), partial sums of X y (rows) and X^T y (cols)
+//   k_bwd_u        u = (X + X^T) y and rho_bar = y^T X y from those partials
 //   k_gemm<EPI_D>  Q = V X on FP64 matrix cores, epilogue partial row sums of
-//                  Q o V (for d_bar)
-//   k_bwd_finish   reduces the partials: u = (X + X^T) y, rho_bar = y^T X y, d_bar
-//   k_bwd_zbar     z_bar = rho V u (one pass over V)
+//                  Q o V (for d_bar) and of V diag(u) (for z_bar)
+//   k_bwd_final    d_bar, z_bar = rho V u from the partials
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -32,8 +32,12 @@
 namespace dpr1 {
 namespace bwd {
 
-constexpr int BM = 64, BN = 64, BK = 16;  // block tile; 4 waves of 32 x 32
+// Block tile 128 x 128 (2 x 2 waves of 64 x 64, each 4 x 4 blocks of the
+// 16x16x4 FP64 MFMA), K staged through LDS in slices of 16, double-buffered.
+constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int NT = 256;
+constexpr int PAD = 2;   // LDS row padding (doubles)
+constexpr int NXCD = 8;  // workgroups are dealt round-robin to the 8 XCDs
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -41,9 +45,10 @@ enum { EPI_X = 0, EPI_D = 1 };
 
 struct GArgs {
   int64_t n;
+  int nb;
   const double* A;   // V (both GEMMs)
-  const double* B;   // V_bar (EPI_X) or X (EPI_D)
-  double* C;         // X (EPI_X) or unused (EPI_D)
+  const double* B;   // V_bar (EPI_X, column-major) or X (EPI_D, row-major)
+  double* C;         // X (EPI_X), stored row-major
   // EPI_X
   const double* lam_bar;  // [nb*n] or null
   const double* d;        // [nb*n]
@@ -53,165 +58,227 @@ struct GArgs {
   double* part_r;         // [nb][ntile][n]  sum_k X_lk y_k over the tile's k range
   double* part_c;         // [nb][ntile][n]  sum_l X_lk y_l over the tile's l range
   // EPI_D
-  double* part_d;         // [nb][ntile][n]
+  const double* u;        // [nb*n]  (X + X^T) y
+  double* part_d;         // [nb][ntile][n]  sum_k Q_jk V_jk
+  double* part_z;         // [nb][ntile][n]  sum_k V_jk u_k
   int has_B;              // 0: V_bar is null, P = 0
 };
 
-// One 64x64 output tile of one problem per block.  Column-major n x n
-// matrices (ld = n).  EPI_X computes op(A) = A^T (A = V), EPI_D op(A) = A.
+// Column-major n x n matrices (ld = n).  EPI_X computes op(A) = A^T (A = V),
+// EPI_D op(A) = A.  The linear block index is mapped so that all tiles of a
+// problem run on one XCD and share its L2.
 template <int EPI>
-__global__ void __launch_bounds__(NT) k_gemm(GArgs g) {
+__global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   const int64_t n = g.n;
   const int tiles = (int)((n + BM - 1) / BM);
-  const int tm = blockIdx.x % tiles;
-  const int tn = blockIdx.x / tiles;
-  const int pb = blockIdx.y;
+  const int T = tiles * tiles;
+  const int B_ = blockIdx.x;
+  const int xcd = B_ % NXCD, slot = B_ / NXCD;
+  const int t = slot % T;
+  const int pb = NXCD * (slot / T) + xcd;
+  if (pb >= g.nb) return;
+  const int tm = t % tiles, tn = t / tiles;
   const int64_t mo = (int64_t)pb * n * n;
   const double* A = g.A + mo;
-  const double* B = g.B + mo;
+  const double* Bm = g.B + mo;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
   const int wv = tid / 64, lane = tid % 64;
-  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  const int wm = (wv & 1) * 64, wn = (wv >> 1) * 64;
 
-  __shared__ double As[BK][BM + 1];  // As[kk][m] = op(A)(m0+m, k0+kk)
-  __shared__ double Bs[BK][BN + 1];  // Bs[kk][c] = B(k0+kk, n0+c)
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
 
-  double4_t acc[2][2];
+  double4_t acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  constexpr int PER = (BM * BK) / NT;  // 8 elements of each operand per thread
+  double ra[PER], rb[PER];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int e2 = 0; e2 < PER; ++e2) {
+      int e = tid + e2 * NT;
+      int m, kk;
+      if (EPI == EPI_X) {
+        kk = e % BK;   // A^T(m, k) = V[k + m n], contiguous along k
+        m = e / BK;
+        int64_t gm = m0 + m, gk = k0 + kk;
+        ra[e2] = (gm < n && gk < n) ? A[gk + gm * n] : 0.0;
+      } else {
+        m = e % BM;    // A(m, k) = V[m + k n], contiguous along m
+        kk = e / BM;
+        int64_t gm = m0 + m, gk = k0 + kk;
+        ra[e2] = (gm < n && gk < n) ? A[gm + gk * n] : 0.0;
+      }
+      if (EPI == EPI_X) {
+        int kb = e % BK, c = e / BK;  // V_bar(k, c) = V_bar[k + c n], contiguous along k
+        int64_t gk = k0 + kb, gc = n0 + c;
+        rb[e2] = (gk < n && gc < n) ? Bm[gk + gc * n] : 0.0;
+      } else {
+        int c = e % BN, kb = e / BN;  // X(k, c) = X[k n + c] (row-major), contiguous along c
+        int64_t gk = k0 + kb, gc = n0 + c;
+        rb[e2] = (gk < n && gc < n) ? Bm[gk * n + gc] : 0.0;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e2 = 0; e2 < PER; ++e2) {
+      int e = tid + e2 * NT;
+      if (EPI == EPI_X) {
+        As[buf][e % BK][e / BK] = ra[e2];
+        Bs[buf][e % BK][e / BK] = rb[e2];
+      } else {
+        As[buf][e / BM][e % BM] = ra[e2];
+        Bs[buf][e / BN][e % BN] = rb[e2];
+      }
+    }
+  };
 
   const bool doB = (EPI == EPI_D) || g.has_B;
   if (doB) {
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
     for (int64_t k0 = 0; k0 < n; k0 += BK) {
-      // stage op(A) and B tiles: 64 x 16 each, 4 elements per thread
-#pragma unroll
-      for (int t = 0; t < (BM * BK) / NT; ++t) {
-        int e = tid + t * NT;
-        int m, kk;
-        double v = 0.0;
-        if (EPI == EPI_X) {
-          kk = e % BK;   // contiguous along k: A^T(m, k) = V[k + m n]
-          m = e / BK;
-          int64_t gm = m0 + m, gk = k0 + kk;
-          if (gm < n && gk < n) v = A[gk + gm * n];
-        } else {
-          m = e % BM;    // contiguous along m: A(m, k) = V[m + k n]
-          kk = e / BM;
-          int64_t gm = m0 + m, gk = k0 + kk;
-          if (gm < n && gk < n) v = A[gm + gk * n];
-        }
-        As[kk][m] = v;
-      }
-#pragma unroll
-      for (int t = 0; t < (BN * BK) / NT; ++t) {
-        int e = tid + t * NT;
-        int kk = e % BK, c = e / BK;  // contiguous along k: B(k, c) = B[k + c n]
-        int64_t gk = k0 + kk, gc = n0 + c;
-        Bs[kk][c] = (gk < n && gc < n) ? B[gk + gc * n] : 0.0;
-      }
-      __syncthreads();
+      const bool more = k0 + BK < n;
+      if (more) gload(k0 + BK);  // next slice in flight during this one
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 4) {
-        // 16x16x4 FP64 MFMA: lane holds A(row = lane%16, k = lane/16),
+        // 16x16x4 FP64 MFMA: lane holds A(row = lane%16, k = lane/16) and
         // B(k = lane/16, col = lane%16)
         const int r = lane % 16, q = lane / 16;
-        double a0 = As[ks + q][wm + r];
-        double a1 = As[ks + q][wm + 16 + r];
-        double b0 = Bs[ks + q][wn + r];
-        double b1 = Bs[ks + q][wn + 16 + r];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        double af[4], bf[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          af[x] = As[buf][ks + q][wm + 16 * x + r];
+          bf[x] = Bs[buf][ks + q][wn + 16 * x + r];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
       }
-      __syncthreads();
+      if (more) {
+        sstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
     }
   }
 
-  // Epilogue.  Accumulator element t of a lane holds row lane/16 + 4t,
+  // Epilogue.  Accumulator element q of a lane holds row lane/16 + 4q,
   // column lane%16 of its 16x16 block (checked on gfx950 with a probe that
-  // multiplies A(:,0) = 2^i by B(0,:) = 3^j).  Per-row / per-column partial
-  // sums go through LDS.
-  __shared__ double rowp[2][BM];  // [wn half][row]
-  __shared__ double colp[2][BN];  // [wm half][col]
+  // multiplies A(:,0) = 2^i by B(0,:) = 3^j).  The per-row and per-column
+  // quantities of this tile are staged in LDS first; per-row / per-column
+  // partial sums go back through LDS.
+  __shared__ double rsig[BM], rmu[BM], ry[BM], csig[BN], cmu[BN], cy[BN], clb[BN];
+  __shared__ double rowp[2][2][BM];  // [quantity][wn half][row]
+  __shared__ double colp[2][BN];     // [wm half][col]
   const int64_t vo = (int64_t)pb * n;
-  double rsum[2][4], csum[2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) rsum[a][t] = 0.0;
-  csum[0] = csum[1] = 0.0;
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int64_t col = n0 + wn + b * 16 + lane % 16;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t row = m0 + wm + a * 16 + (lane / 16) + 4 * t;
-        if (row >= n || col >= n) continue;
-        double v = acc[a][b][t];
-        if (EPI == EPI_X) {
-          // X(row = l, col = k)
-          double x;
-          if (row == col) {
-            x = g.lam_bar ? g.lam_bar[vo + col] : 0.0;
-          } else {
-            double sk = g.d[vo + g.sidx[vo + col]], sl = g.d[vo + g.sidx[vo + row]];
-            dd gap = dd_add(two_sum(sk, -sl), two_sum(g.mu[vo + col], -g.mu[vo + row]));
-            x = v / (gap.hi + gap.lo);
-          }
-          g.C[mo + row + col * n] = x;
-          rsum[a][t] += x * g.y[vo + col];
-          csum[b] += x * g.y[vo + row];
-        } else {
-          // Q(row = j, col = k) * V(j, k)
-          rsum[a][t] += v * A[row + col * n];
-        }
+  if (tid < BM) {
+    int64_t row = m0 + tid;
+    if (row < n) {
+      if (EPI == EPI_X) {
+        rsig[tid] = g.d[vo + g.sidx[vo + row]];
+        rmu[tid] = g.mu[vo + row];
+        ry[tid] = g.y[vo + row];
+      }
+    }
+  } else {
+    int c = tid - BM;
+    int64_t col = n0 + c;
+    if (col < n) {
+      if (EPI == EPI_X) {
+        csig[c] = g.d[vo + g.sidx[vo + col]];
+        cmu[c] = g.mu[vo + col];
+        cy[c] = g.y[vo + col];
+        clb[c] = g.lam_bar ? g.lam_bar[vo + col] : 0.0;
+      } else {
+        cy[c] = g.u[vo + col];
       }
     }
   }
-  // reduce rsum over the 16 lanes sharing a row (same lane/16), csum over the
-  // 4 lane groups sharing a column (same lane%16)
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      double s = rsum[a][t];
-      for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o);
-      rsum[a][t] = s;
-    }
-  if (EPI == EPI_X) {
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      double s = csum[b];
-      s += __shfl_xor(s, 16);
-      s += __shfl_xor(s, 32);
-      csum[b] = s;
-    }
-  }
+  __syncthreads();
   const int half_n = wv >> 1, half_m = wv & 1;
-  if (lane % 16 == 0) {
+  double cs[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a) {
+    double rs1[4] = {0.0, 0.0, 0.0, 0.0}, rs2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int t = 0; t < 4; ++t) rowp[half_n][wm + a * 16 + (lane / 16) + 4 * t] = rsum[a][t];
+    for (int b = 0; b < 4; ++b) {
+      const int cl = wn + b * 16 + lane % 16;
+      const int64_t col = n0 + cl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rl = wm + a * 16 + (lane / 16) + 4 * q;
+        const int64_t row = m0 + rl;
+        if (row >= n || col >= n) continue;
+        double v = acc[a][b][q];
+        if (EPI == EPI_X) {
+          // X(row = l, col = k), stored row-major (consecutive lanes on
+          // consecutive columns)
+          double x;
+          if (row == col) {
+            x = clb[cl];
+          } else {
+            dd gap = dd_add(two_sum(csig[cl], -rsig[rl]), two_sum(cmu[cl], -rmu[rl]));
+            x = v / (gap.hi + gap.lo);
+          }
+          g.C[mo + row * n + col] = x;
+          rs1[q] += x * cy[cl];
+          cs[b] += x * ry[rl];
+        } else {
+          // Q(row = j, col = k) V(j, k) for d_bar, V(j, k) u_k for z_bar
+          double vjk = A[row + col * n];
+          rs1[q] += v * vjk;
+          rs2[q] += vjk * cy[cl];
+        }
+      }
+    }
+    // reduce over the 16 lanes sharing a row (same lane/16)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double s1 = rs1[q], s2 = rs2[q];
+      for (int o = 1; o < 16; o <<= 1) {
+        s1 += __shfl_xor(s1, o);
+        if (EPI == EPI_D) s2 += __shfl_xor(s2, o);
+      }
+      if (lane % 16 == 0) {
+        int r = wm + a * 16 + (lane / 16) + 4 * q;
+        rowp[0][half_n][r] = s1;
+        rowp[1][half_n][r] = s2;
+      }
+    }
   }
-  if (EPI == EPI_X && lane < 16) {
+  if (EPI == EPI_X) {
+    // columns: reduce over the 4 lane groups sharing a column (same lane%16)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) colp[half_m][wn + b * 16 + lane] = csum[b];
+    for (int b = 0; b < 4; ++b) {
+      double c = cs[b];
+      c += __shfl_xor(c, 16);
+      c += __shfl_xor(c, 32);
+      if (lane < 16) colp[half_m][wn + b * 16 + lane] = c;
+    }
   }
   __syncthreads();
   const int ntile = tiles;
   if (tid < BM) {
     int64_t row = m0 + tid;
     if (row < n) {
-      double s = rowp[0][tid] + rowp[1][tid];
-      double* dst = (EPI == EPI_X) ? g.part_r : g.part_d;
-      dst[((int64_t)pb * ntile + tn) * n + row] = s;
+      int64_t a = ((int64_t)pb * ntile + tn) * n + row;
+      double s1 = rowp[0][0][tid] + rowp[0][1][tid];
+      if (EPI == EPI_X) {
+        g.part_r[a] = s1;
+      } else {
+        g.part_d[a] = s1;
+        g.part_z[a] = rowp[1][0][tid] + rowp[1][1][tid];
+      }
     }
   } else if (EPI == EPI_X && tid < BM + BN) {
     int c = tid - BM;
@@ -229,27 +296,22 @@ __global__ void __launch_bounds__(256) k_bwd_y(int64_t n, int64_t nb, const doub
   y[t] = -1.0 / (rho[p] * xnorm[t]);
 }
 
-// X = diag(lambda_bar) when V_bar is absent is produced by k_gemm<EPI_X> with
-// has_B = 0.  Here: u = X y + X^T y, rho_bar = y^T X y, d_bar.
-__global__ void __launch_bounds__(256) k_bwd_finish(int64_t n, int ntile, const double* __restrict__ part_r,
-                                                    const double* __restrict__ part_c,
-                                                    const double* __restrict__ part_d, const double* __restrict__ y,
-                                                    double* __restrict__ u, double* __restrict__ d_bar,
-                                                    double* __restrict__ rho_bar) {
+// u = X y + X^T y and rho_bar = y^T X y from the partials of the first GEMM
+__global__ void __launch_bounds__(256) k_bwd_u(int64_t n, int ntile, const double* __restrict__ part_r,
+                                               const double* __restrict__ part_c, const double* __restrict__ y,
+                                               double* __restrict__ u, double* __restrict__ rho_bar) {
   const int pb = blockIdx.x;
   const int64_t vo = (int64_t)pb * n;
   __shared__ double red[256];
   double acc = 0.0;
   for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-    double r = 0.0, c = 0.0, dsum = 0.0;
+    double r = 0.0, c = 0.0;
     for (int t = 0; t < ntile; ++t) {
       int64_t a = ((int64_t)pb * ntile + t) * n + j;
       r += part_r[a];
       c += part_c[a];
-      dsum += part_d[a];
     }
     u[vo + j] = r + c;
-    d_bar[vo + j] = dsum;
     acc += y[vo + j] * r;
   }
   red[threadIdx.x] = acc;
@@ -261,22 +323,26 @@ __global__ void __launch_bounds__(256) k_bwd_finish(int64_t n, int ntile, const 
   if (threadIdx.x == 0) rho_bar[pb] = red[0];
 }
 
-// z_bar = rho V u (V column-major): threads along rows, loop over columns
-__global__ void __launch_bounds__(256) k_bwd_zbar(int64_t n, const double* __restrict__ rho,
-                                                  const double* __restrict__ V, const double* __restrict__ u,
-                                                  double* __restrict__ z_bar) {
-  const int pb = blockIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const double* Vp = V + (int64_t)pb * n * n;
-  const double* up = u + (int64_t)pb * n;
-  double s = 0.0;
-  for (int64_t l = 0; l < n; ++l) s = __builtin_fma(Vp[j + l * n], up[l], s);
-  z_bar[(int64_t)pb * n + j] = rho[pb] * s;
+// d_bar_j = sum_k (V X)_jk V_jk and z_bar = rho V u from the second GEMM's partials
+__global__ void __launch_bounds__(256) k_bwd_final(int64_t n, int64_t nb, int ntile, const double* __restrict__ rho,
+                                                   const double* __restrict__ part_d,
+                                                   const double* __restrict__ part_z, double* __restrict__ d_bar,
+                                                   double* __restrict__ z_bar) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nb) return;
+  int64_t pb = t / n, j = t % n;
+  double sd = 0.0, sz = 0.0;
+  for (int q = 0; q < ntile; ++q) {
+    int64_t a = (pb * ntile + q) * n + j;
+    sd += part_d[a];
+    sz += part_z[a];
+  }
+  d_bar[t] = sd;
+  z_bar[t] = rho[pb] * sz;
 }
 
 struct BLayout {
-  size_t X, y, u, pr, pc, pd, total;
+  size_t X, y, u, pr, pc, pd, pz, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 static BLayout blayout(int64_t n, int64_t nb) {
@@ -289,6 +355,7 @@ static BLayout blayout(int64_t n, int64_t nb) {
   L.pr = o; o = al(o + sizeof(double) * n * nt * nb);
   L.pc = o; o = al(o + sizeof(double) * n * nt * nb);
   L.pd = o; o = al(o + sizeof(double) * n * nt * nb);
+  L.pz = o; o = al(o + sizeof(double) * n * nt * nb);
   L.total = o;
   return L;
 }
@@ -332,11 +399,15 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
   double* pr = (double*)(w + L.pr);
   double* pc = (double*)(w + L.pc);
   double* pd = (double*)(w + L.pd);
+  double* pz = (double*)(w + L.pz);
   const int tiles = (int)((n + BM - 1) / BM);
+  const int64_t nbpad = (nbatch + NXCD - 1) / NXCD * NXCD;
+  const unsigned ggrid = (unsigned)(nbpad * tiles * tiles);
 
   hipLaunchKernelGGL(k_bwd_y, dim3((unsigned)((n * nbatch + 255) / 256)), dim3(256), 0, st, n, nbatch, rho, xnorm, y);
   GArgs g;
   g.n = n;
+  g.nb = (int)nbatch;
   g.A = V;
   g.B = V_bar;
   g.C = X;
@@ -347,17 +418,18 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
   g.y = y;
   g.part_r = pr;
   g.part_c = pc;
+  g.u = u;
   g.part_d = pd;
+  g.part_z = pz;
   g.has_B = V_bar != nullptr;
-  hipLaunchKernelGGL(k_gemm<EPI_X>, dim3((unsigned)(tiles * tiles), (unsigned)nbatch), dim3(NT), 0, st, g);
+  hipLaunchKernelGGL(k_gemm<EPI_X>, dim3(ggrid), dim3(NT), 0, st, g);
   if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
+  hipLaunchKernelGGL(k_bwd_u, dim3((unsigned)nbatch), dim3(256), 0, st, n, tiles, pr, pc, y, u, rho_bar);
   g.B = X;
-  hipLaunchKernelGGL(k_gemm<EPI_D>, dim3((unsigned)(tiles * tiles), (unsigned)nbatch), dim3(NT), 0, st, g);
+  hipLaunchKernelGGL(k_gemm<EPI_D>, dim3(ggrid), dim3(NT), 0, st, g);
   if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
-  hipLaunchKernelGGL(k_bwd_finish, dim3((unsigned)nbatch), dim3(256), 0, st, n, tiles, pr, pc, pd, y, u, d_bar,
-                     rho_bar);
-  hipLaunchKernelGGL(k_bwd_zbar, dim3((unsigned)((n + 255) / 256), (unsigned)nbatch), dim3(256), 0, st, n, rho, V,
-                     u, z_bar);
+  hipLaunchKernelGGL(k_bwd_final, dim3((unsigned)((n * nbatch + 255) / 256)), dim3(256), 0, st, n, nbatch, tiles,
+                     rho, pd, pz, d_bar, z_bar);
   if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
   return DPR1_OK;
 }
