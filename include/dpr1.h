@@ -129,8 +129,8 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
  * one persistent launch whose blocks take (problem, 64 eigenvalues) items
  * from a device work queue, larger problems first.
  *
- * dpr1_batched_workspace_size(nprob, ntotal): bytes for a batch whose sizes
- *   sum to ntotal.
+ * dpr1_batched_workspace_size(nprob, offs_host): bytes of workspace for the
+ *   batch with these host offsets (0 if the offsets are invalid).
  * dpr1_batched_plan: reads the host offsets (offs_host[0] = 0, sizes >= 1),
  *   builds the work queue and the launch shape, copies the queue into the
  *   workspace and synchronises `stream` (the only host->device copy and the
@@ -146,7 +146,7 @@ typedef struct dpr1_plan {
   dpr1_opts opts;
 } dpr1_plan;
 
-size_t dpr1_batched_workspace_size(int64_t nprob, int64_t ntotal);
+size_t dpr1_batched_workspace_size(int64_t nprob, const int64_t* offs_host);
 int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* opts,
                       dpr1_plan* plan, void* work, size_t work_bytes, void* stream);
 int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d,

@@ -181,11 +181,14 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   __shared__ double rowp[2][2][BM];  // [quantity][wn half][row]
   __shared__ double colp[2][BN];     // [wm half][col]
   const int64_t vo = (int64_t)pb * n;
+  // shift indices come from the caller: clamped so that a bad one cannot
+  // address outside the problem
+  auto sidx = [&](int64_t k) { return (int64_t)min(max(g.sidx[vo + k], 0), (int)(n - 1)); };
   if (tid < BM) {
     int64_t row = m0 + tid;
     if (row < n) {
       if (EPI == EPI_X) {
-        rsig[tid] = g.d[vo + g.sidx[vo + row]];
+        rsig[tid] = g.d[vo + sidx(row)];
         rmu[tid] = g.mu[vo + row];
         ry[tid] = g.y[vo + row];
       }
@@ -195,7 +198,7 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
     int64_t col = n0 + c;
     if (col < n) {
       if (EPI == EPI_X) {
-        csig[c] = g.d[vo + g.sidx[vo + col]];
+        csig[c] = g.d[vo + sidx(col)];
         cmu[c] = g.mu[vo + col];
         cy[c] = g.y[vo + col];
         clb[c] = g.lam_bar ? g.lam_bar[vo + col] : 0.0;

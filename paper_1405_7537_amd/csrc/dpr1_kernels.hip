@@ -1016,17 +1016,35 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
 __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int nprob,
                                              const int32_t* __restrict__ ii, const double* __restrict__ mu,
                                              const double* __restrict__ xs, const double* __restrict__ lam,
-                                             double* __restrict__ lam_out, int32_t* __restrict__ idx_out,
-                                             double* __restrict__ mu_out, double* __restrict__ xn_out) {
+                                             const double* __restrict__ sd, double* __restrict__ csig,
+                                             double* __restrict__ cinv, double* __restrict__ lam_out,
+                                             int32_t* __restrict__ idx_out, double* __restrict__ mu_out,
+                                             double* __restrict__ xn_out) {
   int p = blockIdx.y;
   if (p >= nprob) return;
   const Meta M = meta[p];
   const int n = M.n;
+  if (M.info != 0) {
+    // rejected problem: the solver wrote nothing; leave defined outputs
+    // (NaN values, in-range shift indices) and no eigenvector constants
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+      int64_t b = M.off + k;
+      lam_out[b] = NAN;
+      if (idx_out) idx_out[b] = k;
+      if (mu_out) mu_out[b] = NAN;
+      if (xn_out) xn_out[b] = NAN;
+    }
+    return;
+  }
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     int ko = M.neg ? n - 1 - k : k;
     int64_t a = M.off + k, b = M.off + ko;
     double sg = M.neg ? -1.0 : 1.0;
     lam_out[b] = sg * lam[a];
+    // per-column constants of the eigenvector kernel: sigma_k and
+    // 1/(sign(mu) |mu| ||x||), so that v_j = zeta_j (mu/(delta_j - mu)) cinv
+    csig[a] = sd[M.off + ii[a]];
+    cinv[a] = 1.0 / copysign(xs[a], mu[a]);
     if (idx_out) idx_out[b] = M.neg ? n - 1 - ii[a] : ii[a];
     if (mu_out) mu_out[b] = sg * mu[a];
     if (xn_out) xn_out[b] = xs[a] / fabs(mu[a]);
@@ -1107,9 +1125,40 @@ __global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, co
   }
 }
 
+// Batched problems: a block writes one contiguous chunk of VEC_CH elements of
+// a problem's n_p x n_p block (column-major, ld = n_p), in output order;
+// the internal row/column follow from the position (reversed when rho < 0).
+constexpr int VEC_CH = 8192;
+__global__ void __launch_bounds__(VEC_T) k_vec_chunks(const Meta* __restrict__ meta, const int2* __restrict__ chunks,
+                                                      const double* __restrict__ sd,
+                                                      const double* __restrict__ sz,
+                                                      const double* __restrict__ mu,
+                                                      const double* __restrict__ csig,
+                                                      const double* __restrict__ cinv, double* __restrict__ V,
+                                                      const int64_t* __restrict__ voffs) {
+  const int2 ch = chunks[blockIdx.x];
+  const Meta M = meta[ch.x];
+  if (M.info != 0) return;
+  const int64_t n = M.n;
+  const int64_t e0 = (int64_t)ch.y * VEC_CH;
+  const int64_t e1 = min(e0 + (int64_t)VEC_CH, n * n);
+  double* out = V + voffs[ch.x];
+  const double sg = M.neg ? -1.0 : 1.0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += VEC_T) {
+    const int64_t ko = e / n, jo = e - ko * n;
+    const int64_t k = M.neg ? n - 1 - ko : ko, j = M.neg ? n - 1 - jo : jo;
+    const int64_t a = M.off + k;
+    const double m = mu[a];
+    const double den = (sd[M.off + j] - csig[a]) - m;
+    double q = m * rcp_nr(den);
+    q = __builtin_fma(__builtin_fma(-q, den, m), rcp_1nr(den), q);  // corrected quotient
+    __builtin_nontemporal_store(sg * (sz[M.off + j] * q) * cinv[a], &out[e]);
+  }
+}
+
 // ===================================================================== host
 struct Layout {
-  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, fix, items, groups, ctr, total;
+  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, csig, cinv, fix, items, groups, ctr, total;
 };
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1126,6 +1175,8 @@ static Layout layout(int64_t nprob, int64_t N, int64_t nitems, int64_t ngroups =
   L.mu = o; o = al(o + 8 * N);
   L.xs = o; o = al(o + 8 * N);
   L.lam = o; o = al(o + 8 * N);
+  L.csig = o; o = al(o + 8 * N);
+  L.cinv = o; o = al(o + 8 * N);
   L.fix = o; o = al(o + sizeof(FixItem) * N);
   L.items = o; o = al(o + sizeof(int2) * nitems);
   L.groups = o; o = al(o + sizeof(int2) * ngroups);
@@ -1150,6 +1201,19 @@ static int pick_split(int64_t nblocks, int64_t nmax) {
   w = std::min<int64_t>(w, MAXW);
   while (w > 1 && nmax / w < 256) --w;
   return (int)std::max<int64_t>(w, 1);
+}
+
+// Number of VEC_CH-element chunks of all V blocks of a batch (0 if a
+// problem has more chunks than an int32 index holds).
+static int64_t count_chunks(int64_t nprob, const int64_t* offs) {
+  int64_t c = 0;
+  for (int64_t p = 0; p < nprob; ++p) {
+    int64_t np = offs[p + 1] - offs[p];
+    int64_t cp = (np * np + VEC_CH - 1) / VEC_CH;
+    if (cp > (int64_t)INT32_MAX) return 0;
+    c += cp;
+  }
+  return c;
 }
 
 static size_t red_bytes(int W) { return W > 1 ? sizeof(double) * 2 * W * WAVE : 0; }
@@ -1230,15 +1294,17 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   HIPCHECK(hipGetLastError());
   int64_t nmax = n_single;
   (void)nmax;
+  double* csig = (double*)(w + L.csig);
+  double* cinv = (double*)(w + L.cinv);
   hipLaunchKernelGGL(k_out, dim3(offs ? 1 : (unsigned)std::min<int64_t>((N + 255) / 256, 1024), (unsigned)nprob),
-                     dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, lambda, shift_idx, mu,
-                     xnorm);
+                     dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, A.sd, csig, cinv, lambda,
+                     shift_idx, mu, xnorm);
   HIPCHECK(hipGetLastError());
   if (V) {
     if (ev) HIPCHECK(hipEventRecord(ev[2], st));
     if (persistent_grid) {
-      hipLaunchKernelGGL(k_vec, dim3((unsigned)ngroups), dim3(VEC_T), 0, st, meta, (const int2*)(w + L.groups),
-                         ngroups, A.sd, A.sz, A.ii, A.mu, A.xs, V, voffs, ldv);
+      hipLaunchKernelGGL(k_vec_chunks, dim3((unsigned)ngroups), dim3(VEC_T), 0, st, meta,
+                         (const int2*)(w + L.groups), A.sd, A.sz, A.mu, csig, cinv, V, voffs);
     } else {
       int64_t cg = (N + VEC_C - 1) / VEC_C, rt = (N + VEC_ROWS - 1) / VEC_ROWS;
       hipLaunchKernelGGL(k_vec, dim3((unsigned)(cg * rt)), dim3(VEC_T), 0, st, meta, (const int2*)nullptr, cg,
@@ -1272,10 +1338,15 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
 }
 
 // ------------------------------------------------------------ batched
-size_t dpr1_batched_workspace_size(int64_t nprob, int64_t ntotal) {
-  if (nprob < 1 || ntotal < nprob) return 0;
+size_t dpr1_batched_workspace_size(int64_t nprob, const int64_t* offs_host) {
+  if (nprob < 1 || !offs_host || offs_host[0] != 0) return 0;
+  for (int64_t p = 0; p < nprob; ++p)
+    if (offs_host[p + 1] - offs_host[p] < 1) return 0;
+  int64_t ntotal = offs_host[nprob];
   int64_t nitems = ntotal / WAVE + nprob;  // upper bound of sum ceil(n_p/64)
-  return layout(nprob, ntotal, nitems, ntotal / VEC_C + nprob).total;
+  int64_t nch = count_chunks(nprob, offs_host);
+  if (nch == 0) return 0;
+  return layout(nprob, ntotal, nitems, nch).total;
 }
 
 int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* opts, dpr1_plan* plan,
@@ -1293,7 +1364,9 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   }
   int64_t N = offs_host[nprob];
   if (N > (int64_t)INT32_MAX) return -2;
-  Layout L0 = layout(nprob, N, N / WAVE + nprob, N / VEC_C + nprob);
+  const int64_t nch = count_chunks(nprob, offs_host);
+  if (nch == 0) return -2;
+  Layout L0 = layout(nprob, N, N / WAVE + nprob, nch);
   if (work_bytes < L0.total) return -6;
   dpr1_opts o;
   fill_opts(opts, &o);
@@ -1310,11 +1383,12 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   }
   int64_t nitems = (int64_t)items.size();
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nitems, nmax);
-  // column groups of the eigenvector kernel, one per (problem, VEC_C columns)
+  // chunks of the eigenvector kernel, VEC_CH consecutive elements of one
+  // problem's V block each
   std::vector<int2> groups;
   for (int32_t p : order) {
     int64_t np = offs_host[p + 1] - offs_host[p];
-    for (int64_t c0 = 0; c0 < np; c0 += VEC_C) groups.push_back(make_int2(p, (int)c0));
+    for (int64_t c = 0; c * VEC_CH < np * np; ++c) groups.push_back(make_int2(p, (int)c));
   }
   hipStream_t st = (hipStream_t)stream;
   HIPCHECK(hipMemcpyAsync((char*)work + L0.items, items.data(), sizeof(int2) * nitems, hipMemcpyHostToDevice, st));
@@ -1345,7 +1419,7 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
   if (V && !voffs) return -8;
   if (!info) return -12;
   if (!work) return -14;
-  Layout L = layout(plan->nprob, plan->ntotal, plan->ntotal / WAVE + plan->nprob, plan->ntotal / VEC_C + plan->nprob);
+  Layout L = layout(plan->nprob, plan->ntotal, plan->ntotal / WAVE + plan->nprob, plan->ngroups);
   if (work_bytes < L.total) return -15;
   return launch_solve(L, (char*)work, plan->nprob, plan->ntotal, offs, 0, d, z, rho, 0.0, lambda, V, voffs, 0,
                       shift_idx, mu, xnorm, info, stats, plan->opts, plan->split, plan->nitems, plan->grid,

@@ -50,7 +50,7 @@ def lib():
         L.dpr1_workspace_size.restype = C.c_size_t
         L.dpr1_eig.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, vp, vp, vp, vp,
                                C.POINTER(Opts), vp, C.c_size_t, vp]
-        L.dpr1_batched_workspace_size.argtypes = [i64, i64]
+        L.dpr1_batched_workspace_size.argtypes = [i64, C.POINTER(C.c_int64)]
         L.dpr1_batched_workspace_size.restype = C.c_size_t
         L.dpr1_batched_plan.argtypes = [i64, C.POINTER(C.c_int64), C.POINTER(Opts), C.POINTER(Plan),
                                         vp, C.c_size_t, vp]
@@ -192,7 +192,9 @@ class Batch:
         self.dev = torch.device(device)
         self.offs = torch.as_tensor(offs).to(self.dev)
         self.voffs = torch.as_tensor(voffs).to(self.dev)
-        self.wb = int(lib().dpr1_batched_workspace_size(self.nprob, self.ntotal))
+        self.wb = int(lib().dpr1_batched_workspace_size(self.nprob, offs.ctypes.data_as(C.POINTER(C.c_int64))))
+        if self.wb == 0:
+            raise ValueError("invalid batch offsets")
         self.work = torch.empty(self.wb, dtype=torch.uint8, device=self.dev)
         self.plan = Plan()
         rc = lib().dpr1_batched_plan(self.nprob, offs.ctypes.data_as(C.POINTER(C.c_int64)),

@@ -52,6 +52,13 @@ def test_bad_problem_is_isolated(D, orc):
     b = D.eig_batched(d, z, rho, offs, check=False)
     info = b.info.cpu().numpy().tolist()
     assert info == [0, 0, 1, 0, 2, 4]
+    # rejected problems get defined outputs: NaN eigenvalues, in-range shift indices
+    lam = b.lam.cpu().numpy()
+    idx = b.shift_idx.cpu().numpy()
+    for p in (2, 4, 5):
+        a, e = offs[p], offs[p + 1]
+        assert np.all(np.isnan(lam[a:e]))
+        assert np.array_equal(idx[a:e], np.arange(e - a))
     for p in (0, 1, 3):
         el, ev = check_problem(b, orc, d, z, rho, offs, p)
         assert el <= LAM_TOL and ev <= VEC_TOL
