@@ -14,10 +14,12 @@
 //              Per eigenvalue: shift test, tip b in double-double, extreme
 //              root of the arrowhead secular function, compensated Newton
 //              step, near-zero test, ||x||.
-//   k_fix   -- one wave per flagged eigenpair: double-double Newton polish
-//              and the near-zero recomputation of eq. (gamma).
+//   k_fix   -- one 256-thread block per flagged eigenpair: root search
+//              continued past k_eig's pass budget, double-double Newton
+//              polish, and the near-zero recomputation of eq. (gamma).
 //   k_out   -- user outputs in the caller's index order.
-//   k_vec   -- V, one block per column, coalesced non-temporal stores.
+//   k_vec   -- V, one block per column group and row range, non-temporal
+//              stores in windows aligned to whole cache lines.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -1052,107 +1054,130 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
 }
 
 // ------------------------------------------------------------------- vec
-// v_j = zeta_j r_j / (|mu| ||x||), r_j = mu/(delta_j - mu).  A block owns a
-// segment of up to VEC_ROWS rows of VEC_C columns of one problem: every
-// thread keeps the (d_j, zeta_j) of its VEC_R rows in registers and the block
-// writes the columns one after the other, each segment contiguous (consecutive
-// threads on consecutive rows, non-temporal stores).
-constexpr int VEC_C = 8;
+// v_j = zeta_j r_j / (|mu| ||x||), r_j = mu/(delta_j - mu).  A block owns up
+// to CB columns of one problem over up to ROWS consecutive positions of each
+// column.  The (d_j, zeta_j) of those positions are staged in LDS once; each
+// wave then writes 64-element windows aligned to 512 bytes of V, so every
+// store instruction covers whole cache lines whatever the column's offset
+// (a packed ragged batch puts most columns at odd offsets; misaligned
+// non-temporal stores write partial lines and halve the write bandwidth).
+// Only the first and last window of a column segment are partial.  The
+// single-problem launch derives (column group, row tile) from the block
+// index; the batched launch reads (problem, first column, columns, first
+// row) from a table built by the plan.
 constexpr int VEC_T = 256;
-constexpr int VEC_R = 16;
-constexpr int VEC_ROWS = VEC_T * VEC_R;
+constexpr int VEC_ROWS = 2048;
+constexpr int VEC_C_SINGLE = 32, VEC_C_BATCH = 64;
 
-__global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, const int2* __restrict__ groups,
+template <int CB>
+__global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, const int4* __restrict__ groups,
                                                int64_t ncolgroups, const double* __restrict__ sd,
-                                               const double* __restrict__ sz, const int32_t* __restrict__ ii,
-                                               const double* __restrict__ mu, const double* __restrict__ xs,
+                                               const double* __restrict__ sz, const double* __restrict__ mu,
+                                               const double* __restrict__ csig, const double* __restrict__ cinv,
                                                double* __restrict__ V, const int64_t* __restrict__ voffs,
                                                int64_t ldv) {
-  __shared__ double csig[VEC_C], cmu[VEC_C], cinv[VEC_C];
-  int p, c0;
+  __shared__ double ld_d[VEC_ROWS], ld_z[VEC_ROWS];
+  __shared__ double lsig[CB], lmu[CB], linv[CB];
+  int p, c0, nc;
   int64_t r0;
   if (groups) {
-    int2 g = groups[blockIdx.x];  // batched: (problem, first column), rows from 0
+    const int4 g = groups[blockIdx.x];
     p = g.x;
     c0 = g.y;
-    r0 = 0;
+    nc = g.z;
+    r0 = g.w;
   } else {
     p = 0;
-    c0 = (int)(blockIdx.x % ncolgroups) * VEC_C;
+    c0 = (int)(blockIdx.x % ncolgroups) * CB;
     r0 = (int64_t)(blockIdx.x / ncolgroups) * VEC_ROWS;
+    nc = 0;
   }
   const Meta M = meta[p];
   if (M.info != 0) return;
   const int n = M.n;
-  const int nc = min(VEC_C, n - c0);
-  if (threadIdx.x < VEC_C) {
-    int c = threadIdx.x;
-    if (c < nc) {
-      int64_t a = M.off + c0 + c;
-      double m = mu[a];
-      csig[c] = sd[M.off + ii[a]];
-      cmu[c] = m;
-      cinv[c] = 1.0 / copysign(xs[a], m);  // v = x/||x|| = zeta r/(sign(mu) |mu| ||x||)
-    }
+  if (!groups) nc = min(CB, n - c0);
+  const int nr = (int)min((int64_t)VEC_ROWS, (int64_t)n - r0);
+  if (nc <= 0 || nr <= 0) return;
+  const double sg = M.neg ? -1.0 : 1.0;
+  // stage positions r0 .. r0+nr-1 (position = row in memory order; a
+  // reversed problem stores row j at position n-1-j)
+  for (int t = threadIdx.x; t < nr; t += VEC_T) {
+    const int64_t pos = r0 + t;
+    const int64_t j = M.neg ? n - 1 - pos : pos;
+    ld_d[t] = sd[M.off + j];
+    ld_z[t] = sg * sz[M.off + j];
+  }
+  if (threadIdx.x < nc) {
+    const int64_t a = M.off + c0 + threadIdx.x;
+    lsig[threadIdx.x] = csig[a];
+    lmu[threadIdx.x] = mu[a];
+    linv[threadIdx.x] = cinv[a];
   }
   __syncthreads();
   const int64_t ld = voffs ? (int64_t)n : ldv;
   const int64_t base = voffs ? voffs[p] : 0;
-  const double sg = M.neg ? -1.0 : 1.0;
-  for (int64_t rb = r0; rb < n; rb += VEC_ROWS) {
-    double dj[VEC_R], zj[VEC_R];
-#pragma unroll
-    for (int r = 0; r < VEC_R; ++r) {
-      int64_t j = rb + threadIdx.x + (int64_t)r * VEC_T;
-      dj[r] = j < n ? sd[M.off + j] : 0.0;
-      zj[r] = j < n ? sg * sz[M.off + j] : 0.0;
-    }
-    for (int c = 0; c < nc; ++c) {
-      const double m = cmu[c], sc = csig[c], iv = cinv[c];
-      const int ko = M.neg ? n - 1 - (c0 + c) : c0 + c;
-      double* col = V + base + (int64_t)ko * ld;
-#pragma unroll
-      for (int r = 0; r < VEC_R; ++r) {
-        int64_t j = rb + threadIdx.x + (int64_t)r * VEC_T;
-        const double den = (dj[r] - sc) - m;
-        double q = m * rcp_nr(den);
-        q = __builtin_fma(__builtin_fma(-q, den, m), rcp_1nr(den), q);  // corrected quotient
-        const double v = (zj[r] * q) * iv;
-        if (j < n) __builtin_nontemporal_store(v, &col[M.neg ? n - 1 - j : j]);
+  const int wv = wave_id(), lane = threadIdx.x % WAVE;
+  constexpr int NW = VEC_T / WAVE;
+  if (r0 == 0 && nr == n && ld == n) {
+    // Whole columns of a packed block: the group's columns are one
+    // contiguous range of nc n elements, written in aligned windows with
+    // (column, position) recovered per element.  nc n <= CB VEC_ROWS < 2^24,
+    // so the float quotient is off by at most one and corrected exactly.
+    const int64_t kolo = M.neg ? (int64_t)n - c0 - nc : c0;
+    const int64_t S = base + kolo * n;
+    const int len = nc * n;
+    const int64_t Sal = S & ~(int64_t)(WAVE - 1);
+    const int nwin = (int)((S + len - Sal + WAVE - 1) / WAVE);
+    const float inv_n = 1.0f / (float)n;
+    for (int w = wv; w < nwin; w += NW) {
+      const int64_t e = Sal + (int64_t)w * WAVE + lane;
+      const int64_t l64 = e - S;
+      if (l64 >= 0 && l64 < len) {
+        const int local = (int)l64;
+        int q = (int)((float)local * inv_n);
+        int pos = local - q * n;
+        if (pos < 0) {
+          pos += n;
+          --q;
+        } else if (pos >= n) {
+          pos -= n;
+          ++q;
+        }
+        const int ko = (int)kolo + q;
+        const int c = (M.neg ? n - 1 - ko : ko) - c0;
+        const double m = lmu[c];
+        const double den = (ld_d[pos] - lsig[c]) - m;
+        const double rc = rcp_1nr(den);
+        double qq = m * rc;
+        qq = __builtin_fma(__builtin_fma(-qq, den, m), rc, qq);  // corrected quotient
+        __builtin_nontemporal_store((ld_z[pos] * qq) * linv[c], &V[e]);
       }
     }
-    if (groups == nullptr) break;  // single problem: one row segment per block
+    return;
   }
-}
-
-// Batched problems: a block writes one contiguous chunk of VEC_CH elements of
-// a problem's n_p x n_p block (column-major, ld = n_p), in output order;
-// the internal row/column follow from the position (reversed when rho < 0).
-constexpr int VEC_CH = 8192;
-__global__ void __launch_bounds__(VEC_T) k_vec_chunks(const Meta* __restrict__ meta, const int2* __restrict__ chunks,
-                                                      const double* __restrict__ sd,
-                                                      const double* __restrict__ sz,
-                                                      const double* __restrict__ mu,
-                                                      const double* __restrict__ csig,
-                                                      const double* __restrict__ cinv, double* __restrict__ V,
-                                                      const int64_t* __restrict__ voffs) {
-  const int2 ch = chunks[blockIdx.x];
-  const Meta M = meta[ch.x];
-  if (M.info != 0) return;
-  const int64_t n = M.n;
-  const int64_t e0 = (int64_t)ch.y * VEC_CH;
-  const int64_t e1 = min(e0 + (int64_t)VEC_CH, n * n);
-  double* out = V + voffs[ch.x];
-  const double sg = M.neg ? -1.0 : 1.0;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += VEC_T) {
-    const int64_t ko = e / n, jo = e - ko * n;
-    const int64_t k = M.neg ? n - 1 - ko : ko, j = M.neg ? n - 1 - jo : jo;
-    const int64_t a = M.off + k;
-    const double m = mu[a];
-    const double den = (sd[M.off + j] - csig[a]) - m;
-    double q = m * rcp_nr(den);
-    q = __builtin_fma(__builtin_fma(-q, den, m), rcp_1nr(den), q);  // corrected quotient
-    __builtin_nontemporal_store(sg * (sz[M.off + j] * q) * cinv[a], &out[e]);
+  // Column segments one after the other.  When every column has the same
+  // offset modulo the window (ld a multiple of 64) the window count is
+  // exact, otherwise it allows for the worst offset.
+  const int64_t sfirst = base + (int64_t)(M.neg ? n - 1 - c0 : c0) * ld + r0;
+  const int wc = (ld % WAVE == 0) ? (int)(((sfirst & (WAVE - 1)) + nr + WAVE - 1) / WAVE) : (nr + WAVE - 1) / WAVE + 1;
+  int c = 0, wi = wv;
+  while (wi >= wc) { wi -= wc; ++c; }
+  for (; c < nc;) {
+    const int k = c0 + c;
+    const int64_t ko = M.neg ? n - 1 - k : k;
+    const int64_t s0 = base + ko * ld + r0;  // element index of the segment's first position
+    const int64_t e = (s0 & ~(int64_t)(WAVE - 1)) + (int64_t)wi * WAVE + lane;
+    const int64_t rel = e - s0;
+    if (rel >= 0 && rel < nr) {
+      const double m = lmu[c];
+      const double den = (ld_d[rel] - lsig[c]) - m;
+      const double rc = rcp_1nr(den);
+      double q = m * rc;
+      q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
+      __builtin_nontemporal_store((ld_z[rel] * q) * linv[c], &V[e]);
+    }
+    wi += NW;
+    while (wi >= wc) { wi -= wc; ++c; }
   }
 }
 
@@ -1179,7 +1204,7 @@ static Layout layout(int64_t nprob, int64_t N, int64_t nitems, int64_t ngroups =
   L.cinv = o; o = al(o + 8 * N);
   L.fix = o; o = al(o + sizeof(FixItem) * N);
   L.items = o; o = al(o + sizeof(int2) * nitems);
-  L.groups = o; o = al(o + sizeof(int2) * ngroups);
+  L.groups = o; o = al(o + sizeof(int4) * ngroups);
   L.ctr = o; o = al(o + 64);
   L.total = o;
   return L;
@@ -1203,15 +1228,13 @@ static int pick_split(int64_t nblocks, int64_t nmax) {
   return (int)std::max<int64_t>(w, 1);
 }
 
-// Number of VEC_CH-element chunks of all V blocks of a batch (0 if a
-// problem has more chunks than an int32 index holds).
-static int64_t count_chunks(int64_t nprob, const int64_t* offs) {
+// Number of (problem, column group, row tile) blocks of the batched
+// eigenvector launch.
+static int64_t count_groups(int64_t nprob, const int64_t* offs) {
   int64_t c = 0;
   for (int64_t p = 0; p < nprob; ++p) {
-    int64_t np = offs[p + 1] - offs[p];
-    int64_t cp = (np * np + VEC_CH - 1) / VEC_CH;
-    if (cp > (int64_t)INT32_MAX) return 0;
-    c += cp;
+    const int64_t np = offs[p + 1] - offs[p];
+    c += ((np + VEC_C_BATCH - 1) / VEC_C_BATCH) * ((np + VEC_ROWS - 1) / VEC_ROWS);
   }
   return c;
 }
@@ -1303,12 +1326,13 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   if (V) {
     if (ev) HIPCHECK(hipEventRecord(ev[2], st));
     if (persistent_grid) {
-      hipLaunchKernelGGL(k_vec_chunks, dim3((unsigned)ngroups), dim3(VEC_T), 0, st, meta,
-                         (const int2*)(w + L.groups), A.sd, A.sz, A.mu, csig, cinv, V, voffs);
+      hipLaunchKernelGGL((k_vec<VEC_C_BATCH>), dim3((unsigned)ngroups), dim3(VEC_T), 0, st, meta,
+                         (const int4*)(w + L.groups), ngroups, A.sd, A.sz, A.mu, csig, cinv, V, voffs, ldv);
     } else {
-      int64_t cg = (N + VEC_C - 1) / VEC_C, rt = (N + VEC_ROWS - 1) / VEC_ROWS;
-      hipLaunchKernelGGL(k_vec, dim3((unsigned)(cg * rt)), dim3(VEC_T), 0, st, meta, (const int2*)nullptr, cg,
-                         A.sd, A.sz, A.ii, A.mu, A.xs, V, voffs, ldv);
+      const int64_t cg = (N + VEC_C_SINGLE - 1) / VEC_C_SINGLE;
+      const int64_t rt = (N + VEC_ROWS - 1) / VEC_ROWS;
+      hipLaunchKernelGGL((k_vec<VEC_C_SINGLE>), dim3((unsigned)(cg * rt)), dim3(VEC_T), 0, st, meta,
+                         (const int4*)nullptr, cg, A.sd, A.sz, A.mu, csig, cinv, V, voffs, ldv);
     }
     HIPCHECK(hipGetLastError());
     if (ev) HIPCHECK(hipEventRecord(ev[3], st));
@@ -1344,9 +1368,7 @@ size_t dpr1_batched_workspace_size(int64_t nprob, const int64_t* offs_host) {
     if (offs_host[p + 1] - offs_host[p] < 1) return 0;
   int64_t ntotal = offs_host[nprob];
   int64_t nitems = ntotal / WAVE + nprob;  // upper bound of sum ceil(n_p/64)
-  int64_t nch = count_chunks(nprob, offs_host);
-  if (nch == 0) return 0;
-  return layout(nprob, ntotal, nitems, nch).total;
+  return layout(nprob, ntotal, nitems, count_groups(nprob, offs_host)).total;
 }
 
 int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* opts, dpr1_plan* plan,
@@ -1364,9 +1386,7 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   }
   int64_t N = offs_host[nprob];
   if (N > (int64_t)INT32_MAX) return -2;
-  const int64_t nch = count_chunks(nprob, offs_host);
-  if (nch == 0) return -2;
-  Layout L0 = layout(nprob, N, N / WAVE + nprob, nch);
+  Layout L0 = layout(nprob, N, N / WAVE + nprob, count_groups(nprob, offs_host));
   if (work_bytes < L0.total) return -6;
   dpr1_opts o;
   fill_opts(opts, &o);
@@ -1383,16 +1403,18 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   }
   int64_t nitems = (int64_t)items.size();
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nitems, nmax);
-  // chunks of the eigenvector kernel, VEC_CH consecutive elements of one
-  // problem's V block each
-  std::vector<int2> groups;
+  // blocks of the eigenvector kernel: (problem, first column, columns,
+  // first row), largest problems first
+  std::vector<int4> groups;
   for (int32_t p : order) {
-    int64_t np = offs_host[p + 1] - offs_host[p];
-    for (int64_t c = 0; c * VEC_CH < np * np; ++c) groups.push_back(make_int2(p, (int)c));
+    const int64_t np = offs_host[p + 1] - offs_host[p];
+    for (int64_t c0 = 0; c0 < np; c0 += VEC_C_BATCH)
+      for (int64_t r0 = 0; r0 < np; r0 += VEC_ROWS)
+        groups.push_back(make_int4(p, (int)c0, (int)std::min<int64_t>(VEC_C_BATCH, np - c0), (int)r0));
   }
   hipStream_t st = (hipStream_t)stream;
   HIPCHECK(hipMemcpyAsync((char*)work + L0.items, items.data(), sizeof(int2) * nitems, hipMemcpyHostToDevice, st));
-  HIPCHECK(hipMemcpyAsync((char*)work + L0.groups, groups.data(), sizeof(int2) * groups.size(),
+  HIPCHECK(hipMemcpyAsync((char*)work + L0.groups, groups.data(), sizeof(int4) * groups.size(),
                           hipMemcpyHostToDevice, st));
   HIPCHECK(hipStreamSynchronize(st));
   plan->ngroups = (int64_t)groups.size();

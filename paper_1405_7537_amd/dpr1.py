@@ -139,18 +139,22 @@ def workspace_bytes(n):
 
 
 def eig(d, z, rho, vectors=True, opts: Opts | None = None, check=True, want_stats=False,
-        work=None, out=None, device="cuda"):
+        work=None, out=None, device="cuda", ldv=None):
     """All eigenpairs of D + rho z z^T.  d, z: 1-D float64 (device tensors or host data).
 
-    Returns a Result with lam [n], V [n, n] (V[:, k] = v_k, column-major storage), shift_idx,
-    mu, xnorm, info and (optionally) stats."""
+    Returns a Result with lam [n], V [n, n] (V[:, k] = v_k, column-major storage with leading
+    dimension ldv >= n, default n), shift_idx, mu, xnorm, info and (optionally) stats.  With
+    `out`, its V slot may be an [n, n] view with unit column stride (a slice of a wider buffer)."""
     d = _dev(d, device)
     z = _dev(z, device)
     n = d.numel()
     dev = d.device
     if out is None:
         lam = torch.empty(n, dtype=torch.float64, device=dev)
-        Vt = torch.empty((n, n), dtype=torch.float64, device=dev) if vectors else None
+        ld = n if ldv is None else int(ldv)
+        if ld < max(n, 1):
+            raise ValueError("ldv must be >= n")
+        Vt = torch.empty((n, ld), dtype=torch.float64, device=dev)[:, :n] if vectors else None
         idx = torch.empty(n, dtype=torch.int32, device=dev)
         mu = torch.empty(n, dtype=torch.float64, device=dev)
         xn = torch.empty(n, dtype=torch.float64, device=dev)
@@ -161,7 +165,10 @@ def eig(d, z, rho, vectors=True, opts: Opts | None = None, check=True, want_stat
     wb = workspace_bytes(n)
     if work is None or work.numel() < wb:
         work = torch.empty(wb, dtype=torch.uint8, device=dev)
-    rc = lib().dpr1_eig(_ptr(d), _ptr(z), float(rho), n, _ptr(lam), _ptr(Vt), n, _ptr(idx), _ptr(mu),
+    if Vt is not None and (tuple(Vt.shape) != (n, n) or (n > 1 and Vt.stride(1) != 1)):
+        raise ValueError("V storage must be an [n, n] view with unit column stride")
+    ld = max(n, 1) if Vt is None or n <= 1 else Vt.stride(0)
+    rc = lib().dpr1_eig(_ptr(d), _ptr(z), float(rho), n, _ptr(lam), _ptr(Vt), ld, _ptr(idx), _ptr(mu),
                         _ptr(xn), _ptr(info), _ptr(stats), C.byref(opts) if opts is not None else None,
                         _ptr(work), wb, _stream())
     _rc(rc, "dpr1_eig")

@@ -120,3 +120,16 @@ def test_config_batched_mix_sampled(D, orc):
         inter = np.empty(2 * (e - a))
         inter[0::2], inter[1::2] = lam[a:e], d[a:e]
         assert np.all(inter[:-1] > inter[1:]), p
+
+
+def test_large_and_odd_sizes(D, orc):
+    """Problems above one eigenvector row tile (2048 positions) and odd sizes whose V columns
+    start at every offset modulo a cache line, with both signs of rho."""
+    sizes = [2100, 3000, 17, 64, 65, 2049, 1, 2, 4100, 333]
+    d, z, rho, offs = W.batched(len(sizes), 8, sizes=sizes)
+    rho[1::2] *= -1.0
+    print(f"[batched] large/odd sizes {sizes}", flush=True)
+    b = D.eig_batched(d, z, rho, offs)
+    for p in range(len(sizes)):
+        el, ev = check_problem(b, orc, d, z, rho, offs, p)
+        assert el <= LAM_TOL and ev <= VEC_TOL, (p, sizes[p], el, ev)

@@ -111,3 +111,26 @@ def test_info_codes(D):
     assert int(D.eig(dn, z, rho, check=False).info.item()) == 3
     with pytest.raises(RuntimeError):
         D.eig(d, z, 0.0)
+
+
+@pytest.mark.parametrize("n,pad,rho", [(700, 5, 1.0), (2500, 3, -0.7), (4100, 64, 2.0)])
+def test_strided_v(D, orc, n, pad, rho):
+    """V written into a wider column-major buffer (ldv = n + pad): the columns match the
+    oracle, and the padding rows between columns are left untouched."""
+    import torch
+    d, z, _ = W.uniform(n, 11)
+    ld = n + pad
+    print(f"[parity] strided n={n} ldv={ld} rho={rho}", flush=True)
+    buf = torch.full((n, ld), float("nan"), dtype=torch.float64, device="cuda")
+    out = (torch.empty(n, dtype=torch.float64, device="cuda"), buf[:, :n],
+           torch.empty(n, dtype=torch.int32, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"),
+           torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.int32, device="cuda"))
+    r = D.eig(d, z, rho, out=out)
+    lo, Vo = orc.eig(d, z, rho)
+    el = rel(r.lam.cpu().numpy(), lo)
+    b = buf.cpu().numpy()
+    ev = rel(b[:, :n].T, Vo)
+    print(f"[parity] strided: max rel lam {el.max():.3e} V {ev.max():.3e}", flush=True)
+    assert el.max() <= LAM_TOL
+    assert ev.max() <= VEC_TOL
+    assert np.isnan(b[:, n:]).all()
