@@ -26,19 +26,21 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic FP64 operations per (eigenvalue k, inner index j) pair, division
-# counted as one operation; a double-double operation counted as 10.
-FLOPS_SHIFT = 4           # (d_j - d_k) - tau, zeta^2/den, add
-FLOPS_TIP = 30            # exact difference, DD quotient, DD sum
-FLOPS_ROOT_RATIONAL = 11  # per pass: delta', nu delta' - 1, q, 1/q, t, S' term (3), 2 adds
-FLOPS_ROOT_BISECT = 6     # per pass: delta', fma, mul, div, add
-FLOPS_NEWTON = 16         # compensated pass: term (6), Neumaier (4), S' term (3), S'' term (3)
+# Algorithmic FP64 flops per (eigenvalue k, inner index j) pair, counted as the
+# peak counts them: a fused multiply-add is 2, an add, multiply or division 1
+# (the Newton refinement of the hardware reciprocal is not counted).
+FLOPS_SHIFT = 10          # (d_j - d_k) - tau (2), 1/den, t, t/den, 3 adds, fma for t/den^2 (2)
+FLOPS_TIP = 25            # TwoSum d_j - sigma (6), 1/dl, quotient + residual (7), DD add (11)
+FLOPS_ROOT_MODEL = 14     # per pass: delta' (2), nu delta' - 1 (2), q, 1/q, t, 1/pp (2), tp, tp3, 3 adds
+FLOPS_ROOT_BISECT = 7     # per pass: delta' (2), nu delta' - 1 (2), q, 1/q, add
+FLOPS_NEWTON = 22         # delta', pp (4), q, 1/q, t, corrected quotient (4), 1/pp, tp (2), tp3 (2),
+                          # Neumaier sum (4), 2 adds
 
 
 def flops_per_pair(root, passes_mean):
     """Algorithmic flops per (k, j) pair done by the eigenvalue kernel (k_eig): ||x|| comes
     from the Newton pass, so there is no separate norm pass."""
-    per = FLOPS_ROOT_RATIONAL if root == 1 else FLOPS_ROOT_BISECT
+    per = FLOPS_ROOT_MODEL if root == 1 else FLOPS_ROOT_BISECT
     return FLOPS_SHIFT + FLOPS_TIP + per * passes_mean + FLOPS_NEWTON
 
 
@@ -52,7 +54,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32768)
-    ap.add_argument("--root", type=int, default=1, help="0 bisection, 1 rational (default)")
+    ap.add_argument("--root", type=int, default=1, help="0 bisection, 1 model iteration (default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip batched / fwd+bwd / eigenvalues-only lines")
@@ -152,7 +154,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single DPR1 n={n}, all eigenvalues + full V (FP64), d~U[-1,1] sorted, "
                                f"z~N(0,1)/sqrt(n), rho=1, seed 2",
-                   "n": n, "root": "rational" if args.root == 1 else "bisection"},
+                   "n": n, "root": "model" if args.root == 1 else "bisection"},
         "roofline": {"bound": "alu", "kernel": "k_eig", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "flops_per_pair": fpp, "kernel_ms": eig_ms},

@@ -66,8 +66,8 @@ extern "C" {
 #define DPR1_STAT_SINGULAR 3  /* f(0) rounded to 0: lambda set to 0         */
 #define DPR1_STAT_ITERS_MAX 4 /* most root-finder passes for one eigenvalue */
 #define DPR1_STAT_ITERS_SUM 5 /* root-finder passes summed over eigenvalues */
-#define DPR1_STAT_CONTINUED 6 /* rational iterations finished by the
-                                 cooperative kernel after the pass budget   */
+#define DPR1_STAT_CONTINUED 6 /* root searches finished by the cooperative
+                                 kernel after the pass budget               */
 #define DPR1_NSTATS 8
 
 /* Options.  dpr1_default_opts fills the defaults noted below.               */
@@ -75,8 +75,11 @@ typedef struct dpr1_opts {
   int32_t mode_b;      /* tip b of A_i^{-1}: 0 double-double always (default);
                           1 double-double only when K_b > 100 (the paper's
                           gate); 2 never (the paper's dpr1eig_nd)            */
-  int32_t root;        /* 0 bisection (Alg. 1); 1 safeguarded rational
-                          secular solver (Sec. 2.2; default)                */
+  int32_t root;        /* 0 bisection (Alg. 1); 1 (default) safeguarded
+                          model iteration: the nearest pole exact plus one
+                          pole fitted to the value, slope and curvature of
+                          the rest of the secular sum (Sec. 2.2 leaves the
+                          root finder open)                                 */
   int32_t polish;      /* 1 (default): double-double Newton polish of roots
                           whose rounding amplification is large; 0 off     */
   int32_t split;       /* waves that share one block of 64 eigenvalues by
@@ -86,9 +89,10 @@ typedef struct dpr1_opts {
   double nearzero;     /* near-zero rule factor: recompute lambda from
                           A^{-1} when factor*|lambda| < distance to the
                           neighbouring poles; default 10, 0 disables        */
-  int32_t main_passes; /* rational solver: passes the eigenvalue kernel runs
+  int32_t main_passes; /* model solver: passes the eigenvalue kernel runs
                           before it hands an unconverged eigenpair to the
-                          cooperative kernel; 0 = default (4)              */
+                          cooperative kernel; 0 = default (2 for dpr1_eig,
+                          3 for dpr1_eig_batched)                          */
   int32_t reserved;
   void* events;        /* profiling hook, NULL (default) = off: a host array
                           of 4 hipEvent_t that the solve records on `stream`

@@ -128,6 +128,7 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
 // so all waves keep identical per-lane state.
 template <int NV>
 __device__ __forceinline__ void wg_sum(double (&v)[NV], int W, int wv, int lane, double* red) {
+  static_assert(NV <= 4, "the reduction buffer holds four values per lane and wave");
   if (W == 1) return;
 #pragma unroll
   for (int q = 0; q < NV; ++q) red[(q * W + wv) * WAVE + lane] = v[q];
@@ -262,38 +263,81 @@ __global__ void k_zero(int32_t* __restrict__ a, int n) {
 }
 
 // ------------------------------------------------------------------- eig
-// One step of the safeguarded rational iteration for the rightmost root of
-// g(t) = b' - t + S(t)/zeta_i^2 from its value g and the sum term's value Sz
-// and slope -Spz at m (the bracket [L, U] already updated with the sign of g):
-// the sum term is modelled by A/(t - xm) + B with the same value and slope;
-// all poles of S lie left of the model pole xm, so the model lies above S and
-// its root never undershoots: after the first step the iterates descend
-// monotonically.  A model root outside (L, U) is replaced by the bit midpoint.
-__device__ __forceinline__ void rational_step(double m, double g, double Sz, double Spz, double bp, double xm,
-                                              int iters, double L, double U, double& nu, double& nu0,
-                                              double& prevstep, bool& done) {
+// Root of the model of g at the current iterate m.  Written in poles,
+// g(t) = b' - t + sum_j w_j/(t - xi_j) with xi_j = 1/delta'_j and
+// w_j = zeta_j^2/(delta'_j^2 zeta_i^2); the wanted root lies right of every
+// pole.  The model keeps the nearest pole xm with its exact weight wm and
+// replaces the rest of the sum, R(t), by A/(t - p) + B fitted to R's value,
+// slope and curvature at m (Sz, Spz, Sppz are the moments of the whole sum:
+// S/zeta_i^2, sum w/(m - xi)^2, sum w/(m - xi)^3).  Every other pole lies
+// left of xm, so the fitted pole does too; the model is then convex and
+// decreasing right of its poles and its root is found by Newton's method
+// inside the bracket (L, U).  The model matches g to second order at m, so
+// the outer iteration converges cubically.
+__device__ __forceinline__ double model_root(double m, double Sz, double Spz, double Sppz, double bp, double xm,
+                                             double wm, double L, double U) {
+  double Rs = Sz, Rp = Spz, Rpp = Sppz;
+  if (wm > 0.0) {
+    const double ie = 1.0 / (m - xm);
+    const double tm = wm * ie;
+    Rs -= tm;
+    Rp -= tm * ie;
+    Rpp -= (tm * ie) * ie;
+  }
+  double p = xm, A = 0.0, B = Rs;
+  if (Rp > 0.0 && Rpp > 0.0) {
+    p = fmin(m - Rp / Rpp, xm);
+    const double x = m - p;
+    A = Rp * x * x;
+    B = Rs - Rp * x;
+  }
+  double lo = fmax(L, fmax(xm, p)), hi = U;
+  double t = m;
+  for (int q = 0; q < 40; ++q) {
+    const double e1 = 1.0 / (t - xm), e2 = 1.0 / (t - p);
+    const double a1 = wm * e1, a2 = A * e2;
+    const double h = ((bp - t) + B) + (a1 + a2);
+    if (h == 0.0) break;  // t is a root of the model
+    const double hp = -1.0 - (a1 * e1 + a2 * e2);
+    if (h > 0.0) lo = t; else hi = t;
+    double tn = t - h / hp;
+    if (!(tn > lo && tn < hi)) tn = (hi < INFINITY) ? 0.5 * (lo + hi) : 2.0 * t;
+    const bool fin = fabs(tn - t) <= 0x1p-52 * t;
+    t = tn;
+    if (fin) break;
+  }
+  return t;
+}
+
+// One step of the safeguarded iteration for the rightmost root of g from its
+// value g and moments at m (the bracket [L, U] already updated with the sign
+// of g).  A model root outside (L, U) is replaced by the bit midpoint, and so
+// is the next iterate of a two-cycle: g changed sign at the last two steps
+// while |g| fell by less than a factor 10 on the same side (g1, g2 keep the
+// two previous values of g).
+__device__ __forceinline__ void model_step(double m, double g, double Sz, double Spz, double Sppz, double bp,
+                                           double xm, double wm, int iters, double L, double U, double& nu,
+                                           double& nu0, double& prevstep, double& g1, double& g2, bool& done) {
   if (g == 0.0) {
     done = true;
     nu0 = m;
     return;
   }
-  double x = m - xm;
-  double Am = Spz * x * x;
-  double Bm = Sz - Spz * x;
-  double C = (bp + Bm) - xm;
-  double disc = sqrt(C * C + 4.0 * Am);
-  double u = C >= 0 ? (C + disc) * 0.5 : (2.0 * Am) / (disc - C);
-  double nn = xm + u;
-  double step = fabs(nn - m);
-  // Quadratic convergence: a step below 2^-26 leaves nn within about 2^-52
-  // of the root and the compensated Newton step that follows finishes the
-  // job; smaller steps would only chase the rounding noise of g.
-  if (step <= 0x1p-26 * m) {
+  const bool cycle = (g * g1 < 0.0) && (g1 * g2 < 0.0) && (fabs(g) > 0.1 * fabs(g2));
+  g2 = g1;
+  g1 = g;
+  const double nn0 = model_root(m, Sz, Spz, Sppz, bp, xm, wm, L, U);
+  double nn = nn0;
+  const double step = fabs(nn - m);
+  // Cubic convergence: after a step below 2^-20 the iterate is within about
+  // 2^-60 of the root up to the model's constant, and the compensated Newton
+  // step that follows finishes the job.
+  if (step <= 0x1p-20 * m) {
     done = true;
     nu0 = (nn >= L && nn <= U) ? nn : m;
     return;
   }
-  if (!(nn > L && nn < U)) {
+  if (!(nn > L && nn < U) || cycle) {
     if (adjacent(L, U)) {
       done = true;
       nu0 = U;
@@ -359,16 +403,18 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // The same pass also sums |terms| and terms/den (f' at the midpoint): the
   // midpoint is the first probe of the root finder, so its evaluation is reused.
   const double tau = (dkm1 - dk) / 2;
-  double Fs[3] = {0.0, 0.0, 0.0};
+  double Fs[4] = {0.0, 0.0, 0.0, 0.0};
   sweep(P, j0, j1, wlo, whi, [&](int j, int, const double* pq) {
     double dj = ldu(pq, 0), z2 = ldu(pq, 1);
     double r = rcp_1nr((dj - dk) - tau);
     double t = z2 * r;
+    double tr = t * r;
     Fs[0] += t;
     Fs[1] += fabs(t);
-    Fs[2] = __builtin_fma(t, r, Fs[2]);
+    Fs[2] += tr;
+    Fs[3] = __builtin_fma(tr, r, Fs[3]);
   });
-  wg_sum<3>(Fs, W, wv, lane, red);
+  wg_sum<4>(Fs, W, wv, lane, red);
   const double F = 1.0 + rho * Fs[0];
   const bool right = (kk == 0) || (F > 0);
   const int i = right ? kk : kk - 1;
@@ -426,7 +472,10 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // S(nu') = sum_{j!=i} zeta_j^2/(delta'_j (nu' delta'_j - 1)), delta' = s (d_j - sigma).
   const double nss = -s * sigma;
   const bool interior = kk > 0;
-  const double xm = interior ? 1.0 / (dkm1 - dk) : 0.0;  // pole nearest to the root (model pole)
+  const double xm = interior ? 1.0 / (dkm1 - dk) : 0.0;  // pole nearest to the root
+  // its weight zeta_jm^2/(delta'_jm^2 zeta_i^2), jm the other end of the gap
+  const double zjm = interior ? Zv[right ? kk - 1 : kk] : 0.0;
+  const double wm = interior ? ((zjm * xm) * (zjm * xm)) / zi2 : 0.0;
   double L, U, nu;
   if (interior) {
     L = xm;
@@ -442,7 +491,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // is badly conditioned
   bool done = !valid;
   int iters = 0;
-  double nu0 = nu, prevstep = INFINITY;
+  double nu0 = nu, prevstep = INFINITY, g1 = 0.0, g2 = 0.0;
   const double rz2 = 1.0 / zi2;
 
   // First probe of interior roots from the shift pass: g(nu') = f(lambda)/(rho
@@ -451,12 +500,16 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // upper bound of the root.  If rounding leaves the sign of g open the pole
   // is kept as the lower end.
   bool pre = interior && valid;
-  double pre_Sz = 0.0, pre_Spz = 0.0, pre_g = 0.0;
+  double pre_Sz = 0.0, pre_Spz = 0.0, pre_Sppz = 0.0, pre_g = 0.0;
   if (pre) {
     const double gerr = 8.0 * 2.220446049250313e-16 * (1.0 + rho * Fs[1]) / (rho * zi2);
     pre_g = s * (1.0 + rho * Fs[0]) / (rho * zi2);
     pre_Sz = (pre_g - bp) + nu;
+    // g' = -F2/(zeta_i^2 nu^2) and g'' = 2 (s F3/nu^4 + F2/nu^3)/zeta_i^2 with
+    // F2, F3 the sums of zeta_j^2/(d_j - lambda)^2 and ^3 (lambda = sigma + s/nu)
+    const double inu = 1.0 / nu;
     pre_Spz = fmax(Fs[2] / (zi2 * nu * nu) - 1.0, 0.0);
+    pre_Sppz = (((s * Fs[3]) * inu + Fs[2]) * (inu * inu * inu)) / zi2;
     U = (nu + fmax(pre_g, 0.0) + gerr) * GROW;
     if (pre_g > gerr) L = nu;
   }
@@ -497,49 +550,54 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       }
     }
   } else {
-    // -------- safeguarded rational iteration: at nu the sum term of g is
-    // modelled by A/(t - xm) + B (value and slope matched), whose root with
-    // the linear part b' - t is the next iterate.  Since all poles of S lie
-    // left of the model pole, the model lies above S, so the iterates come
-    // down monotonically onto the root after the first step.
+    // -------- safeguarded model iteration: every pass gives the value, slope
+    // and curvature of the sum term at nu; the root of the model built from
+    // them (the nearest pole exact, the rest one fitted pole) is the next
+    // iterate.
     const int budget = A.main_passes;
     int passes = 0;
     while (wave_any(!done)) {
       if (passes >= budget) break;  // the rest continue in the cooperative kernel
       double m = nu;
-      double S[2] = {0.0, 0.0};
+      double S[3] = {0.0, 0.0, 0.0};
       if (wave_any(!done && !pre)) {
         sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
           double dj = ldu(pq, 0), z2 = ldu(pq, 1);
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
           double rq = rcp_1nr(dl * pp);
-          double t = z2 * rq;
-          double tp = (t * dl) * (dl * rq);  // zeta_j^2/pp^2
+          double t = z2 * rq;           // w_j/(m - xi_j)
+          double u = (dl * rq) * dl;    // delta'_j/pp = 1/(m - xi_j)
+          double tp = t * u;            // w_j/(m - xi_j)^2
+          double tp3 = tp * u;          // w_j/(m - xi_j)^3
           if (seg == 1 && j == i) {
             t = 0.0;
             tp = 0.0;
+            tp3 = 0.0;
           }
           S[0] += t;
           S[1] += tp;
+          S[2] += tp3;
         });
-        wg_sum<2>(S, W, wv, lane, red);
+        wg_sum<3>(S, W, wv, lane, red);
         ++iters;
         ++passes;
       }
       if (!done) {
         double Sz = S[0] * rz2;
         double Spz = S[1] * rz2;  // -dS/dnu / zeta_i^2
+        double Sppz = S[2] * rz2;
         double g = (bp - m) + Sz;
         if (pre) {
           Sz = pre_Sz;
           Spz = pre_Spz;
+          Sppz = pre_Sppz;
           g = pre_g;
           pre = false;  // bracket already set from the probe
         } else {
           if (g > 0) L = m; else U = m;
         }
-        rational_step(m, g, Sz, Spz, bp, xm, iters, L, U, nu, nu0, prevstep, done);
+        model_step(m, g, Sz, Spz, Sppz, bp, xm, wm, iters, L, U, nu, nu0, prevstep, g1, g2, done);
       }
     }
   }
@@ -800,13 +858,15 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
     if (it.flags & FIX_CONTINUE) {
       // the rational iteration, continued with block-wide sums
       const double xm = (k > 0) ? 1.0 / (Dv[k - 1] - Dv[k]) : 0.0;
+      const double zjm = (k > 0) ? Zv[i == k ? k - 1 : k] : 0.0;
+      const double wm = (k > 0) ? ((zjm * xm) * (zjm * xm)) / zi2 : 0.0;
       const double bp = it.bhi, rz2 = 1.0 / zi2;
-      double nu = it.cnu, L = it.cL, U = it.cU, prevstep = it.cprev;
+      double nu = it.cnu, L = it.cL, U = it.cU, prevstep = it.cprev, g1 = 0.0, g2 = 0.0;
       int iters = it.iters;
       bool done = false;
       while (!done) {
         const double m = nu;
-        double S = 0.0, Sq = 0.0;
+        double S = 0.0, Sq = 0.0, Sc = 0.0;
         for (int j = tid; j < n; j += FIXT) {
           if (j == i) continue;
           double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
@@ -814,16 +874,20 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
           double pp = __builtin_fma(m, dl, -1.0);
           double rq = rcp_1nr(dl * pp);
           double t = z2 * rq;
+          double u = (dl * rq) * dl;
+          double tp = t * u;
           S += t;
-          Sq += (t * dl) * (dl * rq);
+          Sq += tp;
+          Sc += tp * u;
         }
         S = block_sum(S, sm);
         Sq = block_sum(Sq, sm);
+        Sc = block_sum(Sc, sm);
         ++iters;
-        double Sz = S * rz2, Spz = Sq * rz2;
+        double Sz = S * rz2, Spz = Sq * rz2, Sppz = Sc * rz2;
         double g = (bp - m) + Sz;
         if (g > 0) L = m; else U = m;
-        rational_step(m, g, Sz, Spz, bp, xm, iters, L, U, nu, nu0, prevstep, done);
+        model_step(m, g, Sz, Spz, Sppz, bp, xm, wm, iters, L, U, nu, nu0, prevstep, g1, g2, done);
       }
       // compensated Newton step, kappa_g and ||x|| as in the eigenvalue kernel
       double cs = 0.0, cc = 0.0, sp = 0.0, sp3 = 0.0;
@@ -1239,7 +1303,10 @@ static int64_t count_groups(int64_t nprob, const int64_t* offs) {
   return c;
 }
 
-static size_t red_bytes(int W) { return W > 1 ? sizeof(double) * 2 * W * WAVE : 0; }
+// LDS of k_eig's cross-wave reductions: the widest, wg_sum<RED_NV>, stores
+// RED_NV values per lane and wave.
+constexpr int RED_NV = 4;
+static size_t red_bytes(int W) { return W > 1 ? sizeof(double) * RED_NV * W * WAVE : 0; }
 
 }  // namespace dpr1
 
@@ -1298,7 +1365,10 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   A.want_v = V != nullptr;
   A.kappa_polish = o.kappa_polish;
   A.nearzero = o.nearzero;
-  A.main_passes = o.main_passes > 0 ? o.main_passes : 4;
+  // Default budget: the single-problem launch leaves the stragglers (under a
+  // tenth of the roots) to one block each in k_fix; a batch of small problems
+  // would queue many of them per block there, so it runs one more pass.
+  A.main_passes = o.main_passes > 0 ? o.main_passes : (persistent_grid ? 3 : 2);
 
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, A.ctr, 16);
   if (stats) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, stats, DPR1_NSTATS);
