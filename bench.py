@@ -129,8 +129,11 @@ def main():
     log(f"[bench] {ms_step:.3f} ms/step, k_eig {eig_ms:.3f} ms, k_vec {vec_ms:.3f} ms ({vec_gbs:.0f} GB/s), "
         f"{value:.4g} eigenpairs/s, iters/eig {iters_mean:.2f}, stats {st}")
 
+    # HBM bytes of one k_eig launch from the FETCH_SIZE / WRITE_SIZE counters,
+    # scaled by the copy-kernel calibration; used only while the kernel
+    # sources are the ones the counters were taken on
     traffic = None
-    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    tf = os.path.join(ROOT, "profiles", f"k_eig_n{n}_traffic.txt")
     if os.path.exists(tf):
         try:
             tj = json.load(open(tf))
