@@ -33,15 +33,16 @@ FLOPS_SHIFT = 10          # (d_j - d_k) - tau (2), 1/den, t, t/den, 3 adds, fma 
 FLOPS_TIP = 25            # TwoSum d_j - sigma (6), 1/dl, quotient + residual (7), DD add (11)
 FLOPS_ROOT_MODEL = 14     # per pass: delta' (2), nu delta' - 1 (2), q, 1/q, t, 1/pp (2), tp, tp3, 3 adds
 FLOPS_ROOT_BISECT = 7     # per pass: delta' (2), nu delta' - 1 (2), q, 1/q, add
-FLOPS_NEWTON = 22         # delta', pp (4), q, 1/q, t, corrected quotient (4), 1/pp, tp (2), tp3 (2),
-                          # Neumaier sum (4), 2 adds
+FLOPS_FINAL = 23          # accurate last pass: delta', pp (4), q, 1/q, t, corrected quotient (4),
+                          # 1/pp (2), tp, tp3, tp4, Neumaier sum (4), 3 adds
 
 
 def flops_per_pair(root, passes_mean):
-    """Algorithmic flops per (k, j) pair done by the eigenvalue kernel (k_eig): ||x|| comes
-    from the Newton pass, so there is no separate norm pass."""
+    """Algorithmic flops per (k, j) pair done by the eigenvalue kernel (k_eig): the shift pass,
+    the tip, `passes_mean` plain root-finder passes and the accurate last pass (which also gives
+    ||x||)."""
     per = FLOPS_ROOT_MODEL if root == 1 else FLOPS_ROOT_BISECT
-    return FLOPS_SHIFT + FLOPS_TIP + per * passes_mean + FLOPS_NEWTON
+    return FLOPS_SHIFT + FLOPS_TIP + per * passes_mean + FLOPS_FINAL
 
 
 def log(msg):

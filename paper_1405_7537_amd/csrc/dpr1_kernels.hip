@@ -301,10 +301,14 @@ __device__ __forceinline__ double model_root(double m, double Sz, double Spz, do
     const double hp = -1.0 - (a1 * e1 + a2 * e2);
     if (h > 0.0) lo = t; else hi = t;
     double tn = t - h / hp;
+    // a step below the resolution of t ends the iteration (t may sit on the
+    // bracket end it has just set, where tn == t would fail the test below)
+    if (fabs(tn - t) <= 0x1p-52 * t) {
+      t = tn;
+      break;
+    }
     if (!(tn > lo && tn < hi)) tn = (hi < INFINITY) ? 0.5 * (lo + hi) : 2.0 * t;
-    const bool fin = fabs(tn - t) <= 0x1p-52 * t;
     t = tn;
-    if (fin) break;
   }
   return t;
 }
@@ -317,7 +321,8 @@ __device__ __forceinline__ double model_root(double m, double Sz, double Spz, do
 // two previous values of g).
 __device__ __forceinline__ void model_step(double m, double g, double Sz, double Spz, double Sppz, double bp,
                                            double xm, double wm, int iters, double L, double U, double& nu,
-                                           double& nu0, double& prevstep, double& g1, double& g2, bool& done) {
+                                           double& nu0, double& prevstep, double& g1, double& g2, bool& done,
+                                           double tol = 0x1p-20) {
   if (g == 0.0) {
     done = true;
     nu0 = m;
@@ -330,9 +335,10 @@ __device__ __forceinline__ void model_step(double m, double g, double Sz, double
   double nn = nn0;
   const double step = fabs(nn - m);
   // Cubic convergence: after a step below 2^-20 the iterate is within about
-  // 2^-60 of the root up to the model's constant, and the compensated Newton
-  // step that follows finishes the job.
-  if (step <= 0x1p-20 * m) {
+  // 2^-60 of the root up to the model's constant, and the accurate last pass
+  // finishes the job.  That pass accepts its own step only below 2^-30 (tol),
+  // so that even a large model constant leaves the root exact to rounding.
+  if (step <= tol * m) {
     done = true;
     nu0 = (nn >= L && nn <= U) ? nn : m;
     return;
@@ -553,13 +559,14 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     // -------- safeguarded model iteration: every pass gives the value, slope
     // and curvature of the sum term at nu; the root of the model built from
     // them (the nearest pole exact, the rest one fitted pole) is the next
-    // iterate.
-    const int budget = A.main_passes;
+    // iterate.  The last pass of the budget is the accurate one below; a pass
+    // taken while some lane still starts from the probe is not counted.
+    const int budget = max(A.main_passes, 1);
     int passes = 0;
-    while (wave_any(!done)) {
-      if (passes >= budget) break;  // the rest continue in the cooperative kernel
+    while (passes < budget - 1 && wave_any(!done)) {
       double m = nu;
       double S[3] = {0.0, 0.0, 0.0};
+      const bool anypre = wave_any(pre);
       if (wave_any(!done && !pre)) {
         sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
           double dj = ldu(pq, 0), z2 = ldu(pq, 1);
@@ -581,7 +588,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
         });
         wg_sum<3>(S, W, wv, lane, red);
         ++iters;
-        ++passes;
+        if (!anypre) ++passes;
       }
       if (!done) {
         double Sz = S[0] * rz2;
@@ -601,44 +608,62 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       }
     }
   }
-  const bool cont = valid && !done;  // unfinished: continued in k_fix
 
-  // ---- one Newton step with a compensated sum, and the amplification
-  // estimate kappa_g = (|b| + |nu| + S)/(|nu| |g'|).
+  // ---- accurate pass at m: compensated sum of the secular terms (each a
+  // corrected quotient), the moments for the last step, the amplification
+  // estimate kappa_g = (|b| + |nu| + S)/(|nu| |g'|) and ||x||.  After
+  // bisection m is the converged bracket end and the last step is Newton's;
+  // in the model iteration m is the converged iterate (or the next one for a
+  // lane that has not converged) and the last step is the model's, which is
+  // accepted when it is below 2^-30 relative.  Right of every pole all terms
+  // are positive, so the Neumaier sum takes the larger operand first by value.
+  const double m = (A.root == 0 || done) ? nu0 : nu;
   double cs = 0.0, cc = 0.0;
-  double Sp[2] = {0.0, 0.0};
-  {
-    const double m = nu0;
-    sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
-      double dj = ldu(pq, 0), z2 = ldu(pq, 1);
-      double dl = __builtin_fma(s, dj, nss);
-      double pp = __builtin_fma(m, dl, -1.0);
-      double q = dl * pp;
-      double r = rcp_nr(q);
-      double t = z2 * r;
-      t = __builtin_fma(__builtin_fma(-t, q, z2), r, t);  // corrected quotient
-      double ir = dl * r;                                 // 1/pp
-      double tp = (t * dl) * ir;                          // zeta_j^2/pp^2
-      double tp3 = (tp * ir) * dl;                        // zeta_j^2 delta'_j/pp^3
-      if (seg == 1 && j == i) {
-        t = 0.0;
-        tp = 0.0;
-        tp3 = 0.0;
-      }
-      double y = cs + t;
-      cc += (fabs(cs) >= fabs(t)) ? ((cs - y) + t) : ((t - y) + cs);
-      cs = y;
-      Sp[0] += tp;
-      Sp[1] += tp3;
-    });
-    wg_sum_comp(cs, cc, W, wv, lane, red);
-    wg_sum<2>(Sp, W, wv, lane, red);
-  }
+  double Sp[3] = {0.0, 0.0, 0.0};
+  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
+    double dj = ldu(pq, 0), z2 = ldu(pq, 1);
+    double dl = __builtin_fma(s, dj, nss);
+    double pp = __builtin_fma(m, dl, -1.0);
+    double q = dl * pp;
+    double r = rcp_1nr(q);
+    double t = z2 * r;
+    t = __builtin_fma(__builtin_fma(-t, q, z2), r, t);  // corrected quotient
+    double u = (dl * r) * dl;                           // 1/(m - xi_j)
+    double tp = t * u;                                  // zeta_j^2/pp^2
+    double tp3 = tp * u;                                // zeta_j^2 delta'_j/pp^3
+    double tp4 = tp3 * u;                               // zeta_j^2 delta'_j^2/pp^4
+    if (seg == 1 && j == i) {
+      t = 0.0;
+      tp = 0.0;
+      tp3 = 0.0;
+      tp4 = 0.0;
+    }
+    const double hi = fmax(cs, t), lo = fmin(cs, t);
+    const double y = hi + lo;
+    cc += (hi - y) + lo;
+    cs = y;
+    Sp[0] += tp;
+    Sp[1] += tp3;
+    Sp[2] += tp4;
+  });
+  wg_sum_comp(cs, cc, W, wv, lane, red);
+  wg_sum<3>(Sp, W, wv, lane, red);
   const double Sz = (cs + cc) / zi2;
-  const double g = (bp - nu0) + Sz;
+  const double g = (bp - m) + Sz;
   const double gp = -1.0 - Sp[0] / zi2;
-  const double nu1 = nu0 - g / gp;
-  const double kap = (fabs(bp) + nu0 + Sz) / (nu0 * fabs(gp));
+  const double kap = (fabs(bp) + m + Sz) / (m * fabs(gp));
+  double nu1 = m;
+  bool fin = true;
+  if (A.root == 0) {
+    nu1 = m - g / gp;
+  } else if (valid) {
+    fin = false;
+    if (g > 0) L = m; else if (g < 0) U = m;
+    double nn = m;
+    model_step(m, g, Sz, Sp[0] / zi2, Sp[1] / zi2, bp, xm, wm, iters, L, U, nu, nn, prevstep, g1, g2, fin);
+    if (fin) nu1 = nn;
+  }
+  const bool cont = valid && !fin;  // unfinished: continued in k_fix
   double muv = s / nu1;
   double lam = sigma + muv;
   double amp = fabs(muv / lam);
@@ -653,10 +678,12 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
 
   // ---- ||x|| scaled by |mu|: with delta_j - mu = s (delta'_j - 1/nu) one has
   // mu/(delta_j - mu) = 1/(nu delta'_j - 1), so |mu|^2 ||x||^2 =
-  // zeta_i^2 + sum_{j != i} zeta_j^2/pp_j^2, the S' sum of the Newton pass.
-  // That sum is taken at nu0; carried to nu1 to first order with its
-  // derivative -2 sum zeta_j^2 delta'_j/pp_j^3 (error O((nu1 - nu0)^2)).
-  double Nx[1] = {zi2 + (Sp[0] - 2.0 * (nu1 - nu0) * Sp[1])};
+  // zeta_i^2 + sum_{j != i} zeta_j^2/pp_j^2, the S' sum of the accurate pass.
+  // That sum is taken at m and carried to nu1 = m + h by its Taylor series to
+  // second order (derivatives -2 sum zeta^2 delta'/pp^3 and 6 sum zeta^2
+  // delta'^2/pp^4; |h|/(m - xi_j) <= 2^-29, so the error is below 2^-85).
+  const double h = nu1 - m;
+  double Nx[1] = {zi2 + ((Sp[0] - 2.0 * h * Sp[1]) + 3.0 * (h * h) * Sp[2])};
   if (wv == 0 && valid) {
     A.ii[off + k] = i;
     A.mu[off + k] = muv;
@@ -671,7 +698,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       it.flags = (pol ? FIX_POLISH : 0) | (nz ? FIX_NEARZERO : 0) | (cont ? FIX_CONTINUE : 0);
       it.iters = iters;
       it.pad = 0;
-      it.nu0 = nu0;
+      it.nu0 = m;
       it.nu1 = nu1;
       it.bhi = bp;
       it.blo = s * bl;
