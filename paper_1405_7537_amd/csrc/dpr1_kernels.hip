@@ -194,25 +194,35 @@ __device__ __forceinline__ void sweep(const double* P, int j0, int j1, int wlo, 
 }
 
 // ------------------------------------------------------------------ prep
-__global__ void __launch_bounds__(256) k_prep(int nprob, const int64_t* __restrict__ offs, int64_t n_single,
-                                              const double* __restrict__ d, const double* __restrict__ z,
-                                              const double* __restrict__ rho_dev, double rho_host,
-                                              Meta* __restrict__ meta, double* __restrict__ sd,
+// nsplit == 1: block p stages problem p and writes its meta.  nsplit > 1 (a
+// single problem): block b stages one slice and leaves its partial sum and
+// flags in `part`; the last block to finish adds the partials in slice order
+// (so the result does not depend on the order the blocks ran in) and writes
+// the meta.
+constexpr int PREP_MAX_SPLIT = 64;
+__global__ void __launch_bounds__(256) k_prep(int nprob, int nsplit, const int64_t* __restrict__ offs,
+                                              int64_t n_single, const double* __restrict__ d,
+                                              const double* __restrict__ z, const double* __restrict__ rho_dev,
+                                              double rho_host, Meta* __restrict__ meta, double* __restrict__ sd,
                                               double* __restrict__ sz, double* __restrict__ pairs,
-                                              double* __restrict__ z2lo, int32_t* __restrict__ info) {
-  int p = blockIdx.x;
+                                              double* __restrict__ z2lo, int32_t* __restrict__ info,
+                                              double2* __restrict__ part, int32_t* __restrict__ done_ctr) {
+  const int p = nsplit == 1 ? (int)blockIdx.x : 0;
+  const int bs = nsplit == 1 ? 0 : (int)blockIdx.x;
   if (p >= nprob) return;
-  int64_t off = offs ? offs[p] : 0;
-  int64_t n = offs ? offs[p + 1] - offs[p] : n_single;
-  double rho = rho_dev ? rho_dev[p] : rho_host;
-  int neg = rho < 0;
+  const int64_t off = offs ? offs[p] : 0;
+  const int64_t n = offs ? offs[p + 1] - offs[p] : n_single;
+  const double rho = rho_dev ? rho_dev[p] : rho_host;
+  const int neg = rho < 0;
+  const int64_t chunk = (n + nsplit - 1) / nsplit;
+  const int64_t ja = min(n, (int64_t)bs * chunk), jb = min(n, ja + chunk);
   __shared__ double red[256];
-  __shared__ int flags;
+  __shared__ int flags, last;
   if (threadIdx.x == 0) flags = 0;
   __syncthreads();
   int f = 0;
   double acc = 0.0;
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+  for (int64_t j = ja + threadIdx.x; j < jb; j += blockDim.x) {
     int64_t src = neg ? n - 1 - j : j;
     double dj = d[off + src], zj = z[off + src];
     if (!isfinite(dj) || !isfinite(zj)) f |= 4;
@@ -238,12 +248,33 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, const int64_t* __restri
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
+  double zz = red[0];
+  int fl = flags;
+  if (nsplit > 1) {
+    if (threadIdx.x == 0) {
+      part[bs] = make_double2(zz, (double)fl);
+      __threadfence();
+      last = atomicAdd(done_ctr, 1) == nsplit - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x == 0) {
+      const volatile double2* vp = part;
+      zz = 0.0;
+      fl = 0;
+      for (int q = 0; q < nsplit; ++q) {
+        zz += vp[q].x;
+        fl |= (int)vp[q].y;
+      }
+    }
+  }
   if (threadIdx.x == 0) {
     int code = 0;
     if (!isfinite(rho) || rho == 0.0) code = DPR1_INFO_BAD_RHO;
-    else if (flags & 4) code = DPR1_INFO_NONFINITE;
-    else if (flags & 1) code = DPR1_INFO_UNSORTED;
-    else if (flags & 2) code = DPR1_INFO_ZERO_Z;
+    else if (fl & 4) code = DPR1_INFO_NONFINITE;
+    else if (fl & 1) code = DPR1_INFO_UNSORTED;
+    else if (fl & 2) code = DPR1_INFO_ZERO_Z;
     Meta m;
     m.off = off;
     m.n = (int32_t)n;
@@ -251,7 +282,7 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, const int64_t* __restri
     m.info = code;
     m.pad = 0;
     m.rho = fabs(rho);
-    m.zz = red[0];
+    m.zz = zz;
     meta[p] = m;
     if (info) info[p] = code;
   }
@@ -1113,14 +1144,17 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
                                              double* __restrict__ cinv, double* __restrict__ lam_out,
                                              int32_t* __restrict__ idx_out, double* __restrict__ mu_out,
                                              double* __restrict__ xn_out) {
-  int p = blockIdx.y;
+  // a batch: block p handles problem p; one problem: the grid strides over it
+  const int p = nprob > 1 ? (int)blockIdx.x : 0;
+  const int k0 = nprob > 1 ? (int)threadIdx.x : (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int kstep = nprob > 1 ? (int)blockDim.x : (int)(gridDim.x * blockDim.x);
   if (p >= nprob) return;
   const Meta M = meta[p];
   const int n = M.n;
   if (M.info != 0) {
     // rejected problem: the solver wrote nothing; leave defined outputs
     // (NaN values, in-range shift indices) and no eigenvector constants
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    for (int k = k0; k < n; k += kstep) {
       int64_t b = M.off + k;
       lam_out[b] = NAN;
       if (idx_out) idx_out[b] = k;
@@ -1129,7 +1163,7 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
     }
     return;
   }
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+  for (int k = k0; k < n; k += kstep) {
     int ko = M.neg ? n - 1 - k : k;
     int64_t a = M.off + k, b = M.off + ko;
     double sg = M.neg ? -1.0 : 1.0;
@@ -1274,7 +1308,7 @@ __global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, co
 
 // ===================================================================== host
 struct Layout {
-  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, csig, cinv, fix, items, groups, ctr, total;
+  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, csig, cinv, fix, items, groups, part, ctr, total;
 };
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1296,6 +1330,7 @@ static Layout layout(int64_t nprob, int64_t N, int64_t nitems, int64_t ngroups =
   L.fix = o; o = al(o + sizeof(FixItem) * N);
   L.items = o; o = al(o + sizeof(int2) * nitems);
   L.groups = o; o = al(o + sizeof(int4) * ngroups);
+  L.part = o; o = al(o + sizeof(double2) * PREP_MAX_SPLIT);
   L.ctr = o; o = al(o + 64);
   L.total = o;
   return L;
@@ -1399,9 +1434,10 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
 
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, A.ctr, 16);
   if (stats) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, stats, DPR1_NSTATS);
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)nprob), dim3(256), 0, st, (int)nprob, offs, n_single, d, z,
-                     rho_dev, rho_host, meta, (double*)A.sd, (double*)A.sz, (double*)A.pairs,
-                     (double*)A.z2lo, info);
+  const int nsplit = nprob == 1 ? (int)std::min<int64_t>(PREP_MAX_SPLIT, std::max<int64_t>(1, N / 512)) : 1;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)(nsplit > 1 ? nsplit : nprob)), dim3(256), 0, st, (int)nprob, nsplit,
+                     offs, n_single, d, z, rho_dev, rho_host, meta, (double*)A.sd, (double*)A.sz,
+                     (double*)A.pairs, (double*)A.z2lo, info, (double2*)(w + L.part), A.ctr + 8);
   HIPCHECK(hipGetLastError());
   hipEvent_t* ev = (hipEvent_t*)o.events;
   unsigned grid = persistent_grid ? (unsigned)persistent_grid : (unsigned)nitems;
@@ -1416,7 +1452,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   (void)nmax;
   double* csig = (double*)(w + L.csig);
   double* cinv = (double*)(w + L.cinv);
-  hipLaunchKernelGGL(k_out, dim3(offs ? 1 : (unsigned)std::min<int64_t>((N + 255) / 256, 1024), (unsigned)nprob),
+  hipLaunchKernelGGL(k_out, dim3(nprob > 1 ? (unsigned)nprob : (unsigned)std::min<int64_t>((N + 255) / 256, 1024)),
                      dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, A.sd, csig, cinv, lambda,
                      shift_idx, mu, xnorm);
   HIPCHECK(hipGetLastError());

@@ -133,3 +133,16 @@ def test_large_and_odd_sizes(D, orc):
     for p in range(len(sizes)):
         el, ev = check_problem(b, orc, d, z, rho, offs, p)
         assert el <= LAM_TOL and ev <= VEC_TOL, (p, sizes[p], el, ev)
+
+
+def test_more_problems_than_a_grid_row(D, orc):
+    """70000 tiny problems: more than 65535, the largest second grid dimension, so every
+    per-problem launch must index problems along the first one."""
+    rng = np.random.default_rng(21)
+    sizes = rng.integers(1, 6, 70000)
+    d, z, rho, offs = W.batched(len(sizes), 9, sizes=sizes)
+    print(f"[batched] {len(sizes)} problems, total n {offs[-1]}", flush=True)
+    b = D.eig_batched(d, z, rho, offs)
+    for p in list(range(5)) + list(range(65530, 65540)) + [69999]:
+        el, ev = check_problem(b, orc, d, z, rho, offs, p)
+        assert el <= LAM_TOL and ev <= VEC_TOL, (p, sizes[p], el, ev)
