@@ -436,10 +436,22 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   const double dk = Dv[kk];
   const double dkm1 = kk > 0 ? Dv[kk - 1] : 0.0;
 
+  // bracket of the exterior root (k = 1): d_1 + rho zeta_1^2 <= lambda_1 <=
+  // d_1 + rho ||z||^2, in nu = 1/(lambda_1 - d_1)
+  double Lx = 0.0, Ux = 0.0, nux = 0.0;
+  if (kk == 0) {
+    const double z0 = Zv[0];
+    Lx = (1.0 / (rho * M.zz)) / GROW;
+    Ux = (1.0 / (rho * (z0 * z0))) * GROW;
+    nux = A.root ? Ux : fmid(Lx, Ux);
+  }
+
   // ---- shift (Alg. 1): F = 1 + rho sum zeta_j^2/((d_j - d_k) - tau)
   // The same pass also sums |terms| and terms/den (f' at the midpoint): the
   // midpoint is the first probe of the root finder, so its evaluation is reused.
-  const double tau = (dkm1 - dk) / 2;
+  // For k = 1 there is no shift to choose; the pass evaluates f at the first
+  // point of the root search instead, lambda = d_1 + 1/nux.
+  const double tau = kk > 0 ? (dkm1 - dk) / 2 : 1.0 / nux;
   double Fs[4] = {0.0, 0.0, 0.0, 0.0};
   sweep(P, j0, j1, wlo, whi, [&](int j, int, const double* pq) {
     double dj = ldu(pq, 0), z2 = ldu(pq, 1);
@@ -519,9 +531,9 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     U = INFINITY;
     nu = 2.0 * xm;  // mu at the midpoint of the gap: the nearest-pole bound
   } else {
-    L = (1.0 / (rho * M.zz)) / GROW;  // lambda_1 <= d_1 + rho ||z||^2
-    U = (1.0 / (rho * zi2)) * GROW;   // lambda_1 >= d_1 + rho zeta_1^2
-    nu = A.root ? U : fmid(L, U);
+    L = Lx;
+    U = Ux;
+    nu = nux;
   }
   // the rigorous bracket [L0, U0] (set below) is kept for the double-double
   // polish: the signs of g seen by the binary64 iteration can be wrong when g
@@ -531,12 +543,13 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   double nu0 = nu, prevstep = INFINITY, g1 = 0.0, g2 = 0.0;
   const double rz2 = 1.0 / zi2;
 
-  // First probe of interior roots from the shift pass: g(nu') = f(lambda)/(rho
-  // zeta_i^2) up to the sign s (eqs. secAi, Pick), lambda the midpoint, so
-  // g >= 0 there by the choice of the shift; b' + S/zeta_i^2 = g + nu' is an
-  // upper bound of the root.  If rounding leaves the sign of g open the pole
-  // is kept as the lower end.
-  bool pre = interior && valid;
+  // First probe from the shift pass: g(nu') = f(lambda)/(rho zeta_i^2) up to
+  // the sign s (eqs. secAi, Pick).  For an interior root lambda is the gap
+  // midpoint, so g >= 0 there by the choice of the shift; b' + S/zeta_i^2 =
+  // g + nu' is then an upper bound of the root (S decreases).  If rounding
+  // leaves the sign of g open the pole is kept as the lower end.  For k = 1
+  // the probe may lie on either side of the root.
+  bool pre = valid;
   double pre_Sz = 0.0, pre_Spz = 0.0, pre_Sppz = 0.0, pre_g = 0.0;
   if (pre) {
     const double gerr = 8.0 * 2.220446049250313e-16 * (1.0 + rho * Fs[1]) / (rho * zi2);
@@ -547,8 +560,15 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     const double inu = 1.0 / nu;
     pre_Spz = fmax(Fs[2] / (zi2 * nu * nu) - 1.0, 0.0);
     pre_Sppz = (((s * Fs[3]) * inu + Fs[2]) * (inu * inu * inu)) / zi2;
-    U = (nu + fmax(pre_g, 0.0) + gerr) * GROW;
-    if (pre_g > gerr) L = nu;
+    if (interior) {
+      U = (nu + fmax(pre_g, 0.0) + gerr) * GROW;
+      if (pre_g > gerr) L = nu;
+    } else if (pre_g > gerr) {
+      L = nu;
+      U = fmin(U, (nu + pre_g + gerr) * GROW);
+    } else if (pre_g < -gerr) {
+      U = nu;
+    }
   }
   const double L0 = L, U0 = U;
 
@@ -590,14 +610,12 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     // -------- safeguarded model iteration: every pass gives the value, slope
     // and curvature of the sum term at nu; the root of the model built from
     // them (the nearest pole exact, the rest one fitted pole) is the next
-    // iterate.  The last pass of the budget is the accurate one below; a pass
-    // taken while some lane still starts from the probe is not counted.
+    // iterate.  The last pass of the budget is the accurate one below.
     const int budget = max(A.main_passes, 1);
     int passes = 0;
     while (passes < budget - 1 && wave_any(!done)) {
       double m = nu;
       double S[3] = {0.0, 0.0, 0.0};
-      const bool anypre = wave_any(pre);
       if (wave_any(!done && !pre)) {
         sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
           double dj = ldu(pq, 0), z2 = ldu(pq, 1);
@@ -619,7 +637,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
         });
         wg_sum<3>(S, W, wv, lane, red);
         ++iters;
-        if (!anypre) ++passes;
+        ++passes;
       }
       if (!done) {
         double Sz = S[0] * rz2;
