@@ -899,13 +899,21 @@ __device__ __forceinline__ double block_sum_comp(double s, double c, double* sm)
   return S + C;
 }
 
-// One block of FIXT threads per flagged eigenpair; the inner index is strided
-// over the block and every pass ends in a block-wide sum.
+// One block of FIXT threads per flagged eigenpair at a time; the inner index
+// is strided over the block and every pass ends in a block-wide sum.
 __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
   __shared__ double sm[8];
+  __shared__ int next;
   const int tid = threadIdx.x;
   const int cnt = A.ctr[0];
-  for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+  for (;;) {
+    // items are taken from a queue, so a block that drew cheap items takes
+    // more of them (polish steps cost several times a continued root's)
+    if (tid == 0) next = atomicAdd(&A.ctr[2], 1);
+    __syncthreads();
+    const int e = next;
+    __syncthreads();
+    if (e >= cnt) break;
     const FixItem it = A.fix[e];
     const Meta M = A.meta[it.p];
     const int n = M.n;
@@ -913,6 +921,7 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
     const double* Dv = A.sd + off;
     const double* Zv = A.sz + off;
     const double* Z2 = A.pairs + 2 * off;
+    const double2* Z2v = reinterpret_cast<const double2*>(Z2);  // (d_j, zeta_j^2), 16-byte aligned
     const double* Zl = A.z2lo + off;
     const double rho = M.rho;
     const int k = it.k, i = it.i;
@@ -932,66 +941,57 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
     bool have_xs = false;
 
     if (it.flags & FIX_CONTINUE) {
-      // the rational iteration, continued with block-wide sums
+      // the root search continued with block-wide sums; every pass is the
+      // accurate one of the eigenvalue kernel (compensated sum, corrected
+      // quotients, derivative sums up to the third), so the pass whose model
+      // step is accepted also gives kappa_g and ||x||
       const double xm = (k > 0) ? 1.0 / (Dv[k - 1] - Dv[k]) : 0.0;
       const double zjm = (k > 0) ? Zv[i == k ? k - 1 : k] : 0.0;
       const double wm = (k > 0) ? ((zjm * xm) * (zjm * xm)) / zi2 : 0.0;
-      const double bp = it.bhi, rz2 = 1.0 / zi2;
+      const double bp = it.bhi;
       double nu = it.cnu, L = it.cL, U = it.cU, prevstep = it.cprev, g1 = 0.0, g2 = 0.0;
       int iters = it.iters;
       bool done = false;
+      double m = nu, Sz = 0.0, sp = 0.0, sp3 = 0.0, sp4 = 0.0;
       while (!done) {
-        const double m = nu;
-        double S = 0.0, Sq = 0.0, Sc = 0.0;
+        m = nu;
+        double cs = 0.0, cc = 0.0;
+        sp = 0.0;
+        sp3 = 0.0;
+        sp4 = 0.0;
+#pragma unroll 4
         for (int j = tid; j < n; j += FIXT) {
           if (j == i) continue;
-          double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
-          double dl = __builtin_fma(s, dj, -s * sigma);
-          double pp = __builtin_fma(m, dl, -1.0);
-          double rq = rcp_1nr(dl * pp);
-          double t = z2 * rq;
-          double u = (dl * rq) * dl;
-          double tp = t * u;
-          S += t;
-          Sq += tp;
-          Sc += tp * u;
+          const double2 pj = Z2v[j];
+          const double dl = __builtin_fma(s, pj.x, -s * sigma);
+          const double pp = __builtin_fma(m, dl, -1.0);
+          const double q = dl * pp;
+          const double r = rcp_1nr(q);
+          double t = pj.y * r;
+          t = __builtin_fma(__builtin_fma(-t, q, pj.y), r, t);  // corrected quotient
+          const double u = (dl * r) * dl;                       // 1/(m - xi_j)
+          const double tp = t * u;
+          const double tp3 = tp * u;
+          const double hi = fmax(cs, t), lo = fmin(cs, t);     // positive terms
+          const double y = hi + lo;
+          cc += (hi - y) + lo;
+          cs = y;
+          sp += tp;
+          sp3 += tp3;
+          sp4 += tp3 * u;
         }
-        S = block_sum(S, sm);
-        Sq = block_sum(Sq, sm);
-        Sc = block_sum(Sc, sm);
+        Sz = block_sum_comp(cs, cc, sm) / zi2;
+        sp = block_sum(sp, sm);
+        sp3 = block_sum(sp3, sm);
+        sp4 = block_sum(sp4, sm);
         ++iters;
-        double Sz = S * rz2, Spz = Sq * rz2, Sppz = Sc * rz2;
-        double g = (bp - m) + Sz;
-        if (g > 0) L = m; else U = m;
-        model_step(m, g, Sz, Spz, Sppz, bp, xm, wm, iters, L, U, nu, nu0, prevstep, g1, g2, done);
+        const double g = (bp - m) + Sz;
+        if (g > 0) L = m; else if (g < 0) U = m;
+        model_step(m, g, Sz, sp / zi2, sp3 / zi2, bp, xm, wm, iters, L, U, nu, nu0, prevstep, g1, g2, done);
       }
-      // compensated Newton step, kappa_g and ||x|| as in the eigenvalue kernel
-      double cs = 0.0, cc = 0.0, sp = 0.0, sp3 = 0.0;
-      for (int j = tid; j < n; j += FIXT) {
-        if (j == i) continue;
-        double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
-        double dl = __builtin_fma(s, dj, -s * sigma);
-        double pp = __builtin_fma(nu0, dl, -1.0);
-        double q = dl * pp;
-        double r = rcp_nr(q);
-        double t = z2 * r;
-        t = __builtin_fma(__builtin_fma(-t, q, z2), r, t);
-        double ir = dl * r;
-        double tp = (t * dl) * ir;
-        double y = cs + t;
-        cc += (fabs(cs) >= fabs(t)) ? ((cs - y) + t) : ((t - y) + cs);
-        cs = y;
-        sp += tp;
-        sp3 += (tp * ir) * dl;
-      }
-      double S = block_sum_comp(cs, cc, sm);
-      sp = block_sum(sp, sm);
-      sp3 = block_sum(sp3, sm);
-      const double Sz = S / zi2;
-      const double g = (bp - nu0) + Sz;
+      nu1 = nu0;
       const double gp = -1.0 - sp / zi2;
-      nu1 = nu0 - g / gp;
-      const double kap = (fabs(bp) + nu0 + Sz) / (nu0 * fabs(gp));
+      const double kap = (fabs(bp) + m + Sz) / (m * fabs(gp));
       muv = s / nu1;
       lam = sigma + muv;
       double amp = fabs(muv / lam);
@@ -1002,7 +1002,10 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
         if (k > 0) gap = fmin(gap, fabs(lam - Dv[k - 1]));
         nz = A.nearzero * fabs(lam) < gap;
       }
-      xsv = sqrt(zi2 + (sp - 2.0 * (nu1 - nu0) * sp3));
+      // ||x|| carried from m to the root to second order, as in k_eig
+      const double h = nu1 - m;
+      xsv = sqrt(zi2 + ((sp - 2.0 * h * sp3) + 3.0 * (h * h) * sp4));
+      nu0 = m;
       have_xs = true;
     }
 
@@ -1019,9 +1022,11 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
       for (int pit = 0; pit < 48; ++pit) {
         dd acc = {0.0, 0.0};
         double sp = 0.0;
+        #pragma unroll 4
         for (int j = tid; j < n; j += FIXT) {
           if (j == i) continue;
-          double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
+          const double2 pj = Z2v[j];
+          double dj = pj.x, z2 = pj.y;
           dd dl = two_sum(s * dj, -s * sigma);                   // delta'_j exactly
           dd pp = dd_add(dd_mul_d(dl, cur), dd{-1.0, 0.0});       // nu delta' - 1
           dd q = dd_mul(dl, pp);
@@ -1068,8 +1073,10 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
       // eq. (gamma): f(0) = 1 + rho z^T D^{-1} z in double-double
       dd f0 = {0.0, 0.0};
       double uu = 0.0, dmin = INFINITY;
-      for (int j = tid; j < n; j += FIXT) {
-        double dj = Z2[2 * j], z2 = Z2[2 * j + 1];
+      #pragma unroll 4
+        for (int j = tid; j < n; j += FIXT) {
+        const double2 pj = Z2v[j];
+          double dj = pj.x, z2 = pj.y;
         dd t = dd_div(dd{z2, Zl[j]}, dd{dj, 0.0});
         f0 = dd_add(f0, t);
         double u = Zv[j] / dj;
@@ -1099,8 +1106,10 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
         for (int hit = 0; hit < 200 && !adjacent(lo, hi); ++hit) {
           double m = fmid(lo, hi);
           double acc = 0.0;
-          for (int j = tid; j < n; j += FIXT) {
-            double dt = sh * Z2[2 * j], z2 = Z2[2 * j + 1];
+          #pragma unroll 4
+        for (int j = tid; j < n; j += FIXT) {
+            const double2 pj = Z2v[j];
+            double dt = sh * pj.x, z2 = pj.y;
             acc += z2 / (dt * __builtin_fma(-m, dt, 1.0));
           }
           acc = block_sum(acc, sm);
@@ -1109,8 +1118,10 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
         }
         const double e0 = hi;
         double cs = 0.0, cc = 0.0, sp = 0.0;
+        #pragma unroll 4
         for (int j = tid; j < n; j += FIXT) {
-          double dt = sh * Z2[2 * j], z2 = Z2[2 * j + 1];
+          const double2 pj = Z2v[j];
+            double dt = sh * pj.x, z2 = pj.y;
           double om = __builtin_fma(-e0, dt, 1.0);
           double t = z2 / (dt * om);
           double y = cs + t;
@@ -1129,7 +1140,8 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
 
     if (polished && A.want_v) {
       double acc = 0.0;
-      for (int j = tid; j < n; j += FIXT) {
+      #pragma unroll 4
+        for (int j = tid; j < n; j += FIXT) {
         double r = muv / ((Dv[j] - sigma) - muv);
         double z2 = Z2[2 * j + 1];
         acc = __builtin_fma(z2 * r, r, acc);
@@ -1298,29 +1310,26 @@ __global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, co
     }
     return;
   }
-  // Column segments one after the other.  When every column has the same
-  // offset modulo the window (ld a multiple of 64) the window count is
-  // exact, otherwise it allows for the worst offset.
-  const int64_t sfirst = base + (int64_t)(M.neg ? n - 1 - c0 : c0) * ld + r0;
-  const int wc = (ld % WAVE == 0) ? (int)(((sfirst & (WAVE - 1)) + nr + WAVE - 1) / WAVE) : (nr + WAVE - 1) / WAVE + 1;
-  int c = 0, wi = wv;
-  while (wi >= wc) { wi -= wc; ++c; }
-  for (; c < nc;) {
+  // Column segments: wave w writes columns w, w + NW, ... of the group, each
+  // in aligned windows (the column's address set up once, then a plain loop).
+  for (int c = wv; c < nc; c += NW) {
     const int k = c0 + c;
     const int64_t ko = M.neg ? n - 1 - k : k;
     const int64_t s0 = base + ko * ld + r0;  // element index of the segment's first position
-    const int64_t e = (s0 & ~(int64_t)(WAVE - 1)) + (int64_t)wi * WAVE + lane;
-    const int64_t rel = e - s0;
-    if (rel >= 0 && rel < nr) {
-      const double m = lmu[c];
-      const double den = (ld_d[rel] - lsig[c]) - m;
-      const double rc = rcp_1nr(den);
-      double q = m * rc;
-      q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
-      __builtin_nontemporal_store((ld_z[rel] * q) * linv[c], &V[e]);
+    const int64_t sal = s0 & ~(int64_t)(WAVE - 1);
+    const int nwin = (int)((s0 + nr - sal + WAVE - 1) / WAVE);
+    const double m = lmu[c], sc = lsig[c], iv = linv[c];
+    double* vp = V + sal + lane;
+    int rel = (int)(sal - s0) + lane;
+    for (int w = 0; w < nwin; ++w, vp += WAVE, rel += WAVE) {
+      if (rel >= 0 && rel < nr) {
+        const double den = (ld_d[rel] - sc) - m;
+        const double rc = rcp_1nr(den);
+        double q = m * rc;
+        q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
+        __builtin_nontemporal_store((ld_z[rel] * q) * iv, vp);
+      }
     }
-    wi += NW;
-    while (wi >= wc) { wi -= wc; ++c; }
   }
 }
 
@@ -1466,8 +1475,6 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048);
   hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(FIXT), 0, st, A);
   HIPCHECK(hipGetLastError());
-  int64_t nmax = n_single;
-  (void)nmax;
   double* csig = (double*)(w + L.csig);
   double* cinv = (double*)(w + L.cinv);
   hipLaunchKernelGGL(k_out, dim3(nprob > 1 ? (unsigned)nprob : (unsigned)std::min<int64_t>((N + 255) / 256, 1024)),
