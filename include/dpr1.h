@@ -97,7 +97,9 @@ typedef struct dpr1_opts {
   void* events;        /* profiling hook, NULL (default) = off: a host array
                           of 4 hipEvent_t that the solve records on `stream`
                           right before and after the eigenvalue kernel
-                          ([0], [1]) and the eigenvector kernel ([2], [3]) */
+                          ([0], [1]) and around the second phase ([2], [3]):
+                          the flagged eigenpairs overlapped with the
+                          eigenvector write                                 */
 } dpr1_opts;
 
 void dpr1_default_opts(dpr1_opts* opts);

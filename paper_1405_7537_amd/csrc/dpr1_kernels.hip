@@ -12,14 +12,18 @@
 //              same (d_j, zeta_j^2) at the same time, so the data arrive
 //              through scalar loads and feed the FP64 VALU as SGPR operands.
 //              Per eigenvalue: shift test, tip b in double-double, extreme
-//              root of the arrowhead secular function, compensated Newton
-//              step, near-zero test, ||x||.
-//   k_fix   -- one 256-thread block per flagged eigenpair: root search
-//              continued past k_eig's pass budget, double-double Newton
-//              polish, and the near-zero recomputation of eq. (gamma).
+//              root of the arrowhead secular function (model passes, the
+//              last one with compensated summation), near-zero test, ||x||.
 //   k_out   -- user outputs in the caller's index order.
-//   k_vec   -- V, one block per column group and row range, non-temporal
-//              stores in windows aligned to whole cache lines.
+//   k_fix   -- one 256-thread block at a time per flagged eigenpair: root
+//              search continued past k_eig's pass budget, double-double
+//              Newton polish, and the near-zero recomputation of eq. (gamma).
+//   k_fixvec -- k_fix's work and the eigenvector writer in one launch: a few
+//              blocks finish the flagged eigenpairs while the others write V,
+//              one block per column group and row range, non-temporal stores
+//              in windows aligned to whole cache lines; flagged columns are
+//              left to k_fixout.
+//   k_fixout -- outputs and V columns of the flagged eigenpairs.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -76,7 +80,8 @@ struct KArgs {
   double* xs;           // [N]  |mu| * ||x||_2
   double* lam;          // [N]
   FixItem* fix;         // [N]
-  int32_t* ctr;         // [0] fix count, [1] queue head
+  uint8_t* vflag;       // [N]  1: eigenpair finished in k_fix (its V column written after)
+  int32_t* ctr;         // [0] fix count, [1] queue head, [2] k_fix queue head
   int32_t* stats;       // nullable
   const int2* items;    // batched queue (p, k0) or nullptr
   int32_t nitems;
@@ -426,6 +431,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double z0 = Zv[0];
       double m = rho * (z0 * z0);
       A.ii[off] = 0;
+      A.vflag[off] = 0;
       A.mu[off] = m;
       A.xs[off] = fabs(z0);
       A.lam[off] = Dv[0] + m;
@@ -735,6 +741,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   double Nx[1] = {zi2 + ((Sp[0] - 2.0 * h * Sp[1]) + 3.0 * (h * h) * Sp[2])};
   if (wv == 0 && valid) {
     A.ii[off + k] = i;
+    A.vflag[off + k] = (pol || nz || cont) ? 1 : 0;
     A.mu[off + k] = muv;
     A.xs[off + k] = sqrt(Nx[0]);
     A.lam[off + k] = lam;
@@ -901,7 +908,7 @@ __device__ __forceinline__ double block_sum_comp(double s, double c, double* sm)
 
 // One block of FIXT threads per flagged eigenpair at a time; the inner index
 // is strided over the block and every pass ends in a block-wide sum.
-__global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
+__device__ void fix_items(const KArgs& A) {
   __shared__ double sm[8];
   __shared__ int next;
   const int tid = threadIdx.x;
@@ -1165,6 +1172,8 @@ __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) {
   }
 }
 
+__global__ void __launch_bounds__(FIXT) k_fix(KArgs A) { fix_items(A); }
+
 // ------------------------------------------------------------------- out
 // user outputs in the caller's order (rho < 0 maps k -> n-1-k, lambda -> -lambda)
 __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int nprob,
@@ -1224,27 +1233,49 @@ constexpr int VEC_T = 256;
 constexpr int VEC_ROWS = 2048;
 constexpr int VEC_C_SINGLE = 32, VEC_C_BATCH = 64;
 
+// Arguments of the eigenvector writer.  Columns flagged in vflag belong to
+// eigenpairs that k_fix finishes; they are skipped here and written by
+// k_fixout once their values are final.
+struct VArgs {
+  const Meta* meta;
+  const int4* groups;  // batched: (problem, first column, columns, first row) per block
+  int64_t ncolgroups;  // single problem: column groups per row tile
+  const double* sd;
+  const double* sz;
+  const double* mu;
+  const double* csig;
+  const double* cinv;
+  const uint8_t* vflag;
+  double* V;
+  const int64_t* voffs;
+  int64_t ldv;
+};
+
 template <int CB>
-__global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, const int4* __restrict__ groups,
-                                               int64_t ncolgroups, const double* __restrict__ sd,
-                                               const double* __restrict__ sz, const double* __restrict__ mu,
-                                               const double* __restrict__ csig, const double* __restrict__ cinv,
-                                               double* __restrict__ V, const int64_t* __restrict__ voffs,
-                                               int64_t ldv) {
+__device__ void vec_block(unsigned bid, const VArgs& v) {
   __shared__ double ld_d[VEC_ROWS], ld_z[VEC_ROWS];
   __shared__ double lsig[CB], lmu[CB], linv[CB];
+  __shared__ uint8_t lskip[CB];
+  const Meta* __restrict__ meta = v.meta;
+  const int4* __restrict__ groups = v.groups;
+  const int64_t ncolgroups = v.ncolgroups;
+  const double* __restrict__ sd = v.sd;
+  const double* __restrict__ sz = v.sz;
+  double* __restrict__ V = v.V;
+  const int64_t* __restrict__ voffs = v.voffs;
+  const int64_t ldv = v.ldv;
   int p, c0, nc;
   int64_t r0;
   if (groups) {
-    const int4 g = groups[blockIdx.x];
+    const int4 g = groups[bid];
     p = g.x;
     c0 = g.y;
     nc = g.z;
     r0 = g.w;
   } else {
     p = 0;
-    c0 = (int)(blockIdx.x % ncolgroups) * CB;
-    r0 = (int64_t)(blockIdx.x / ncolgroups) * VEC_ROWS;
+    c0 = (int)(bid % ncolgroups) * CB;
+    r0 = (int64_t)(bid / ncolgroups) * VEC_ROWS;
     nc = 0;
   }
   const Meta M = meta[p];
@@ -1264,9 +1295,10 @@ __global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, co
   }
   if (threadIdx.x < nc) {
     const int64_t a = M.off + c0 + threadIdx.x;
-    lsig[threadIdx.x] = csig[a];
-    lmu[threadIdx.x] = mu[a];
-    linv[threadIdx.x] = cinv[a];
+    lsig[threadIdx.x] = v.csig[a];
+    lmu[threadIdx.x] = v.mu[a];
+    linv[threadIdx.x] = v.cinv[a];
+    lskip[threadIdx.x] = v.vflag ? v.vflag[a] : 0;
   }
   __syncthreads();
   const int64_t ld = voffs ? (int64_t)n : ldv;
@@ -1300,6 +1332,7 @@ __global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, co
         }
         const int ko = (int)kolo + q;
         const int c = (M.neg ? n - 1 - ko : ko) - c0;
+        if (lskip[c]) continue;
         const double m = lmu[c];
         const double den = (ld_d[pos] - lsig[c]) - m;
         const double rc = rcp_1nr(den);
@@ -1313,6 +1346,7 @@ __global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, co
   // Column segments: wave w writes columns w, w + NW, ... of the group, each
   // in aligned windows (the column's address set up once, then a plain loop).
   for (int c = wv; c < nc; c += NW) {
+    if (lskip[c]) continue;
     const int k = c0 + c;
     const int64_t ko = M.neg ? n - 1 - k : k;
     const int64_t s0 = base + ko * ld + r0;  // element index of the segment's first position
@@ -1333,9 +1367,61 @@ __global__ void __launch_bounds__(VEC_T) k_vec(const Meta* __restrict__ meta, co
   }
 }
 
+
+// k_fix and the eigenvector writer in one launch: the first nfix blocks take
+// flagged eigenpairs from the queue (latency-bound work), the others write V
+// (HBM-bound), so the two overlap.
+template <int CB>
+__global__ void __launch_bounds__(VEC_T) k_fixvec(KArgs A, VArgs v, int nfix) {
+  if (blockIdx.x < (unsigned)nfix)
+    fix_items(A);
+  else
+    vec_block<CB>(blockIdx.x - nfix, v);
+}
+
+// Outputs and V columns of the eigenpairs finished in k_fix, in the same
+// arithmetic as k_out and the eigenvector writer.
+__global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ lam_out,
+                                                int32_t* __restrict__ idx_out, double* __restrict__ mu_out,
+                                                double* __restrict__ xn_out, double* __restrict__ V,
+                                                const int64_t* __restrict__ voffs, int64_t ldv) {
+  const int cnt = A.ctr[0];
+  for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+    const FixItem it = A.fix[e];
+    const Meta M = A.meta[it.p];
+    const int n = M.n, k = it.k;
+    const int64_t a = M.off + k;
+    const int ii = A.ii[a];
+    const double m = A.mu[a], xs = A.xs[a];
+    const int ko = M.neg ? n - 1 - k : k;
+    const double sg = M.neg ? -1.0 : 1.0;
+    if (threadIdx.x == 0) {
+      const int64_t b = M.off + ko;
+      lam_out[b] = sg * A.lam[a];
+      if (idx_out) idx_out[b] = M.neg ? n - 1 - ii : ii;
+      if (mu_out) mu_out[b] = sg * m;
+      if (xn_out) xn_out[b] = xs / fabs(m);
+    }
+    if (V) {
+      const double sc = A.sd[M.off + ii];
+      const double iv = 1.0 / copysign(xs, m);
+      const int64_t ld = voffs ? (int64_t)n : ldv;
+      double* col = V + (voffs ? voffs[it.p] : 0) + (int64_t)ko * ld;
+      for (int pos = threadIdx.x; pos < n; pos += blockDim.x) {
+        const int j = M.neg ? n - 1 - pos : pos;
+        const double den = (A.sd[M.off + j] - sc) - m;
+        const double rc = rcp_1nr(den);
+        double q = m * rc;
+        q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
+        col[pos] = ((sg * A.sz[M.off + j]) * q) * iv;
+      }
+    }
+  }
+}
+
 // ===================================================================== host
 struct Layout {
-  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, csig, cinv, fix, items, groups, part, ctr, total;
+  size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, csig, cinv, fix, vflag, items, groups, part, ctr, total;
 };
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1355,6 +1441,7 @@ static Layout layout(int64_t nprob, int64_t N, int64_t nitems, int64_t ngroups =
   L.csig = o; o = al(o + 8 * N);
   L.cinv = o; o = al(o + 8 * N);
   L.fix = o; o = al(o + sizeof(FixItem) * N);
+  L.vflag = o; o = al(o + N);
   L.items = o; o = al(o + sizeof(int2) * nitems);
   L.groups = o; o = al(o + sizeof(int4) * ngroups);
   L.part = o; o = al(o + sizeof(double2) * PREP_MAX_SPLIT);
@@ -1443,6 +1530,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   A.xs = (double*)(w + L.xs);
   A.lam = (double*)(w + L.lam);
   A.fix = (FixItem*)(w + L.fix);
+  A.vflag = (uint8_t*)(w + L.vflag);
   A.ctr = (int32_t*)(w + L.ctr);
   A.stats = stats;
   A.items = persistent_grid ? (const int2*)(w + L.items) : nullptr;
@@ -1472,29 +1560,51 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   hipLaunchKernelGGL(k_eig, dim3(grid), dim3(64 * W), red_bytes(W), st, A);
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[1], st));
-  unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048);
-  hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(FIXT), 0, st, A);
-  HIPCHECK(hipGetLastError());
+  // user outputs of every eigenpair (those of flagged ones are rewritten by
+  // k_fixout once k_fix has finished them)
   double* csig = (double*)(w + L.csig);
   double* cinv = (double*)(w + L.cinv);
   hipLaunchKernelGGL(k_out, dim3(nprob > 1 ? (unsigned)nprob : (unsigned)std::min<int64_t>((N + 255) / 256, 1024)),
                      dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, A.sd, csig, cinv, lambda,
                      shift_idx, mu, xnorm);
   HIPCHECK(hipGetLastError());
+  if (ev) HIPCHECK(hipEventRecord(ev[2], st));
   if (V) {
-    if (ev) HIPCHECK(hipEventRecord(ev[2], st));
+    // k_fix overlapped with the eigenvector writer: a few blocks take the
+    // flagged eigenpairs, the rest write every other column
+    VArgs va;
+    va.meta = meta;
+    va.sd = A.sd;
+    va.sz = A.sz;
+    va.mu = A.mu;
+    va.csig = csig;
+    va.cinv = cinv;
+    va.vflag = A.vflag;
+    va.V = V;
+    va.voffs = voffs;
+    va.ldv = ldv;
+    const int nfix = persistent_grid ? 512 : 256;
     if (persistent_grid) {
-      hipLaunchKernelGGL((k_vec<VEC_C_BATCH>), dim3((unsigned)ngroups), dim3(VEC_T), 0, st, meta,
-                         (const int4*)(w + L.groups), ngroups, A.sd, A.sz, A.mu, csig, cinv, V, voffs, ldv);
+      va.groups = (const int4*)(w + L.groups);
+      va.ncolgroups = ngroups;
+      hipLaunchKernelGGL((k_fixvec<VEC_C_BATCH>), dim3((unsigned)(nfix + ngroups)), dim3(VEC_T), 0, st, A, va, nfix);
     } else {
       const int64_t cg = (N + VEC_C_SINGLE - 1) / VEC_C_SINGLE;
       const int64_t rt = (N + VEC_ROWS - 1) / VEC_ROWS;
-      hipLaunchKernelGGL((k_vec<VEC_C_SINGLE>), dim3((unsigned)(cg * rt)), dim3(VEC_T), 0, st, meta,
-                         (const int4*)nullptr, cg, A.sd, A.sz, A.mu, csig, cinv, V, voffs, ldv);
+      va.groups = nullptr;
+      va.ncolgroups = cg;
+      hipLaunchKernelGGL((k_fixvec<VEC_C_SINGLE>), dim3((unsigned)(nfix + cg * rt)), dim3(VEC_T), 0, st, A, va,
+                         nfix);
     }
-    HIPCHECK(hipGetLastError());
-    if (ev) HIPCHECK(hipEventRecord(ev[3], st));
+  } else {
+    unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048);
+    hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(FIXT), 0, st, A);
   }
+  HIPCHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_fixout, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 1024)), dim3(256), 0, st,
+                     A, lambda, shift_idx, mu, xnorm, V, voffs, ldv);
+  HIPCHECK(hipGetLastError());
+  if (ev) HIPCHECK(hipEventRecord(ev[3], st));
   return DPR1_OK;
 }
 
