@@ -86,7 +86,7 @@ struct KArgs {
   const int2* items;    // batched queue (p, k0) or nullptr
   int32_t nitems;
   int32_t W;
-  int32_t mode_b, root, polish, want_v;
+  int32_t mode_b, root, polish;
   int32_t main_passes;
   double kappa_polish, nearzero;
 };
@@ -1145,7 +1145,7 @@ __device__ void fix_items(const KArgs& A) {
       }
     }
 
-    if (polished && A.want_v) {
+    if (polished) {
       double acc = 0.0;
       #pragma unroll 4
         for (int j = tid; j < n; j += FIXT) {
@@ -1159,7 +1159,7 @@ __device__ void fix_items(const KArgs& A) {
       A.lam[off + k] = lam;
       if (polished || have_xs) {
         A.mu[off + k] = muv;
-        if (A.want_v) A.xs[off + k] = xsv;
+        A.xs[off + k] = xsv;
       }
       if (A.stats) {
         if (polished) atomicAdd(&A.stats[DPR1_STAT_POLISHED], 1);
@@ -1407,13 +1407,14 @@ __global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ la
       const double iv = 1.0 / copysign(xs, m);
       const int64_t ld = voffs ? (int64_t)n : ldv;
       double* col = V + (voffs ? voffs[it.p] : 0) + (int64_t)ko * ld;
-      for (int pos = threadIdx.x; pos < n; pos += blockDim.x) {
+#pragma unroll 8
+      for (int pos = threadIdx.x; pos < n; pos += 256) {
         const int j = M.neg ? n - 1 - pos : pos;
         const double den = (A.sd[M.off + j] - sc) - m;
         const double rc = rcp_1nr(den);
         double q = m * rc;
         q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
-        col[pos] = ((sg * A.sz[M.off + j]) * q) * iv;
+        __builtin_nontemporal_store(((sg * A.sz[M.off + j]) * q) * iv, &col[pos]);
       }
     }
   }
@@ -1539,7 +1540,6 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   A.mode_b = o.mode_b;
   A.root = o.root;
   A.polish = o.polish;
-  A.want_v = V != nullptr;
   A.kappa_polish = o.kappa_polish;
   A.nearzero = o.nearzero;
   // Default budget: the single-problem launch leaves the stragglers (under a
@@ -1601,7 +1601,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
     hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(FIXT), 0, st, A);
   }
   HIPCHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_fixout, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 1024)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_fixout, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048)), dim3(256), 0, st,
                      A, lambda, shift_idx, mu, xnorm, V, voffs, ldv);
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[3], st));
