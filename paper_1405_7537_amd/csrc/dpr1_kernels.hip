@@ -181,21 +181,27 @@ __device__ __forceinline__ void wg_sum_dd(dd& a, int W, int wv, int lane, double
 // j < i), inside it (seg 1: per-lane test), above it (seg 2: every lane has
 // j > i).  j is wave-uniform in all three loops.
 template <class F>
-__device__ __forceinline__ void sweep(const double* P, int j0, int j1, int wlo, int whi, F&& f) {
-  // q walks the (d_j, zeta_j^2) pairs so that the unrolled loads share one
-  // base address with immediate offsets
-  int a = j0, b = min(j1, wlo);
+__device__ __forceinline__ void sweep_seg(const double* P, int a, int b, int seg, F& f) {
+  // blocks of 8 pairs: all 16 scalar loads are issued before the first use,
+  // so a block waits for its data once
   const double* q = P + 2 * (int64_t)a;
-#pragma unroll 8
-  for (int j = a; j < b; ++j, q += 2) f(j, 0, q);
-  a = max(j0, wlo);
-  b = min(j1, whi);
-  q = P + 2 * (int64_t)a;
-  for (int j = a; j < b; ++j, q += 2) f(j, 1, q);
-  a = max(j0, whi);
-  q = P + 2 * (int64_t)a;
-#pragma unroll 8
-  for (int j = a; j < j1; ++j, q += 2) f(j, 2, q);
+  int j = a;
+  for (; j + 8 <= b; j += 8, q += 16) {
+    double c[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) c[t] = ldu(q, t);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) f(j + u, seg, c[2 * u], c[2 * u + 1]);
+  }
+  for (; j < b; ++j, q += 2) f(j, seg, ldu(q, 0), ldu(q, 1));
+}
+
+template <class F>
+__device__ __forceinline__ void sweep(const double* P, int j0, int j1, int wlo, int whi, F&& f) {
+  sweep_seg(P, j0, min(j1, wlo), 0, f);
+  sweep_seg(P, max(j0, wlo), min(j1, whi), 1, f);
+  sweep_seg(P, max(j0, whi), j1, 2, f);
 }
 
 // ------------------------------------------------------------------ prep
@@ -459,8 +465,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // point of the root search instead, lambda = d_1 + 1/nux.
   const double tau = kk > 0 ? (dkm1 - dk) / 2 : 1.0 / nux;
   double Fs[4] = {0.0, 0.0, 0.0, 0.0};
-  sweep(P, j0, j1, wlo, whi, [&](int j, int, const double* pq) {
-    double dj = ldu(pq, 0), z2 = ldu(pq, 1);
+  sweep(P, j0, j1, wlo, whi, [&](int j, int, double dj, double z2) {
     double r = rcp_1nr((dj - dk) - tau);
     double t = z2 * r;
     double tr = t * r;
@@ -490,8 +495,8 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     t.lo += a.lo + q2;
     a = fast_two_sum(t.hi, t.lo);
   };
-  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
-    double dj = ldu(pq, 0), z2 = ldu(pq, 1), z2l = ldu(Zl, j);
+  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2) {
+    double z2l = ldu(Zl, j);
     dd dl = two_sum(dj, -sigma);  // exact d_j - sigma
     double r = rcp_1nr(dl.hi);
     double q1 = z2 * r;
@@ -584,8 +589,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double m = nu;
       double S[1] = {0.0};
       if (wave_any(!done && !pre)) {
-        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
-          double dj = ldu(pq, 0), z2 = ldu(pq, 1);
+        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2) {
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
           double t = z2 * rcp_1nr(dl * pp);
@@ -623,8 +627,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double m = nu;
       double S[3] = {0.0, 0.0, 0.0};
       if (wave_any(!done && !pre)) {
-        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
-          double dj = ldu(pq, 0), z2 = ldu(pq, 1);
+        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2) {
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
           double rq = rcp_1nr(dl * pp);
@@ -675,8 +678,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   const double m = (A.root == 0 || done) ? nu0 : nu;
   double cs = 0.0, cc = 0.0;
   double Sp[3] = {0.0, 0.0, 0.0};
-  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, const double* pq) {
-    double dj = ldu(pq, 0), z2 = ldu(pq, 1);
+  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2) {
     double dl = __builtin_fma(s, dj, nss);
     double pp = __builtin_fma(m, dl, -1.0);
     double q = dl * pp;
