@@ -32,10 +32,14 @@
 namespace dpr1 {
 namespace bwd {
 
-// Block tile 128 x 128 (2 x 2 waves of 64 x 64, each 4 x 4 blocks of the
-// 16x16x4 FP64 MFMA), K staged through LDS in slices of 16, double-buffered.
+// Block tile 128 x 128 (2 x WNW waves of 64 x TN, each 4 x TN/16 blocks of
+// the 16x16x4 FP64 MFMA), K staged through LDS in slices of 16,
+// double-buffered.
 constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int NT = 256;
+constexpr int WNW = 4;               // waves along n
+constexpr int TN = BN / WNW;         // columns per wave
+constexpr int NBT = TN / 16;         // MFMA blocks per wave along n
+constexpr int NT = 128 * WNW;
 constexpr int PAD = 2;   // LDS row padding (doubles)
 constexpr int NXCD = 8;  // workgroups are dealt round-robin to the 8 XCDs
 
@@ -84,18 +88,24 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
   const int wv = tid / 64, lane = tid % 64;
-  const int wm = (wv & 1) * 64, wn = (wv >> 1) * 64;
+  const int wm = (wv & 1) * 64, wn = (wv >> 1) * TN;
 
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+  // one LDS buffer: the double-buffered operand tiles during the K loop,
+  // the epilogue's per-row / per-column arrays after it
+  constexpr int TILE_D = 2 * BK * (BM + PAD);
+  constexpr int EPI_D_N = 3 * BM + 4 * BN + 2 * WNW * BM + 2 * BN;
+  constexpr int SMEM_D = 2 * TILE_D > EPI_D_N ? 2 * TILE_D : EPI_D_N;
+  __shared__ double smem[SMEM_D];
+  double(*As)[BK][BM + PAD] = reinterpret_cast<double(*)[BK][BM + PAD]>(smem);
+  double(*Bs)[BK][BN + PAD] = reinterpret_cast<double(*)[BK][BN + PAD]>(smem + TILE_D);
 
-  double4_t acc[4][4];
+  double4_t acc[4][NBT];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NBT; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-  constexpr int PER = (BM * BK) / NT;  // 8 elements of each operand per thread
+  constexpr int PER = (BM * BK) / NT;  // elements of each operand per thread
   double ra[PER], rb[PER];
   auto gload = [&](int64_t k0) {
 #pragma unroll
@@ -152,16 +162,15 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
         // 16x16x4 FP64 MFMA: lane holds A(row = lane%16, k = lane/16) and
         // B(k = lane/16, col = lane%16)
         const int r = lane % 16, q = lane / 16;
-        double af[4], bf[4];
+        double af[4], bf[NBT];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          af[x] = As[buf][ks + q][wm + 16 * x + r];
-          bf[x] = Bs[buf][ks + q][wn + 16 * x + r];
-        }
+        for (int x = 0; x < 4; ++x) af[x] = As[buf][ks + q][wm + 16 * x + r];
+#pragma unroll
+        for (int x = 0; x < NBT; ++x) bf[x] = Bs[buf][ks + q][wn + 16 * x + r];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
+          for (int b = 0; b < NBT; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
       }
       if (more) {
@@ -177,9 +186,16 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   // multiplies A(:,0) = 2^i by B(0,:) = 3^j).  The per-row and per-column
   // quantities of this tile are staged in LDS first; per-row / per-column
   // partial sums go back through LDS.
-  __shared__ double rsig[BM], rmu[BM], ry[BM], csig[BN], cmu[BN], cy[BN], clb[BN];
-  __shared__ double rowp[2][2][BM];  // [quantity][wn half][row]
-  __shared__ double colp[2][BN];     // [wm half][col]
+  __syncthreads();  // every wave is done with the operand tiles
+  double* rsig = smem;
+  double* rmu = rsig + BM;
+  double* ry = rmu + BM;
+  double* csig = ry + BM;
+  double* cmu = csig + BN;
+  double* cy = cmu + BN;
+  double* clb = cy + BN;
+  double(*rowp)[WNW][BM] = reinterpret_cast<double(*)[WNW][BM]>(clb + BN);  // [quantity][wave along n][row]
+  double(*colp)[BN] = reinterpret_cast<double(*)[BN]>(clb + BN + 2 * WNW * BM);  // [wave along m][col]
   const int64_t vo = (int64_t)pb * n;
   // shift indices come from the caller: clamped so that a bad one cannot
   // address outside the problem
@@ -193,7 +209,7 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
         ry[tid] = g.y[vo + row];
       }
     }
-  } else {
+  } else if (tid < BM + BN) {
     int c = tid - BM;
     int64_t col = n0 + c;
     if (col < n) {
@@ -208,13 +224,15 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
     }
   }
   __syncthreads();
-  const int half_n = wv >> 1, half_m = wv & 1;
-  double cs[4] = {0.0, 0.0, 0.0, 0.0};
+  const int half_n = wv >> 1, half_m = wv & 1;  // wave index along n, along m
+  double cs[NBT];
+#pragma unroll
+  for (int b = 0; b < NBT; ++b) cs[b] = 0.0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     double rs1[4] = {0.0, 0.0, 0.0, 0.0}, rs2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < NBT; ++b) {
       const int cl = wn + b * 16 + lane % 16;
       const int64_t col = n0 + cl;
 #pragma unroll
@@ -262,7 +280,7 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   if (EPI == EPI_X) {
     // columns: reduce over the 4 lane groups sharing a column (same lane%16)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < NBT; ++b) {
       double c = cs[b];
       c += __shfl_xor(c, 16);
       c += __shfl_xor(c, 32);
@@ -275,12 +293,16 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
     int64_t row = m0 + tid;
     if (row < n) {
       int64_t a = ((int64_t)pb * ntile + tn) * n + row;
-      double s1 = rowp[0][0][tid] + rowp[0][1][tid];
+      double s1 = rowp[0][0][tid], s2 = rowp[1][0][tid];
+      for (int w = 1; w < WNW; ++w) {
+        s1 += rowp[0][w][tid];
+        s2 += rowp[1][w][tid];
+      }
       if (EPI == EPI_X) {
         g.part_r[a] = s1;
       } else {
         g.part_d[a] = s1;
-        g.part_z[a] = rowp[1][0][tid] + rowp[1][1][tid];
+        g.part_z[a] = s2;
       }
     }
   } else if (EPI == EPI_X && tid < BM + BN) {
