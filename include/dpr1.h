@@ -90,7 +90,8 @@ typedef struct dpr1_opts {
                           A^{-1} when factor*|lambda| < distance to the
                           neighbouring poles; default 10, 0 disables        */
   int32_t main_passes; /* model solver: passes the eigenvalue kernel runs
-                          before it hands an unconverged eigenpair to the
+                          (the last one with compensated summation) before
+                          it hands an unconverged eigenpair to the
                           cooperative kernel; 0 = default (2 for dpr1_eig,
                           3 for dpr1_eig_batched)                          */
   int32_t reserved;

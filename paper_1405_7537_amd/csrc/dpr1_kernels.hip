@@ -102,22 +102,12 @@ __device__ __forceinline__ double fmid(double lo, double hi) {
 }
 __device__ __forceinline__ bool adjacent(double lo, double hi) { return bits(hi) - bits(lo) <= 1; }
 
-// Reciprocal from the hardware estimate refined by two Newton steps (within
-// about one ulp) and a quotient with one residual correction (within about
-// half an ulp more than correct rounding).  Used where the iteration only
-// needs the value, not the correctly rounded one; the IEEE divide costs about
-// twice as many instructions on this ISA.
-// v_rcp_f64 is good to 2^-24.4 relative (measured on gfx950 over random
-// normal inputs); one Newton step gives 2^-48.7, two give full precision.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-// one Newton step: enough where only the sign or a model step is needed, and
-// as the seed of a quotient that is corrected by its residual
+// Reciprocal from the hardware estimate refined by one Newton step: enough
+// where only a sign or a model step is needed, and as the seed of a quotient
+// that is then corrected by its residual (within about half an ulp more than
+// correct rounding).  v_rcp_f64 is good to 2^-24.4 relative (measured on
+// gfx950 over random normal inputs); one Newton step gives 2^-48.7.  The IEEE
+// divide costs about twice as many instructions on this ISA.
 __device__ __forceinline__ double rcp_1nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = __builtin_fma(-x, r, 1.0);
@@ -829,15 +819,6 @@ __device__ __forceinline__ dd wave_sum_dd(dd a) {
   return a;
 }
 // Neumaier partials of the lanes, combined in a fixed butterfly order
-__device__ __forceinline__ double wave_sum_comp(double s, double c) {
-  for (int o = 32; o > 0; o >>= 1) {
-    double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
-    dd t = two_sum(s, s2);
-    s = t.hi;
-    c = c + c2 + t.lo;
-  }
-  return s + c;
-}
 
 // Block-wide sums over FIXT threads (4 waves) in a fixed order; every thread
 // receives the total.
@@ -1544,9 +1525,10 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   A.polish = o.polish;
   A.kappa_polish = o.kappa_polish;
   A.nearzero = o.nearzero;
-  // Default budget: the single-problem launch leaves the stragglers (under a
-  // tenth of the roots) to one block each in k_fix; a batch of small problems
-  // would queue many of them per block there, so it runs one more pass.
+  // Default budget: 2 passes (one plain, one accurate) for a single problem,
+  // whose stragglers (under a tenth of the roots) are finished beside the V
+  // write; a batch runs one more, since its many small problems would queue
+  // their stragglers in k_fix.
   A.main_passes = o.main_passes > 0 ? o.main_passes : (persistent_grid ? 3 : 2);
 
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, A.ctr, 16);

@@ -65,10 +65,17 @@ def test_bad_problem_is_isolated(D, orc):
 
 
 def test_eigenvalues_only_matches_vectors_run(D):
+    """Skipping V changes no other output: eigenvalues, shift indices, mu and ||x|| (also of
+    polished and continued roots) are bit for bit those of the run with vectors."""
     d, z, rho, offs = W.batched(32, 6, nmin=16, nmax=600)
-    b1 = D.eig_batched(d, z, rho, offs, vectors=True)
-    b2 = D.eig_batched(d, z, rho, offs, vectors=False)
-    assert np.array_equal(b1.lam.cpu().numpy(), b2.lam.cpu().numpy())
+    o = D.opts(main_passes=2)  # leaves some roots to the cooperative kernel at these sizes
+    b1 = D.eig_batched(d, z, rho, offs, vectors=True, want_stats=True, opts=o)
+    b2 = D.eig_batched(d, z, rho, offs, vectors=False, opts=o)
+    st = b1.stats.cpu().numpy()
+    print(f"[batched] polished {st[1]} continued {st[6]}", flush=True)
+    assert st[1] > 0 and st[6] > 0
+    for name in ("lam", "shift_idx", "mu", "xnorm"):
+        assert np.array_equal(getattr(b1, name).cpu().numpy(), getattr(b2, name).cpu().numpy()), name
 
 
 def test_repeat_solve_and_graph_capture(D):
