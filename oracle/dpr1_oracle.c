@@ -42,6 +42,7 @@
  *  - The near-zero rule (Alg. 1, last test) fires when
  *    10*|lambda| < min |lambda - neighbouring pole|.
  */
+#include <float.h>
 #include <math.h>
 #include <quadmath.h>
 #include <stdint.h>
@@ -286,8 +287,13 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
 
   /* Bracket of the extreme eigenvalue nu of A_i^{-1}.  Rightmost (side +1):
    * nu > max xi_j; leftmost: nu < min xi_j.  The far end uses the 2x2
-   * Loewner bound from Xi <= xi_max*I (resp. >= xi_min*I):
-   * (b+x)/2 +- sqrt(((b-x)/2)^2 + ||w||^2). */
+   * Loewner bound from Xi <= xi_max*I (resp. >= xi_min*I): the extreme
+   * eigenvalue of [[x, ||w||], [||w||, b]], i.e. (b+x)/2 +- sqrt(h^2 + ||w||^2)
+   * with h = (b-x)/2, written as max(b,x) + ||w||^2/(|h| + sqrt(h^2 + ||w||^2))
+   * (resp. min(b,x) - ...) so that b never cancels against the square root:
+   * with a tiny zeta_i, |b| can exceed nu by fifteen orders of magnitude.
+   * The final sum can still cancel (for k = 1 when nu << |x|), so a bound on
+   * its rounding error, 8 eps (|max(b,x)| + the quotient), is added. */
   double wn2 = 0.0, xmax = -INFINITY, xmin = INFINITY;
   for (int64_t j = 0; j < n; ++j) {
     if (j == i) continue;
@@ -298,8 +304,9 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
   const double grow = 1.0 + 0x1p-40;
   double L, U;
   if (side > 0) {
-    double h = (A.b - xmax) / 2;
-    U = ((A.b + xmax) / 2 + sqrt(h * h + wn2)) * grow;
+    double h = fabs(A.b - xmax) / 2;
+    double m = fmax(A.b, xmax), t = wn2 / (h + sqrt(h * h + wn2));
+    U = (m + t) * grow + 8 * DBL_EPSILON * (fabs(m) + t);
     if (k == 0) {
       /* lambda_1 lies in [d_1 + rho*zeta_1^2, d_1 + rho*||z||^2]. */
       double zz = 0.0;
@@ -311,10 +318,12 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
       L = xmax;              /* the pole nearest to nu, never evaluated */
     }
   } else {
-    double h = (A.b - xmin) / 2;
-    L = ((A.b + xmin) / 2 - sqrt(h * h + wn2)) * grow;
+    double h = fabs(A.b - xmin) / 2;
+    double m = fmin(A.b, xmin), t = wn2 / (h + sqrt(h * h + wn2));
+    L = (m - t) * grow - 8 * DBL_EPSILON * (fabs(m) + t);
     U = xmin;
   }
+  const double L0 = L, U0 = U;
 
   /* Bisection on g (decreasing on the bracket): g(mid) > 0 -> root above. */
   int it = 0;
@@ -339,22 +348,7 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
   if (opts.polish && kap * amp > opts.kappa_polish) {
     /* Safeguarded Newton on g evaluated in binary128.  The bracket is the
      * rigorous initial one, narrowed by the signs of the binary128 g. */
-    double lo, hi;
-    if (side > 0) {
-      double h = (A.b - xmax) / 2;
-      hi = ((A.b + xmax) / 2 + sqrt(h * h + wn2)) * grow;
-      if (k == 0) {
-        double zz = 0.0;
-        for (int64_t j = 0; j < n; ++j) zz += z[j] * z[j];
-        lo = (1.0 / (rho * zz)) / grow;
-        double Ub = (1.0 / (rho * zi * zi)) * grow;
-        if (Ub < hi || !(hi > lo)) hi = Ub;
-      } else lo = xmax;
-    } else {
-      double h = (A.b - xmin) / 2;
-      lo = ((A.b + xmin) / 2 - sqrt(h * h + wn2)) * grow;
-      hi = xmin;
-    }
+    double lo = L0, hi = U0;
     double cur = nu;
     if (!(cur >= lo && cur <= hi)) cur = nu0;
     int pit = 0;

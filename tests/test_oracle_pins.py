@@ -192,6 +192,44 @@ def test_truth_graded_clustered(orc):
     assert sum(x["polished"] for x in dg) >= 1
 
 
+# Shift poles with a tiny z_i next to heavy neighbours: the tip b of eq. (b_ob)
+# exceeds the sought eigenvalue nu of A_i^{-1} by about fifteen orders of
+# magnitude, so the bisection interval for nu must be formed without
+# cancellation (d, z, rho found by a seeded search; 3x3 keeps truth cheap).
+TINY_ZETA = [
+    ([1.0052135892525185, 1.0, 0.9906958220102936],
+     [0.46764735833376336, 2.303199938686197e-09, 0.857289141879661], 0.15727925514943147),
+    ([1.0051791603083504, 1.0, 0.990822438827502],
+     [0.727290823634564, 2.600781568413243e-09, 1.2259044602434073], 0.035812918374303324),
+    ([1.000004897825219, 1.0, 0.9999955488804597],
+     [0.6708627720878867, 1.2668571709217755e-09, 0.7021722483815622], 0.23171238115037016),
+]
+
+
+@pytest.mark.parametrize("case", range(len(TINY_ZETA)))
+def test_truth_tiny_zeta_shift(orc, case):
+    d, z, rho = TINY_ZETA[case]
+    d, z = np.array(d), np.array(z)
+    dg = _vs_truth(orc, d, z, rho, 2e-14, 5e-14)
+    assert dg[1]["i"] == 1 and abs(dg[1]["b"]) > 1e15 * abs(dg[1]["nu"])
+    L, _ = T.dense(d, z, rho, dps=60)
+    lam, _ = orc.eig(d, z, rho)
+    assert max(T.rel(lam[k], L[k]) for k in range(3)) <= 2e-14
+
+
+def test_truth_graded_4096_tiny_zeta(orc):
+    """The full-size graded matrix around its eigenvalue 814 (1-based), whose shift
+    pole has z_i ~ 1e-8 beside z_{i-1} ~ 0.6: the same cancellation at n = 4096."""
+    d, z, rho = W.graded(4096, 1)
+    ks = [811, 812, 813, 814, 815]
+    lam, V, dg = orc.eig_some(d, z, rho, ks, vectors=True)
+    tr = T.eig(d, z, rho, ks=ks)
+    assert abs(dg[2]["b"]) > 1e14 * abs(dg[2]["nu"])
+    for m in range(len(ks)):
+        assert T.rel(lam[m], tr[m]["lam"]) <= 2e-14
+        assert max(T.rel(V[j, m], tr[m]["v"][j]) for j in range(0, 4096, 7)) <= 5e-14
+
+
 def test_negative_rho_reduction(orc):
     d, z, _ = W.uniform(24, 5)
     lam, V = orc.eig(d, z, -0.7)
