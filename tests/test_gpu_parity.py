@@ -134,3 +134,72 @@ def test_strided_v(D, orc, n, pad, rho):
     assert el.max() <= LAM_TOL
     assert ev.max() <= VEC_TOL
     assert np.isnan(b[:, n:]).all()
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_tiny_zeta_shift(D, orc, case):
+    """3x3 problems whose middle pole has z_i ~ 1e-9 next to heavy neighbours: the
+    tip b is ~1e15 times the root of eq. (secAi)."""
+    from test_oracle_pins import TINY_ZETA
+    d, z, rho = TINY_ZETA[case]
+    compare(D, orc, np.array(d), np.array(z), rho, tag=f"tinyzeta{case}")
+
+
+def test_config_graded_4096(D, orc):
+    """Graded/clustered matrix at its full size (n = 4096, every 64th pair of poles at a
+    relative gap of 1e-10): every eigenpair against the oracle, element by element."""
+    r, *_ = compare(D, orc, *W.graded(4096, 1), tag="graded4096")
+    assert r.stats_dict()["polished"] >= 1
+
+
+def test_config_n32768_sampled(D, orc):
+    """n = 32768 with the full V (8.6 GB), solved as the benchmark solves it (default options,
+    one launch sequence).  Sampled eigenpairs against the oracle to the parity bar; for every
+    eigenpair: strict ordering and interlacing (eq. interlace), unit norm, and the residual
+    (D - lambda I) v + rho z (z^T v) = 0 relative to ||A||."""
+    import torch
+    n = 32768
+    d, z, rho = W.uniform(n, 2, zscale=1.0 / math.sqrt(n))
+    print(f"[parity] n32768 full V", flush=True)
+    r = D.eig(d, z, rho, opts=D.opts(root=1), want_stats=True)
+    lam = r.lam.cpu().numpy()
+    st = r.stats_dict()
+    print(f"[parity] n32768 stats {st}", flush=True)
+    assert np.all(np.diff(lam) < 0)
+    assert lam[0] > d[0] and np.all(lam[1:] >= d[1:]) and np.all(lam[1:] <= d[:-1])
+
+    # sample: the ends, the middle, the smallest relative gaps, the smallest |lambda|, random
+    gap = np.minimum(np.abs(np.diff(lam, prepend=np.inf)), np.abs(np.diff(lam, append=-np.inf)))
+    rng = np.random.default_rng(77)
+    ks = np.unique(np.concatenate([
+        [0, 1, 2, n // 2, n - 2, n - 1],
+        np.argsort(gap / np.abs(lam))[:16],
+        np.argsort(np.abs(lam))[:8],
+        rng.choice(n, 40, replace=False)])).astype(np.int64)
+    lo, Vo, _ = orc.eig_some(d, z, rho, ks, vectors=True)
+    Vt = r.V.t()                                          # rows = eigenvectors
+    Vs = Vt[torch.as_tensor(ks, device=Vt.device)].cpu().numpy().T
+    el = rel(lam[ks], lo)
+    ev = rel(Vs, Vo)
+    print(f"[parity] n32768 sample {ks.size}: max rel lam {el.max():.3e} V {ev.max():.3e}", flush=True)
+    assert el.max() <= LAM_TOL, (ks[np.argmax(el)], el.max())
+    assert ev.max() <= VEC_TOL, (np.unravel_index(np.argmax(ev), ev.shape), ev.max())
+
+    # properties of every eigenpair, checked on the device in column chunks
+    dd = torch.as_tensor(d, device=Vt.device)
+    zz = torch.as_tensor(z, device=Vt.device)
+    anorm = float(np.max(np.abs(d)) + abs(rho) * np.dot(z, z))
+    worst_norm = 0.0
+    worst_res = 0.0
+    for k0 in range(0, n, 4096):
+        blk = Vt[k0:k0 + 4096]
+        lb = r.lam[k0:k0 + 4096]
+        worst_norm = max(worst_norm, float((torch.linalg.vector_norm(blk, dim=1) - 1.0).abs().max()))
+        res = blk * (dd[None, :] - lb[:, None]) + rho * (blk @ zz)[:, None] * zz[None, :]
+        worst_res = max(worst_res, float(res.abs().max()) / anorm)
+        del res
+    print(f"[parity] n32768 all pairs: max | ||v|| - 1 | {worst_norm:.3e} max residual {worst_res:.3e}",
+          flush=True)
+    assert worst_norm <= 1e-13
+    # the residual's own rounding: the length-n product z^T v alone may round by n*u*||z||*||v||
+    assert worst_res <= 1e-12
