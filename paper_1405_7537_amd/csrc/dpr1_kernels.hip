@@ -366,10 +366,10 @@ __device__ __forceinline__ void model_step(double m, double g, double Sz, double
   const double nn0 = model_root(m, Sz, Spz, Sppz, bp, xm, wm, L, U);
   double nn = nn0;
   const double step = fabs(nn - m);
-  // Cubic convergence: after a step below 2^-20 the iterate is within about
-  // 2^-60 of the root up to the model's constant, and the accurate last pass
-  // finishes the job.  That pass accepts its own step only below 2^-30 (tol),
-  // so that even a large model constant leaves the root exact to rounding.
+  // Cubic convergence: a step e leaves a model error of about 8 e^3 (the
+  // shift keeps every pole at least nu/2 from the root), so after a step
+  // below 2^-20 the new iterate is exact to rounding.  The same tolerance
+  // accepts the step of the accurate last pass.
   if (step <= tol * m) {
     done = true;
     nu0 = (nn >= L && nn <= U) ? nn : m;
@@ -663,7 +663,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // bisection m is the converged bracket end and the last step is Newton's;
   // in the model iteration m is the converged iterate (or the next one for a
   // lane that has not converged) and the last step is the model's, which is
-  // accepted when it is below 2^-30 relative.  Right of every pole all terms
+  // accepted when it is below 2^-20 relative.  Right of every pole all terms
   // are positive, so the Neumaier sum takes the larger operand first by value.
   const double m = (A.root == 0 || done) ? nu0 : nu;
   double cs = 0.0, cc = 0.0;
@@ -728,7 +728,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // zeta_i^2 + sum_{j != i} zeta_j^2/pp_j^2, the S' sum of the accurate pass.
   // That sum is taken at m and carried to nu1 = m + h by its Taylor series to
   // second order (derivatives -2 sum zeta^2 delta'/pp^3 and 6 sum zeta^2
-  // delta'^2/pp^4; |h|/(m - xi_j) <= 2^-29, so the error is below 2^-85).
+  // delta'^2/pp^4; |h|/(m - xi_j) <= 2^-19, so the error is below 2^-55).
   const double h = nu1 - m;
   double Nx[1] = {zi2 + ((Sp[0] - 2.0 * h * Sp[1]) + 3.0 * (h * h) * Sp[2])};
   if (wv == 0 && valid) {
