@@ -30,11 +30,12 @@ HBM_PEAK_GBS = 8000.0
 # peak counts them: a fused multiply-add is 2, an add, multiply or division 1
 # (the Newton refinement of the hardware reciprocal is not counted).
 FLOPS_SHIFT = 10          # (d_j - d_k) - tau (2), 1/den, t, t/den, 3 adds, fma for t/den^2 (2)
-FLOPS_TIP = 25            # TwoSum d_j - sigma (6), 1/dl, quotient + residual (7), DD add (11)
+FLOPS_TIP = 19            # TwoSum d_j - sigma (6), 1/dl, quotient + residual (7), compensated add (5)
 FLOPS_ROOT_MODEL = 14     # per pass: delta' (2), nu delta' - 1 (2), q, 1/q, t, 1/pp (2), tp, tp3, 3 adds
 FLOPS_ROOT_BISECT = 7     # per pass: delta' (2), nu delta' - 1 (2), q, 1/q, add
-FLOPS_FINAL = 23          # accurate last pass: delta', pp (4), q, 1/q, t, corrected quotient (4),
-                          # 1/pp (2), tp, tp3, tp4, Neumaier sum (4), 3 adds
+FLOPS_FINAL = 20.375      # accurate last pass: delta', pp (4), q, 1/q, t, corrected quotient (4),
+                          # 1/pp (2), tp, tp3, tp4, 3 adds, and the sum of t: a tree over blocks
+                          # of eight (7/8) feeding a Neumaier sum (4/8)
 
 
 def flops_per_pair(root, passes_mean):

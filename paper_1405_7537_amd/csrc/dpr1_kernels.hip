@@ -102,12 +102,13 @@ __device__ __forceinline__ double fmid(double lo, double hi) {
 }
 __device__ __forceinline__ bool adjacent(double lo, double hi) { return bits(hi) - bits(lo) <= 1; }
 
-// Reciprocal from the hardware estimate refined by one Newton step: enough
-// where only a sign or a model step is needed, and as the seed of a quotient
-// that is then corrected by its residual (within about half an ulp more than
-// correct rounding).  v_rcp_f64 is good to 2^-24.4 relative (measured on
-// gfx950 over random normal inputs); one Newton step gives 2^-48.7.  The IEEE
-// divide costs about twice as many instructions on this ISA.
+// Reciprocal from the hardware estimate refined by one Newton step: for the
+// signs that steer bisection, and as the seed of a quotient that is then
+// corrected by its residual (within about half an ulp more than correct
+// rounding).  v_rcp_f64 is specified to 2^29 ulp (2^-23 relative) and
+// measured at 2^-24.4 on gfx950 over random normal inputs; one Newton step
+// gives 2^-48.7.  The IEEE divide costs about twice as many instructions on
+// this ISA.
 __device__ __forceinline__ double rcp_1nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = __builtin_fma(-x, r, 1.0);
@@ -169,7 +170,9 @@ __device__ __forceinline__ void wg_sum_dd(dd& a, int W, int wv, int lane, double
 // Walk the wave's slice [j0, j1) of the inner index in three segments:
 // below the window of shift indices this wave can own (seg 0: every lane has
 // j < i), inside it (seg 1: per-lane test), above it (seg 2: every lane has
-// j > i).  j is wave-uniform in all three loops.
+// j > i).  j is wave-uniform in all three loops.  The last argument of f is
+// the position u = 0..7 of the pair in its block of eight (a compile-time
+// constant once unrolled), or -1 for the pairs after the last whole block.
 template <class F>
 __device__ __forceinline__ void sweep_seg(const double* P, int a, int b, int seg, F& f) {
   // blocks of 8 pairs: all 16 scalar loads are issued before the first use,
@@ -182,9 +185,9 @@ __device__ __forceinline__ void sweep_seg(const double* P, int a, int b, int seg
     for (int t = 0; t < 16; ++t) c[t] = ldu(q, t);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) f(j + u, seg, c[2 * u], c[2 * u + 1]);
+    for (int u = 0; u < 8; ++u) f(j + u, seg, c[2 * u], c[2 * u + 1], u);
   }
-  for (; j < b; ++j, q += 2) f(j, seg, ldu(q, 0), ldu(q, 1));
+  for (; j < b; ++j, q += 2) f(j, seg, ldu(q, 0), ldu(q, 1), -1);
 }
 
 template <class F>
@@ -454,9 +457,12 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // For k = 1 there is no shift to choose; the pass evaluates f at the first
   // point of the root search instead, lambda = d_1 + 1/nux.
   const double tau = kk > 0 ? (dkm1 - dk) / 2 : 1.0 / nux;
+  // Only the sign of F and a first model step are taken from these sums, so
+  // the reciprocal is the hardware estimate alone (relative error below
+  // 2^-23): the bounds taken from the probe allow for it.
   double Fs[4] = {0.0, 0.0, 0.0, 0.0};
-  sweep(P, j0, j1, wlo, whi, [&](int j, int, double dj, double z2) {
-    double r = rcp_1nr((dj - dk) - tau);
+  sweep(P, j0, j1, wlo, whi, [&](int j, int, double dj, double z2, int) {
+    double r = __builtin_amdgcn_rcp((dj - dk) - tau);
     double t = z2 * r;
     double tr = t * r;
     Fs[0] += t;
@@ -477,15 +483,19 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // of eq. (knu2).  P collects j < i (delta > 0), N collects j > i.
   // Each term zeta_j^2/(d_j - sigma) is formed as q1 + q2 from the exact
   // difference (TwoSum), the exact square (hi + lo) and one residual
-  // correction, relative error about 2^-100; P and N each add terms of one
-  // sign only, so their double-double sums do not cancel.
-  dd Pd = {0.0, 0.0}, Nd = {0.0, 0.0};
-  auto add_to = [](dd& a, double q1, double q2) {
-    dd t = two_sum(a.hi, q1);
-    t.lo += a.lo + q2;
-    a = fast_two_sum(t.hi, t.lo);
+  // correction, relative error about 2^-100.  P and N each add terms of one
+  // sign (N adds the negated terms), so max/min by value orders the operands
+  // by magnitude: each sum is a Neumaier compensated sum of the q1 whose
+  // compensation also collects the q2.  Its error is O(n eps^2) of the sum,
+  // as for a double-double accumulation, at 7 operations a term instead of 11.
+  double ps = 0.0, pc = 0.0, ns = 0.0, nc = 0.0;
+  auto acc = [](double& a, double& c, double q1, double q2) {
+    const double hi = fmax(a, q1), lo = fmin(a, q1);
+    const double y = hi + lo;
+    c += ((hi - y) + lo) + q2;
+    a = y;
   };
-  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2) {
+  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, int) {
     double z2l = ldu(Zl, j);
     dd dl = two_sum(dj, -sigma);  // exact d_j - sigma
     double r = rcp_1nr(dl.hi);
@@ -494,16 +504,18 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     e = __builtin_fma(-q1, dl.lo, e + z2l);
     double q2 = e * r;
     if (seg == 0) {
-      add_to(Pd, q1, q2);
+      acc(ps, pc, q1, q2);
     } else if (seg == 2) {
-      add_to(Nd, q1, q2);
+      acc(ns, nc, -q1, -q2);
     } else if (j != i) {
-      dd pn = Pd, nn = Nd;
-      add_to(pn, q1, q2);
-      add_to(nn, q1, q2);
-      if (j < i) Pd = pn; else Nd = nn;
+      const bool up = j < i;
+      double a = up ? ps : ns, c = up ? pc : nc;
+      acc(a, c, up ? q1 : -q1, up ? q2 : -q2);
+      if (up) { ps = a; pc = c; } else { ns = a; nc = c; }
     }
   });
+  dd Pd = fast_two_sum(ps, pc);
+  dd Nd = fast_two_sum(-ns, -nc);
   wg_sum_dd(Pd, W, wv, lane, red);
   wg_sum_dd(Nd, W, wv, lane, red);
   const dd rr = dd_div(dd{1.0, 0.0}, dd{rho, 0.0});
@@ -553,7 +565,9 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   bool pre = valid;
   double pre_Sz = 0.0, pre_Spz = 0.0, pre_Sppz = 0.0, pre_g = 0.0;
   if (pre) {
-    const double gerr = 8.0 * 2.220446049250313e-16 * (1.0 + rho * Fs[1]) / (rho * zi2);
+    // error of f(lambda) from the estimated reciprocals: 2^-23 of |terms|,
+    // taken with a margin of 8
+    const double gerr = 0x1p-20 * (1.0 + rho * Fs[1]) / (rho * zi2);
     pre_g = s * (1.0 + rho * Fs[0]) / (rho * zi2);
     pre_Sz = (pre_g - bp) + nu;
     // g' = -F2/(zeta_i^2 nu^2) and g'' = 2 (s F3/nu^4 + F2/nu^3)/zeta_i^2 with
@@ -579,7 +593,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double m = nu;
       double S[1] = {0.0};
       if (wave_any(!done && !pre)) {
-        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2) {
+        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, int) {
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
           double t = z2 * rcp_1nr(dl * pp);
@@ -617,10 +631,10 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double m = nu;
       double S[3] = {0.0, 0.0, 0.0};
       if (wave_any(!done && !pre)) {
-        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2) {
+        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, int) {
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
-          double rq = rcp_1nr(dl * pp);
+          double rq = __builtin_amdgcn_rcp(dl * pp);
           double t = z2 * rq;           // w_j/(m - xi_j)
           double u = (dl * rq) * dl;    // delta'_j/pp = 1/(m - xi_j)
           double tp = t * u;            // w_j/(m - xi_j)^2
@@ -650,7 +664,11 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
           g = pre_g;
           pre = false;  // bracket already set from the probe
         } else {
-          if (g > 0) L = m; else U = m;
+          // the terms of a plain pass carry the error of the estimated
+          // reciprocal (below 2^-23, all terms positive): a sign of g within
+          // that error leaves the bracket as it is
+          const double gtol = 0x1p-20 * Sz + 0x1p-50 * fabs(bp);
+          if (g > gtol) L = m; else if (g < -gtol) U = m;
         }
         model_step(m, g, Sz, Spz, Sppz, bp, xm, wm, iters, L, U, nu, nu0, prevstep, g1, g2, done);
       }
@@ -664,11 +682,20 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // in the model iteration m is the converged iterate (or the next one for a
   // lane that has not converged) and the last step is the model's, which is
   // accepted when it is below 2^-20 relative.  Right of every pole all terms
-  // are positive, so the Neumaier sum takes the larger operand first by value.
+  // are positive: the eight terms of a block are added as a tree of depth 3
+  // (error at most 3 eps of the block sum), and the block sums go into a
+  // Neumaier sum, which takes the larger operand first by value.
   const double m = (A.root == 0 || done) ? nu0 : nu;
   double cs = 0.0, cc = 0.0;
   double Sp[3] = {0.0, 0.0, 0.0};
-  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2) {
+  double ga = 0.0, gb = 0.0, gc = 0.0;
+  auto neu = [&](double t) {
+    const double hi = fmax(cs, t), lo = fmin(cs, t);
+    const double y = hi + lo;
+    cc += (hi - y) + lo;
+    cs = y;
+  };
+  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, int ub) {
     double dl = __builtin_fma(s, dj, nss);
     double pp = __builtin_fma(m, dl, -1.0);
     double q = dl * pp;
@@ -685,10 +712,17 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       tp3 = 0.0;
       tp4 = 0.0;
     }
-    const double hi = fmax(cs, t), lo = fmin(cs, t);
-    const double y = hi + lo;
-    cc += (hi - y) + lo;
-    cs = y;
+    switch (ub) {
+      case 0: ga = t; break;
+      case 1: ga += t; break;
+      case 2: gb = t; break;
+      case 3: gb += t; ga += gb; break;
+      case 4: gb = t; break;
+      case 5: gb += t; break;
+      case 6: gc = t; break;
+      case 7: gc += t; gb += gc; ga += gb; neu(ga); break;
+      default: neu(t);
+    }
     Sp[0] += tp;
     Sp[1] += tp3;
     Sp[2] += tp4;
