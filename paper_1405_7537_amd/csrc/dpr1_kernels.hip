@@ -170,31 +170,71 @@ __device__ __forceinline__ void wg_sum_dd(dd& a, int W, int wv, int lane, double
 // Walk the wave's slice [j0, j1) of the inner index in three segments:
 // below the window of shift indices this wave can own (seg 0: every lane has
 // j < i), inside it (seg 1: per-lane test), above it (seg 2: every lane has
-// j > i).  j is wave-uniform in all three loops.  The last argument of f is
-// the position u = 0..7 of the pair in its block of eight (a compile-time
-// constant once unrolled), or -1 for the pairs after the last whole block.
-template <class F>
-__device__ __forceinline__ void sweep_seg(const double* P, int a, int b, int seg, F& f) {
-  // blocks of 8 pairs: all 16 scalar loads are issued before the first use,
-  // so a block waits for its data once
+// j > i).  j is wave-uniform in all three loops.  f(j, seg, d_j, zeta_j^2,
+// low part of zeta_j^2 (0 unless asked for), u) with u the position of the
+// pair in its block (a compile-time constant once unrolled), or -1 for the
+// pairs after the last whole block.
+template <bool LO, class F>
+__device__ __forceinline__ void sweep_seg(const double* P, const double* Zl, int a, int b, int seg, F& f) {
+  // Blocks of B pairs (with LO also the B low parts of zeta_j^2), software-
+  // pipelined: the scalar loads of the next block are issued before the
+  // current block is computed, so their latency hides behind that work.  A
+  // wait for scalar loads covers all of them, so no load may be waited for
+  // inside the computation; with LO the blocks are halved to keep both
+  // blocks in scalar registers.
+  constexpr int B = LO ? 4 : 8;
+  constexpr int NV = LO ? 3 * B : 2 * B;
+  auto load = [](double (&c)[NV], const double* q, const double* ql) {
+#pragma unroll
+    for (int t = 0; t < 2 * B; ++t) c[t] = ldu(q, t);
+    if constexpr (LO) {
+#pragma unroll
+      for (int t = 0; t < B; ++t) c[2 * B + t] = ldu(ql, t);
+    }
+  };
   const double* q = P + 2 * (int64_t)a;
+  const double* ql = LO ? Zl + a : nullptr;
   int j = a;
-  for (; j + 8 <= b; j += 8, q += 16) {
-    double c[16];
+  if (j + B <= b) {
+    double c[NV];
+    load(c, q, ql);
+    // wait for the first block here (s_waitcnt lgkmcnt(0)): otherwise the wait
+    // for it lands inside the loop, where it also waits for the prefetch
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    for (; j + 2 * B <= b; j += B, q += 2 * B, ql += LO ? B : 0) {
+      double nx[NV];
+      load(nx, q + 2 * B, LO ? ql + B : nullptr);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int t = 0; t < 16; ++t) c[t] = ldu(q, t);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int u = 0; u < B; ++u) f(j + u, seg, c[2 * u], c[2 * u + 1], LO ? c[2 * B + u] : 0.0, u);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) f(j + u, seg, c[2 * u], c[2 * u + 1], u);
+      for (int t = 0; t < NV; ++t) c[t] = nx[t];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) f(j + u, seg, c[2 * u], c[2 * u + 1], LO ? c[2 * B + u] : 0.0, u);
+    j += B;
+    q += 2 * B;
+    ql += LO ? B : 0;
   }
-  for (; j < b; ++j, q += 2) f(j, seg, ldu(q, 0), ldu(q, 1), -1);
+  for (; j < b; ++j, q += 2, ql += LO ? 1 : 0)
+    f(j, seg, ldu(q, 0), ldu(q, 1), LO ? ldu(ql, 0) : 0.0, -1);
 }
 
 template <class F>
 __device__ __forceinline__ void sweep(const double* P, int j0, int j1, int wlo, int whi, F&& f) {
-  sweep_seg(P, j0, min(j1, wlo), 0, f);
-  sweep_seg(P, max(j0, wlo), min(j1, whi), 1, f);
-  sweep_seg(P, max(j0, whi), j1, 2, f);
+  sweep_seg<false>(P, nullptr, j0, min(j1, wlo), 0, f);
+  sweep_seg<false>(P, nullptr, max(j0, wlo), min(j1, whi), 1, f);
+  sweep_seg<false>(P, nullptr, max(j0, whi), j1, 2, f);
+}
+
+// the same walk, also handing f the low part of zeta_j^2 from Zl
+template <class F>
+__device__ __forceinline__ void sweep_lo(const double* P, const double* Zl, int j0, int j1, int wlo, int whi,
+                                         F&& f) {
+  sweep_seg<true>(P, Zl, j0, min(j1, wlo), 0, f);
+  sweep_seg<true>(P, Zl, max(j0, wlo), min(j1, whi), 1, f);
+  sweep_seg<true>(P, Zl, max(j0, whi), j1, 2, f);
 }
 
 // ------------------------------------------------------------------ prep
@@ -461,7 +501,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // the reciprocal is the hardware estimate alone (relative error below
   // 2^-23): the bounds taken from the probe allow for it.
   double Fs[4] = {0.0, 0.0, 0.0, 0.0};
-  sweep(P, j0, j1, wlo, whi, [&](int j, int, double dj, double z2, int) {
+  sweep(P, j0, j1, wlo, whi, [&](int j, int, double dj, double z2, double, int) {
     double r = __builtin_amdgcn_rcp((dj - dk) - tau);
     double t = z2 * r;
     double tr = t * r;
@@ -495,8 +535,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     c += ((hi - y) + lo) + q2;
     a = y;
   };
-  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, int) {
-    double z2l = ldu(Zl, j);
+  sweep_lo(P, Zl, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, double z2l, int) {
     dd dl = two_sum(dj, -sigma);  // exact d_j - sigma
     double r = rcp_1nr(dl.hi);
     double q1 = z2 * r;
@@ -593,7 +632,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double m = nu;
       double S[1] = {0.0};
       if (wave_any(!done && !pre)) {
-        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, int) {
+        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, double, int) {
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
           double t = z2 * rcp_1nr(dl * pp);
@@ -631,7 +670,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
       double m = nu;
       double S[3] = {0.0, 0.0, 0.0};
       if (wave_any(!done && !pre)) {
-        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, int) {
+        sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, double, int) {
           double dl = __builtin_fma(s, dj, nss);
           double pp = __builtin_fma(m, dl, -1.0);
           double rq = __builtin_amdgcn_rcp(dl * pp);
@@ -695,7 +734,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     cc += (hi - y) + lo;
     cs = y;
   };
-  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, int ub) {
+  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, double, int ub) {
     double dl = __builtin_fma(s, dj, nss);
     double pp = __builtin_fma(m, dl, -1.0);
     double q = dl * pp;
