@@ -60,6 +60,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip batched / fwd+bwd / eigenvalues-only lines")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="default launch shape instead of the autotuned one (tuning cache or a fresh tuning run)")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="fill the tuning cache for every solve this bench times, then exit")
     ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
                     help="copy: a plain device copy of known size, to calibrate HBM byte counters")
     ap.add_argument("--only", default=None, choices=["batched", "fwd_bwd"],
@@ -107,7 +111,12 @@ def main():
         return D.eig(d, z, rho, vectors=vectors, opts=o, check=False, out=out if vectors else
                      (lam, None, idx, mu, xn, info), work=work, want_stats=want_stats)
 
-    base = D.opts(root=args.root)
+    base, tune = tuned(D, args, d, z, rho, vectors=True)
+    base_ev, tune_ev = tuned(D, args, d, z, rho, vectors=False)
+    if args.tune_only:
+        bench_batched(D, W, torch, dev, args)
+        print(json.dumps({"mode": "tune-only", "n": n, "vectors": tune, "eigenvalues_only": tune_ev}), flush=True)
+        return
     for _ in range(args.warmup):
         step(base)
     torch.cuda.synchronize()
@@ -117,7 +126,7 @@ def main():
     assert int(info.item()) == 0
     t0 = time.perf_counter()
     for s in range(args.steps):
-        step(D.opts(root=args.root, events=ev[s].ptr))
+        step(D.opts(root=args.root, split=base.split, main_passes=base.main_passes, events=ev[s].ptr))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -159,7 +168,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single DPR1 n={n}, all eigenvalues + full V (FP64), d~U[-1,1] sorted, "
                                f"z~N(0,1)/sqrt(n), rho=1, seed 2",
-                   "n": n, "root": "model" if args.root == 1 else "bisection"},
+                   "n": n, "root": "model" if args.root == 1 else "bisection", "tuning": tune},
         "roofline": {"bound": "alu", "kernel": "k_eig", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "flops_per_pair": fpp, "kernel_ms": eig_ms},
@@ -195,14 +204,14 @@ def main():
     if not args.no_extra:
         # eigenvalues only
         for _ in range(2):
-            step(base, vectors=False)
+            step(base_ev, vectors=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(base, vectors=False)
+            step(base_ev, vectors=False)
         torch.cuda.synchronize()
         ms_ev = (time.perf_counter() - t0) * 1e3 / args.steps
-        result["eigenvalues_only"] = {"value": n / (ms_ev / 1e3), "ms_per_step": ms_ev}
+        result["eigenvalues_only"] = {"value": n / (ms_ev / 1e3), "ms_per_step": ms_ev, "tuning": tune_ev}
         del Vt, out
         torch.cuda.empty_cache()
         result["batched"] = bench_batched(D, W, torch, dev, args)
@@ -237,13 +246,36 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
+def tuned(D, args, d, z, rho, vectors):
+    """Options of the timed solves: the autotuned split and pass budget (tuning cache, else a tuning
+    run before any timing), or the defaults with --no-tune.  Returns (opts, description)."""
+    o = D.opts(root=args.root)
+    if args.no_tune:
+        return o, {"split": "default", "main_passes": "default"}
+    from paper_1405_7537_amd import tuning
+    o, entry, hit = tuning.tuned_opts(d, z, rho, vectors=vectors, opts=o)
+    log(f"[bench] tuned (vectors={vectors}): split {o.split}, main_passes {o.main_passes} "
+        f"({'cache' if hit else 'tuned now'}, {entry['ms']:.3f} ms)")
+    return o, {"split": int(o.split), "main_passes": int(o.main_passes), "from_cache": bool(hit)}
+
+
 def bench_batched(D, W, torch, dev, args):
     d_h, z_h, rho_h, offs = W.batched(2048, 3)
     sizes = np.diff(offs)
     d = torch.as_tensor(d_h, device=dev)
     z = torch.as_tensor(z_h, device=dev)
     rho = torch.as_tensor(rho_h, device=dev)
-    b = D.Batch(offs, opts=D.opts(root=args.root))
+    if args.no_tune:
+        b = D.Batch(offs, opts=D.opts(root=args.root))
+        tune = {"split": int(b.plan.split), "main_passes": "default"}
+    else:
+        from paper_1405_7537_amd import tuning
+        b, entry, hit = tuning.tuned_batch(offs, d, z, rho, opts=D.opts(root=args.root))
+        tune = {"split": int(b.plan.split), "main_passes": int(b.plan.opts.main_passes), "from_cache": bool(hit)}
+        log(f"[bench] batched tuned: split {tune['split']}, main_passes {tune['main_passes']} "
+            f"({'cache' if hit else 'tuned now'}, {entry['ms']:.3f} ms)")
+    if args.tune_only:
+        return tune
     N = int(offs[-1])
     for _ in range(2):
         b.solve(d, z, rho)
@@ -282,7 +314,7 @@ def bench_batched(D, W, torch, dev, args):
     log(f"[bench] batched mix N={N}: persistent {ms_p:.3f} ms, one launch each {ms_e:.3f} ms")
     res = {"workload": "2048 DPR1 problems, sizes log-uniform in [16,2048] (seed 3), all eigenpairs + V",
            "ntotal": N, "sum_n2": int(np.sum(sizes ** 2)),
-           "persistent": {"value": N / (ms_p / 1e3), "unit": "eigenpairs/s", "ms_per_step": ms_p},
+           "persistent": {"value": N / (ms_p / 1e3), "unit": "eigenpairs/s", "ms_per_step": ms_p, "tuning": tune},
            "one_launch_each": {"value": N / (ms_e / 1e3), "unit": "eigenpairs/s", "ms_per_step": ms_e}}
     del b, views
     torch.cuda.empty_cache()

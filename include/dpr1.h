@@ -162,6 +162,31 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
                      int32_t* info, int32_t* stats, void* work, size_t work_bytes,
                      void* stream);
 
+/* Autotuning (not in the paper): the launch shape is chosen by measurement.
+ * The candidates are the split W in {1, 2, 4, 8, 16} (waves sharing one block
+ * of 64 eigenvalues, i.e. W threads per eigenvalue; every wave's slice of the
+ * inner sum keeps at least 64 terms) and, for the model iteration (root = 1),
+ * the pass budget main_passes ({2, 3} single, {2, 3, 4} batched).  Each
+ * candidate is solved once untimed and then `reps` times (0 = 3) between two
+ * events on `stream`; the fastest mean wins, ties keep the smaller W and the
+ * smaller budget.  Both calls run on the caller's data and buffers, leave a
+ * valid solution in the outputs (that of the last candidate, equal to the
+ * tuned one's within the parity bounds) and synchronise `stream`.
+ * dpr1_autotune: arguments as dpr1_eig; opts (in/out, required) supplies the
+ *   other options and receives the chosen split and main_passes; best_ms
+ *   (optional) the fastest mean time.
+ * dpr1_batched_autotune: arguments as dpr1_eig_batched; plan (in/out, from
+ *   dpr1_batched_plan for these offsets) receives the chosen split, grid and
+ *   main_passes.  Return codes as the solves they time; -13 reps < 0.        */
+int dpr1_autotune(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V,
+                  int64_t ldv, int32_t* shift_idx, double* mu, double* xnorm, int32_t* info,
+                  dpr1_opts* opts, int32_t reps, double* best_ms, void* work, size_t work_bytes,
+                  void* stream);
+int dpr1_batched_autotune(dpr1_plan* plan, const int64_t* offs, const double* d, const double* z,
+                          const double* rho, double* lambda, double* V, const int64_t* voffs,
+                          int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, int32_t reps,
+                          double* best_ms, void* work, size_t work_bytes, void* stream);
+
 /* Reverse mode (not in the paper; standard eigenvalue perturbation theory).
  * For L(Lambda, V) with lambda_bar = dL/dlambda, V_bar = dL/dV:
  *   Abar = V X V^T,  X = diag(lambda_bar) + F o (V^T V_bar),

@@ -1525,6 +1525,46 @@ static int pick_split(int64_t nblocks, int64_t nmax) {
   return (int)std::max<int64_t>(w, 1);
 }
 
+// Blocks of the persistent batched k_eig: 16 waves per CU at this kernel's
+// register use (4 per SIMD), never more blocks than work items.
+static int32_t persistent_grid_for(int64_t nitems, int W) {
+  return (int32_t)std::min<int64_t>(nitems, std::max<int64_t>(1, (int64_t)(256 * 16) / W));
+}
+
+// ------------------------------------------------------------ autotuning
+// Mean duration in ms of `reps` calls of `solve` after one untimed call,
+// between two events on stream st.
+template <class F>
+static int time_calls(F&& solve, int reps, hipStream_t st, double* ms) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return DPR1_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DPR1_EHIP;
+  }
+  int rc = solve();
+  if (rc == 0 && hipEventRecord(e0, st) != hipSuccess) rc = DPR1_EHIP;
+  for (int r = 0; r < reps && rc == 0; ++r) rc = solve();
+  if (rc == 0 && hipEventRecord(e1, st) != hipSuccess) rc = DPR1_EHIP;
+  if (rc == 0 && hipEventSynchronize(e1) != hipSuccess) rc = DPR1_EHIP;
+  float t = 0.0f;
+  if (rc == 0 && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = DPR1_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)t / reps;
+  return rc;
+}
+
+// Candidate splits for inner length nmax (the largest problem): W waves
+// share one block of 64 eigenvalues (W threads per eigenvalue), and every
+// wave's slice of the inner sum keeps at least 64 terms.
+static int split_candidates(int64_t nmax, int* out) {
+  int c = 0;
+  for (int w = 1; w <= MAXW; w *= 2)
+    if (w == 1 || nmax / w >= 64) out[c++] = w;
+  return c;
+}
+
 // Number of (problem, column group, row tile) blocks of the batched
 // eigenvector launch.
 static int64_t count_groups(int64_t nprob, const int64_t* offs) {
@@ -1748,7 +1788,7 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   plan->nitems = nitems;
   plan->nmax = nmax;
   plan->split = W;
-  plan->grid = (int32_t)std::min<int64_t>(nitems, std::max<int64_t>(1, (int64_t)(256 * 16) / W));
+  plan->grid = persistent_grid_for(nitems, W);
   plan->opts = o;
   return DPR1_OK;
 }
@@ -1771,6 +1811,82 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
   return launch_solve(L, (char*)work, plan->nprob, plan->ntotal, offs, 0, d, z, rho, 0.0, lambda, V, voffs, 0,
                       shift_idx, mu, xnorm, info, stats, plan->opts, plan->split, plan->nitems, plan->grid,
                       plan->ngroups, (hipStream_t)stream);
+}
+
+// Autotuning: every candidate (split, pass budget) is timed on the caller's
+// data and the fastest kept; ties keep the earlier candidate.
+int dpr1_autotune(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V,
+                  int64_t ldv, int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, dpr1_opts* opts,
+                  int32_t reps, double* best_ms, void* work, size_t work_bytes, void* stream) {
+  if (!opts) return -12;
+  if (reps < 0) return -13;
+  if (reps == 0) reps = 3;
+  dpr1_opts o;
+  fill_opts(opts, &o);
+  o.events = nullptr;
+  int ws[8];
+  const int nw = split_candidates(n, ws);
+  const int passes[2] = {2, 3};
+  const int np = o.root == 1 ? 2 : 1;
+  double best = INFINITY;
+  int bw = ws[0], bp = o.main_passes;
+  for (int a = 0; a < nw; ++a)
+    for (int b = 0; b < np; ++b) {
+      dpr1_opts c = o;
+      c.split = ws[a];
+      if (o.root == 1) c.main_passes = passes[b];
+      double ms = 0.0;
+      int rc = time_calls([&]() { return dpr1_eig(d, z, rho, n, lambda, V, ldv, shift_idx, mu, xnorm, info,
+                                                  nullptr, &c, work, work_bytes, stream); },
+                          reps, (hipStream_t)stream, &ms);
+      if (rc != 0) return rc;
+      if (ms < best) {
+        best = ms;
+        bw = c.split;
+        bp = c.main_passes;
+      }
+    }
+  opts->split = bw;
+  opts->main_passes = bp;
+  if (best_ms) *best_ms = best;
+  return DPR1_OK;
+}
+
+int dpr1_batched_autotune(dpr1_plan* plan, const int64_t* offs, const double* d, const double* z,
+                          const double* rho, double* lambda, double* V, const int64_t* voffs,
+                          int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, int32_t reps,
+                          double* best_ms, void* work, size_t work_bytes, void* stream) {
+  if (!plan || plan->nprob < 1) return -1;
+  if (reps < 0) return -13;
+  if (reps == 0) reps = 3;
+  const dpr1_plan base = *plan;
+  int ws[8];
+  const int nw = split_candidates(base.nmax, ws);
+  const int passes[3] = {2, 3, 4};
+  const int np = base.opts.root == 1 ? 3 : 1;
+  double best = INFINITY;
+  dpr1_plan bestp = base;
+  for (int a = 0; a < nw; ++a)
+    for (int b = 0; b < np; ++b) {
+      dpr1_plan c = base;
+      c.split = ws[a];
+      c.grid = persistent_grid_for(c.nitems, ws[a]);
+      c.opts.events = nullptr;
+      if (base.opts.root == 1) c.opts.main_passes = passes[b];
+      double ms = 0.0;
+      int rc = time_calls([&]() { return dpr1_eig_batched(&c, offs, d, z, rho, lambda, V, voffs, shift_idx, mu,
+                                                          xnorm, info, nullptr, work, work_bytes, stream); },
+                          reps, (hipStream_t)stream, &ms);
+      if (rc != 0) return rc;
+      if (ms < best) {
+        best = ms;
+        bestp = c;
+      }
+    }
+  bestp.opts.events = base.opts.events;
+  *plan = bestp;
+  if (best_ms) *best_ms = best;
+  return DPR1_OK;
 }
 
 const char* dpr1_strerror(int code) {

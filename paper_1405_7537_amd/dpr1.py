@@ -56,6 +56,10 @@ def lib():
                                         vp, C.c_size_t, vp]
         L.dpr1_eig_batched.argtypes = [C.POINTER(Plan), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                        vp, vp, C.c_size_t, vp]
+        L.dpr1_autotune.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, vp, vp, vp, C.POINTER(Opts),
+                                    C.c_int32, C.POINTER(C.c_double), vp, C.c_size_t, vp]
+        L.dpr1_batched_autotune.argtypes = [C.POINTER(Plan), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                            C.c_int32, C.POINTER(C.c_double), vp, C.c_size_t, vp]
         if hasattr(L, "dpr1_backward_workspace_size"):
             L.dpr1_backward_workspace_size.argtypes = [i64, i64]
             L.dpr1_backward_workspace_size.restype = C.c_size_t
@@ -181,6 +185,34 @@ def eig(d, z, rho, vectors=True, opts: Opts | None = None, check=True, want_stat
     return r
 
 
+def autotune(d, z, rho, vectors=True, opts: Opts | None = None, reps=3, device="cuda"):
+    """Time every (split, pass budget) candidate on this problem (dpr1_autotune) and return
+    (the options with the fastest split and main_passes, its mean ms).  Synchronises the stream."""
+    d = _dev(d, device)
+    z = _dev(z, device)
+    n = d.numel()
+    dev = d.device
+    o = Opts()
+    if opts is not None:
+        C.memmove(C.byref(o), C.byref(opts), C.sizeof(Opts))
+    else:
+        lib().dpr1_default_opts(C.byref(o))
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Vt = torch.empty((n, n), dtype=torch.float64, device=dev) if vectors else None
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    mu = torch.empty(n, dtype=torch.float64, device=dev)
+    xn = torch.empty(n, dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    wb = workspace_bytes(n)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    best = C.c_double()
+    rc = lib().dpr1_autotune(_ptr(d), _ptr(z), float(rho), n, _ptr(lam), _ptr(Vt), max(n, 1), _ptr(idx), _ptr(mu),
+                             _ptr(xn), _ptr(info), C.byref(o), int(reps), C.byref(best), _ptr(work), wb,
+                             _stream())
+    _rc(rc, "dpr1_autotune")
+    return o, float(best.value)
+
+
 class Batch:
     """A planned ragged batch (sizes fixed); solve() can be called repeatedly."""
 
@@ -226,6 +258,18 @@ class Batch:
                                     _stream())
         _rc(rc, "dpr1_eig_batched")
         return self
+
+    def autotune(self, d, z, rho, reps=3):
+        """Time every (split, pass budget) candidate on this batch (dpr1_batched_autotune) and keep
+        the fastest in the plan; returns its mean ms.  Synchronises the stream."""
+        best = C.c_double()
+        rc = lib().dpr1_batched_autotune(C.byref(self.plan), _ptr(self.offs), _ptr(d), _ptr(z), _ptr(rho),
+                                         _ptr(self.lam), _ptr(self.V),
+                                         _ptr(self.voffs) if self.V is not None else None, _ptr(self.shift_idx),
+                                         _ptr(self.mu), _ptr(self.xnorm), _ptr(self.info), int(reps),
+                                         C.byref(best), _ptr(self.work), self.wb, _stream())
+        _rc(rc, "dpr1_batched_autotune")
+        return float(best.value)
 
     def vblock(self, p):
         """V of problem p as an [n_p, n_p] view (V[:, k] = v_k)."""
