@@ -126,7 +126,8 @@ def main():
     assert int(info.item()) == 0
     t0 = time.perf_counter()
     for s in range(args.steps):
-        step(D.opts(root=args.root, split=base.split, main_passes=base.main_passes, events=ev[s].ptr))
+        step(D.opts(root=args.root, split=base.split, main_passes=base.main_passes,
+                    waves_per_simd=base.waves_per_simd, events=ev[s].ptr))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -254,9 +255,10 @@ def tuned(D, args, d, z, rho, vectors):
         return o, {"split": "default", "main_passes": "default"}
     from paper_1405_7537_amd import tuning
     o, entry, hit = tuning.tuned_opts(d, z, rho, vectors=vectors, opts=o)
-    log(f"[bench] tuned (vectors={vectors}): split {o.split}, main_passes {o.main_passes} "
-        f"({'cache' if hit else 'tuned now'}, {entry['ms']:.3f} ms)")
-    return o, {"split": int(o.split), "main_passes": int(o.main_passes), "from_cache": bool(hit)}
+    log(f"[bench] tuned (vectors={vectors}): split {o.split}, waves/SIMD {o.waves_per_simd}, "
+        f"main_passes {o.main_passes} ({'cache' if hit else 'tuned now'}, {entry['ms']:.3f} ms)")
+    return o, {"split": int(o.split), "waves_per_simd": int(o.waves_per_simd), "main_passes": int(o.main_passes),
+               "from_cache": bool(hit)}
 
 
 def bench_batched(D, W, torch, dev, args):
@@ -271,9 +273,10 @@ def bench_batched(D, W, torch, dev, args):
     else:
         from paper_1405_7537_amd import tuning
         b, entry, hit = tuning.tuned_batch(offs, d, z, rho, opts=D.opts(root=args.root))
-        tune = {"split": int(b.plan.split), "main_passes": int(b.plan.opts.main_passes), "from_cache": bool(hit)}
-        log(f"[bench] batched tuned: split {tune['split']}, main_passes {tune['main_passes']} "
-            f"({'cache' if hit else 'tuned now'}, {entry['ms']:.3f} ms)")
+        tune = {"split": int(b.plan.split), "waves_per_simd": int(b.plan.opts.waves_per_simd),
+                "main_passes": int(b.plan.opts.main_passes), "from_cache": bool(hit)}
+        log(f"[bench] batched tuned: split {tune['split']}, waves/SIMD {tune['waves_per_simd']}, main_passes "
+            f"{tune['main_passes']} ({'cache' if hit else 'tuned now'}, {entry['ms']:.3f} ms)")
     if args.tune_only:
         return tune
     N = int(offs[-1])

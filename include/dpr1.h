@@ -94,7 +94,11 @@ typedef struct dpr1_opts {
                           it hands an unconverged eigenpair to the
                           cooperative kernel; 0 = default (2 for dpr1_eig,
                           3 for dpr1_eig_batched)                          */
-  int32_t reserved;
+  int32_t waves_per_simd; /* register budget of the eigenvalue kernel: 4
+                          (default, 0) waves per SIMD with up to 128 VGPRs,
+                          6 (80) or 8 (64); more waves hide more latency,
+                          fewer registers spill more of the outer state;
+                          other values are rejected                        */
   void* events;        /* profiling hook, NULL (default) = off: a host array
                           of 4 hipEvent_t that the solve records on `stream`
                           right before and after the eigenvalue kernel
@@ -163,21 +167,25 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
                      void* stream);
 
 /* Autotuning (not in the paper): the launch shape is chosen by measurement.
- * The candidates are the split W in {1, 2, 4, 8, 16} (waves sharing one block
- * of 64 eigenvalues, i.e. W threads per eigenvalue; every wave's slice of the
- * inner sum keeps at least 64 terms) and, for the model iteration (root = 1),
- * the pass budget main_passes ({2, 3} single, {2, 3, 4} batched).  Each
+ * The candidates are the split W in {1, 2, 4, 8, 12, 16} (waves sharing one
+ * block of 64 eigenvalues, i.e. W threads per eigenvalue; every wave's slice
+ * of the inner sum keeps at least 64 terms), the register budget
+ * waves_per_simd in {4, 6, 8} and, for the model iteration (root = 1), the
+ * pass budget main_passes ({2, 3} single, {2, 3, 4} batched).  Each
  * candidate is solved once untimed and then `reps` times (0 = 3) between two
- * events on `stream`; the fastest mean wins, ties keep the smaller W and the
- * smaller budget.  Both calls run on the caller's data and buffers, leave a
+ * events on `stream`; the fastest mean wins, ties keep the earlier candidate
+ * (smaller W, then fewer waves, then the smaller budget).  Both calls run on
+ * the caller's data and buffers, leave a
  * valid solution in the outputs (that of the last candidate, equal to the
  * tuned one's within the parity bounds) and synchronise `stream`.
  * dpr1_autotune: arguments as dpr1_eig; opts (in/out, required) supplies the
- *   other options and receives the chosen split and main_passes; best_ms
+ *   other options and receives the chosen split, waves_per_simd and
+ *   main_passes; best_ms
  *   (optional) the fastest mean time.
  * dpr1_batched_autotune: arguments as dpr1_eig_batched; plan (in/out, from
- *   dpr1_batched_plan for these offsets) receives the chosen split, grid and
- *   main_passes.  Return codes as the solves they time; -13 reps < 0.        */
+ *   dpr1_batched_plan for these offsets) receives the chosen split, grid,
+ *   waves_per_simd and main_passes.  Return codes as the solves they time;
+ *   -13 reps < 0.                                                            */
 int dpr1_autotune(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V,
                   int64_t ldv, int32_t* shift_idx, double* mu, double* xnorm, int32_t* info,
                   dpr1_opts* opts, int32_t reps, double* best_ms, void* work, size_t work_bytes,

@@ -849,7 +849,11 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   }
 }
 
-__global__ void __launch_bounds__(1024) k_eig(KArgs A) {
+// OCC: waves per SIMD the register allocation is made for (4: up to 128
+// VGPRs; 6: 80; 8: 64, the outer state then partly in scratch, the inner
+// sweeps unchanged), so that more waves can hide the FP64 latencies.
+template <int OCC>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) k_eig(KArgs A) {
   extern __shared__ double red[];
   if (A.items == nullptr) {
     eig_block(A, 0, blockIdx.x * WAVE, red);
@@ -1525,10 +1529,16 @@ static int pick_split(int64_t nblocks, int64_t nmax) {
   return (int)std::max<int64_t>(w, 1);
 }
 
-// Blocks of the persistent batched k_eig: 16 waves per CU at this kernel's
-// register use (4 per SIMD), never more blocks than work items.
-static int32_t persistent_grid_for(int64_t nitems, int W) {
-  return (int32_t)std::min<int64_t>(nitems, std::max<int64_t>(1, (int64_t)(256 * 16) / W));
+// k_eig occupancy variant of the options: 4 (default), 6 or 8 waves per SIMD.
+static int occ_of(const dpr1_opts& o) { return o.waves_per_simd == 0 ? 4 : o.waves_per_simd; }
+static bool occ_valid(int32_t w) { return w == 0 || w == 4 || w == 6 || w == 8; }
+
+// Blocks of the persistent batched k_eig: as many W-wave blocks as the 256
+// CUs hold at the variant's occupancy (4 SIMDs x occ waves per CU), never
+// more blocks than work items.
+static int32_t persistent_grid_for(int64_t nitems, int W, int occ) {
+  const int64_t per_cu = std::max<int64_t>(1, (4 * occ) / W);
+  return (int32_t)std::min<int64_t>(nitems, 256 * per_cu);
 }
 
 // ------------------------------------------------------------ autotuning
@@ -1557,13 +1567,16 @@ static int time_calls(F&& solve, int reps, hipStream_t st, double* ms) {
 
 // Candidate splits for inner length nmax (the largest problem): W waves
 // share one block of 64 eigenvalues (W threads per eigenvalue), and every
-// wave's slice of the inner sum keeps at least 64 terms.
+// wave's slice of the inner sum keeps at least 64 terms.  Candidate
+// occupancy variants of k_eig: 4, 6 and 8 waves per SIMD.
 static int split_candidates(int64_t nmax, int* out) {
+  static const int cand[6] = {1, 2, 4, 8, 12, 16};
   int c = 0;
-  for (int w = 1; w <= MAXW; w *= 2)
-    if (w == 1 || nmax / w >= 64) out[c++] = w;
+  for (int w : cand)
+    if (w <= MAXW && (w == 1 || nmax / w >= 64)) out[c++] = w;
   return c;
 }
+static const int OCC_CAND[3] = {4, 6, 8};
 
 // Number of (problem, column group, row tile) blocks of the batched
 // eigenvector launch.
@@ -1595,7 +1608,7 @@ void dpr1_default_opts(dpr1_opts* o) {
   o->kappa_polish = 16.0;
   o->nearzero = 10.0;
   o->main_passes = 0;
-  o->reserved = 0;
+  o->waves_per_simd = 0;
   o->events = nullptr;
 }
 
@@ -1654,7 +1667,11 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   hipEvent_t* ev = (hipEvent_t*)o.events;
   unsigned grid = persistent_grid ? (unsigned)persistent_grid : (unsigned)nitems;
   if (ev) HIPCHECK(hipEventRecord(ev[0], st));
-  hipLaunchKernelGGL(k_eig, dim3(grid), dim3(64 * W), red_bytes(W), st, A);
+  switch (occ_of(o)) {
+    case 6: hipLaunchKernelGGL(k_eig<6>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
+    case 8: hipLaunchKernelGGL(k_eig<8>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
+    default: hipLaunchKernelGGL(k_eig<4>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
+  }
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[1], st));
   // user outputs of every eigenpair (those of flagged ones are rewritten by
@@ -1720,6 +1737,7 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
   if (work_bytes < L.total) return -15;
   dpr1_opts o;
   fill_opts(opts, &o);
+  if (!occ_valid(o.waves_per_simd)) return -13;
   int64_t nblocks = (n + WAVE - 1) / WAVE;
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
   return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
@@ -1755,6 +1773,7 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   if (work_bytes < L0.total) return -6;
   dpr1_opts o;
   fill_opts(opts, &o);
+  if (!occ_valid(o.waves_per_simd)) return -3;
   // longest-processing-time order: larger problems first
   std::vector<int32_t> order(nprob);
   for (int64_t p = 0; p < nprob; ++p) order[p] = (int32_t)p;
@@ -1788,7 +1807,7 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   plan->nitems = nitems;
   plan->nmax = nmax;
   plan->split = W;
-  plan->grid = persistent_grid_for(nitems, W);
+  plan->grid = persistent_grid_for(nitems, W, occ_of(o));
   plan->opts = o;
   return DPR1_OK;
 }
@@ -1813,8 +1832,9 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
                       plan->ngroups, (hipStream_t)stream);
 }
 
-// Autotuning: every candidate (split, pass budget) is timed on the caller's
-// data and the fastest kept; ties keep the earlier candidate.
+// Autotuning: every candidate (split, occupancy variant, pass budget) is
+// timed on the caller's data and the fastest kept; ties keep the earlier
+// candidate.
 int dpr1_autotune(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V,
                   int64_t ldv, int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, dpr1_opts* opts,
                   int32_t reps, double* best_ms, void* work, size_t work_bytes, void* stream) {
@@ -1829,25 +1849,29 @@ int dpr1_autotune(const double* d, const double* z, double rho, int64_t n, doubl
   const int passes[2] = {2, 3};
   const int np = o.root == 1 ? 2 : 1;
   double best = INFINITY;
-  int bw = ws[0], bp = o.main_passes;
+  int bw = ws[0], bp = o.main_passes, bo = 4;
   for (int a = 0; a < nw; ++a)
-    for (int b = 0; b < np; ++b) {
-      dpr1_opts c = o;
-      c.split = ws[a];
-      if (o.root == 1) c.main_passes = passes[b];
-      double ms = 0.0;
-      int rc = time_calls([&]() { return dpr1_eig(d, z, rho, n, lambda, V, ldv, shift_idx, mu, xnorm, info,
-                                                  nullptr, &c, work, work_bytes, stream); },
-                          reps, (hipStream_t)stream, &ms);
-      if (rc != 0) return rc;
-      if (ms < best) {
-        best = ms;
-        bw = c.split;
-        bp = c.main_passes;
+    for (int oc : OCC_CAND)
+      for (int b = 0; b < np; ++b) {
+        dpr1_opts c = o;
+        c.split = ws[a];
+        c.waves_per_simd = oc;
+        if (o.root == 1) c.main_passes = passes[b];
+        double ms = 0.0;
+        int rc = time_calls([&]() { return dpr1_eig(d, z, rho, n, lambda, V, ldv, shift_idx, mu, xnorm, info,
+                                                    nullptr, &c, work, work_bytes, stream); },
+                            reps, (hipStream_t)stream, &ms);
+        if (rc != 0) return rc;
+        if (ms < best) {
+          best = ms;
+          bw = c.split;
+          bp = c.main_passes;
+          bo = oc;
+        }
       }
-    }
   opts->split = bw;
   opts->main_passes = bp;
+  opts->waves_per_simd = bo;
   if (best_ms) *best_ms = best;
   return DPR1_OK;
 }
@@ -1867,22 +1891,24 @@ int dpr1_batched_autotune(dpr1_plan* plan, const int64_t* offs, const double* d,
   double best = INFINITY;
   dpr1_plan bestp = base;
   for (int a = 0; a < nw; ++a)
-    for (int b = 0; b < np; ++b) {
-      dpr1_plan c = base;
-      c.split = ws[a];
-      c.grid = persistent_grid_for(c.nitems, ws[a]);
-      c.opts.events = nullptr;
-      if (base.opts.root == 1) c.opts.main_passes = passes[b];
-      double ms = 0.0;
-      int rc = time_calls([&]() { return dpr1_eig_batched(&c, offs, d, z, rho, lambda, V, voffs, shift_idx, mu,
-                                                          xnorm, info, nullptr, work, work_bytes, stream); },
-                          reps, (hipStream_t)stream, &ms);
-      if (rc != 0) return rc;
-      if (ms < best) {
-        best = ms;
-        bestp = c;
+    for (int oc : OCC_CAND)
+      for (int b = 0; b < np; ++b) {
+        dpr1_plan c = base;
+        c.split = ws[a];
+        c.opts.waves_per_simd = oc;
+        c.grid = persistent_grid_for(c.nitems, ws[a], oc);
+        c.opts.events = nullptr;
+        if (base.opts.root == 1) c.opts.main_passes = passes[b];
+        double ms = 0.0;
+        int rc = time_calls([&]() { return dpr1_eig_batched(&c, offs, d, z, rho, lambda, V, voffs, shift_idx, mu,
+                                                            xnorm, info, nullptr, work, work_bytes, stream); },
+                            reps, (hipStream_t)stream, &ms);
+        if (rc != 0) return rc;
+        if (ms < best) {
+          best = ms;
+          bestp = c;
+        }
       }
-    }
   bestp.opts.events = base.opts.events;
   *plan = bestp;
   if (best_ms) *best_ms = best;

@@ -25,7 +25,7 @@ STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "ite
 class Opts(C.Structure):
     _fields_ = [("mode_b", C.c_int32), ("root", C.c_int32), ("polish", C.c_int32),
                 ("split", C.c_int32), ("kappa_polish", C.c_double), ("nearzero", C.c_double),
-                ("main_passes", C.c_int32), ("reserved", C.c_int32), ("events", C.c_void_p)]
+                ("main_passes", C.c_int32), ("waves_per_simd", C.c_int32), ("events", C.c_void_p)]
 
 
 class Plan(C.Structure):
@@ -71,8 +71,8 @@ def lib():
 
 
 def opts(mode_b=0, root=1, polish=1, split=0, kappa_polish=16.0, nearzero=10.0, main_passes=0,
-         events=None) -> Opts:
-    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, main_passes, 0, events)
+         events=None, waves_per_simd=0) -> Opts:
+    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, main_passes, waves_per_simd, events)
 
 
 class HipEvents:

@@ -1,12 +1,12 @@
-"""Persistent cache of autotuned launch shapes (split W and pass budget).
+"""Persistent cache of autotuned launch shapes (split W, register budget, pass budget).
 
 The library's autotuner (dpr1_autotune / dpr1_batched_autotune) times every
 candidate on real data; this module remembers the winner in a JSON file keyed
 by GPU architecture, operation and a size bucket, so that later solves of a
 similar shape reuse it without timing again.  File: $DPR1_TUNING_CACHE, else
 ~/.cache/paper_1405_7537_amd/tuning.json.  Entries hold only integers
-(split, main_passes) and the measured time; a corrupt or unreadable file is
-treated as empty.
+(split, waves_per_simd, main_passes) and the measured time; a corrupt or
+unreadable file is treated as empty.
 """
 from __future__ import annotations
 
@@ -17,7 +17,7 @@ import tempfile
 
 import numpy as np
 
-VERSION = 1
+VERSION = 2
 
 
 def cache_path() -> str:
@@ -58,7 +58,7 @@ def store(key: str, entry: dict, path: str | None = None) -> None:
     path = path or cache_path()
     data = load(path)
     data[key] = {"split": int(entry["split"]), "main_passes": int(entry["main_passes"]),
-                 "ms": float(entry["ms"])}
+                 "waves_per_simd": int(entry.get("waves_per_simd", 0)), "ms": float(entry["ms"])}
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     fd, tmp = tempfile.mkstemp(dir=os.path.dirname(os.path.abspath(path)), suffix=".tmp")
     with os.fdopen(fd, "w") as f:
@@ -72,7 +72,7 @@ def arch_of(device) -> str:
 
 
 def tuned_opts(d, z, rho, vectors=True, opts=None, reps=3, device="cuda", path=None):
-    """Options for a single problem with the cached (or freshly tuned) split and pass budget.
+    """Options for a single problem with the cached (or freshly tuned) split, register and pass budgets.
     Returns (opts, entry, from_cache)."""
     from . import dpr1 as D
     o = D.opts() if opts is None else opts
@@ -82,15 +82,16 @@ def tuned_opts(d, z, rho, vectors=True, opts=None, reps=3, device="cuda", path=N
     if hit is not None:
         o.split = int(hit["split"])
         o.main_passes = int(hit["main_passes"])
+        o.waves_per_simd = int(hit.get("waves_per_simd", 0))
         return o, hit, True
     o, ms = D.autotune(d, z, rho, vectors=vectors, opts=o, reps=reps, device=device)
-    entry = {"split": o.split, "main_passes": o.main_passes, "ms": ms}
+    entry = {"split": o.split, "main_passes": o.main_passes, "waves_per_simd": o.waves_per_simd, "ms": ms}
     store(key, entry, path)
     return o, entry, False
 
 
 def tuned_batch(offs, d, z, rho, vectors=True, opts=None, reps=3, device="cuda", path=None):
-    """A Batch whose plan carries the cached (or freshly tuned) split and pass budget.
+    """A Batch whose plan carries the cached (or freshly tuned) split, register and pass budgets.
     d, z, rho: device tensors of the batch (used only when tuning).  Returns (batch, entry, from_cache)."""
     from . import dpr1 as D
     o = D.opts() if opts is None else opts
@@ -100,9 +101,11 @@ def tuned_batch(offs, d, z, rho, vectors=True, opts=None, reps=3, device="cuda",
     if hit is not None:
         o.split = int(hit["split"])
         o.main_passes = int(hit["main_passes"])
+        o.waves_per_simd = int(hit.get("waves_per_simd", 0))
         return D.Batch(offs, opts=o, vectors=vectors, device=device), hit, True
     b = D.Batch(offs, opts=o, vectors=vectors, device=device)
     ms = b.autotune(d, z, rho, reps=reps)
-    entry = {"split": b.plan.split, "main_passes": b.plan.opts.main_passes, "ms": ms}
+    entry = {"split": b.plan.split, "main_passes": b.plan.opts.main_passes,
+             "waves_per_simd": b.plan.opts.waves_per_simd, "ms": ms}
     store(key, entry, path)
     return b, entry, False

@@ -24,8 +24,10 @@ def test_autotune_single_problem(D, orc):
     d, z, rho = W.uniform(3000, 21)
     print("[tuning] single n=3000", flush=True)
     o, ms = D.autotune(d, z, rho, reps=2)
-    print(f"[tuning] split {o.split} main_passes {o.main_passes} {ms:.3f} ms", flush=True)
-    assert o.split in (1, 2, 4, 8, 16) and o.main_passes in (2, 3) and ms > 0
+    print(f"[tuning] split {o.split} waves/SIMD {o.waves_per_simd} main_passes {o.main_passes} {ms:.3f} ms",
+          flush=True)
+    assert o.split in (1, 2, 4, 8, 12, 16) and o.waves_per_simd in (4, 6, 8) and o.main_passes in (2, 3)
+    assert ms > 0
     r = D.eig(d, z, rho, opts=o)
     lo, Vo = orc.eig(d, z, rho)
     assert np.max(np.abs(r.lam.cpu().numpy() - lo) / np.abs(lo)) <= LAM_TOL
@@ -45,7 +47,8 @@ def test_autotune_batched_and_cache(D, orc, tmp_path):
     b, entry, hit = T.tuned_batch(offs, d, z, rho, reps=2, path=path)
     print(f"[tuning] batched entry {entry} from cache {hit}", flush=True)
     assert not hit
-    assert b.plan.split in (1, 2, 4, 8, 16) and b.plan.opts.main_passes in (2, 3, 4)
+    assert b.plan.split in (1, 2, 4, 8, 12, 16) and b.plan.opts.main_passes in (2, 3, 4)
+    assert b.plan.opts.waves_per_simd in (4, 6, 8)
     b.solve(d, z, rho)
     b.check()
     for p in (0, 1, 150, 299):
@@ -57,7 +60,7 @@ def test_autotune_batched_and_cache(D, orc, tmp_path):
     V1 = b.V.clone()
     # the cache gives the same plan, hence bit-identical results
     b2, entry2, hit2 = T.tuned_batch(offs, d, z, rho, path=path)
-    assert hit2 and entry2["split"] == entry["split"] and entry2["main_passes"] == entry["main_passes"]
+    assert hit2 and entry2 == entry
     assert b2.plan.split == b.plan.split and b2.plan.grid == b.plan.grid
     b2.solve(d, z, rho)
     b2.check()
