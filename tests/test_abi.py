@@ -66,3 +66,24 @@ def test_argument_errors_need_no_gpu(lib):
     assert lib.dpr1_eig(fake, fake, 1.0, 0, fake, None, 4, None, None, None, fake, None, None, fake, 1 << 20, None) == -4
     assert lib.dpr1_eig(fake, fake, 1.0, 8, fake, fake, 4, None, None, None, fake, None, None, fake, 1 << 20, None) == -7
     assert lib.dpr1_eig(fake, fake, 1.0, 8, fake, None, 8, None, None, None, fake, None, None, fake, 16, None) == -15
+
+
+def test_invalid_register_budget_is_rejected_before_launch(lib):
+    """opts.waves_per_simd other than 0, 4, 6, 8 is argument 13 (dpr1_eig) / 3 (dpr1_batched_plan)."""
+    from paper_1405_7537_amd.dpr1 import Opts, Plan
+    vp = ctypes.c_void_p
+    lib.dpr1_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.dpr1_eig.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64, vp, vp, vp,
+                             vp, vp, ctypes.POINTER(Opts), vp, ctypes.c_size_t, vp]
+    o = Opts()
+    lib.dpr1_default_opts(ctypes.byref(o))
+    assert o.waves_per_simd == 0
+    o.waves_per_simd = 5
+    fake = vp(0x1000)
+    assert lib.dpr1_eig(fake, fake, 1.0, 8, fake, None, 8, None, None, None, fake, None, ctypes.byref(o),
+                        fake, 1 << 20, None) == -13
+    lib.dpr1_batched_plan.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Opts),
+                                      ctypes.POINTER(Plan), vp, ctypes.c_size_t, vp]
+    offs = (ctypes.c_int64 * 3)(0, 5, 9)
+    plan = Plan()
+    assert lib.dpr1_batched_plan(2, offs, ctypes.byref(o), ctypes.byref(plan), fake, 1 << 24, None) == -3
