@@ -68,6 +68,9 @@ extern "C" {
 #define DPR1_STAT_ITERS_SUM 5 /* root-finder passes summed over eigenvalues */
 #define DPR1_STAT_CONTINUED 6 /* root searches finished by the cooperative
                                  kernel after the pass budget               */
+#define DPR1_STAT_POLISH_STEPS_MAX 7 /* most double-double steps one polish
+                                 took (including the one that confirmed the
+                                 root)                                      */
 #define DPR1_NSTATS 8
 
 /* Options.  dpr1_default_opts fills the defaults noted below.               */

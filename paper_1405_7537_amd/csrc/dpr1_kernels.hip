@@ -85,6 +85,7 @@ struct KArgs {
   int32_t* stats;       // nullable
   const int2* items;    // batched queue (p, k0) or nullptr
   int32_t nitems;
+  int32_t nfixcap;  // capacity of `fix` (one slot per eigenvalue)
   int32_t W;
   int32_t mode_b, root, polish;
   int32_t main_passes;
@@ -811,7 +812,11 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     A.xs[off + k] = sqrt(Nx[0]);
     A.lam[off + k] = lam;
     if (pol || nz || cont) {
-      int e = atomicAdd(&A.ctr[0], 1);
+      // the long items (polish, near-zero recomputation) fill the list from
+      // the front, roots only continued fill it from the back, so that the
+      // queue of k_fix hands out the long ones first
+      const bool longer = pol || nz;
+      int e = longer ? atomicAdd(&A.ctr[0], 1) : A.nfixcap - 1 - atomicAdd(&A.ctr[3], 1);
       FixItem it;
       it.p = p;
       it.k = k;
@@ -968,20 +973,28 @@ __device__ __forceinline__ double block_sum_comp(double s, double c, double* sm)
 
 // One block of FIXT threads per flagged eigenpair at a time; the inner index
 // is strided over the block and every pass ends in a block-wide sum.
+// Item e of the list: the n0 long items sit at the front, the others at the
+// back in reverse order.
+__device__ __forceinline__ int fix_slot(const KArgs& A, int n0, int e) {
+  return e < n0 ? e : A.nfixcap - 1 - (e - n0);
+}
+
 __device__ void fix_items(const KArgs& A) {
   __shared__ double sm[8];
   __shared__ int next;
   const int tid = threadIdx.x;
-  const int cnt = A.ctr[0];
+  const int n0 = A.ctr[0];
+  const int cnt = n0 + A.ctr[3];
   for (;;) {
-    // items are taken from a queue, so a block that drew cheap items takes
-    // more of them (polish steps cost several times a continued root's)
+    // items are taken from a queue, long ones first, so a block that drew
+    // cheap items takes more of them (polish steps cost several times a
+    // continued root's)
     if (tid == 0) next = atomicAdd(&A.ctr[2], 1);
     __syncthreads();
     const int e = next;
     __syncthreads();
     if (e >= cnt) break;
-    const FixItem it = A.fix[e];
+    const FixItem it = A.fix[fix_slot(A, n0, e)];
     const Meta M = A.meta[it.p];
     const int n = M.n;
     const int64_t off = M.off;
@@ -1003,6 +1016,7 @@ __device__ void fix_items(const KArgs& A) {
     bool pol = (it.flags & FIX_POLISH) != 0;
     bool polished = false;
     int singular = 0;
+    int pit = 0;  // double-double steps of the polish
     double nu0 = it.nu0, nu1 = it.nu1;
     double xsv = 0.0;
     bool have_xs = false;
@@ -1086,7 +1100,7 @@ __device__ void fix_items(const KArgs& A) {
       double cur = nu1;
       if (!(cur > lo && cur < hi)) cur = nu0;
       if (!(cur > lo && cur < hi)) cur = fmid(lo, hi);
-      for (int pit = 0; pit < 48; ++pit) {
+      for (pit = 0; pit < 48; ++pit) {
         dd acc = {0.0, 0.0};
         double sp = 0.0;
         #pragma unroll 4
@@ -1099,7 +1113,7 @@ __device__ void fix_items(const KArgs& A) {
           dd q = dd_mul(dl, pp);
           dd t = dd_div(dd{z2, Zl[j]}, q);
           acc = dd_add_same(acc, t);
-          sp += z2 / (pp.hi * pp.hi);
+          sp += z2 * rcp_1nr(pp.hi * pp.hi);  // g' only steers the step
         }
         acc = block_sum_same(acc, sm);
         sp = block_sum(sp, sm);
@@ -1222,7 +1236,10 @@ __device__ void fix_items(const KArgs& A) {
         A.xs[off + k] = xsv;
       }
       if (A.stats) {
-        if (polished) atomicAdd(&A.stats[DPR1_STAT_POLISHED], 1);
+        if (polished) {
+          atomicAdd(&A.stats[DPR1_STAT_POLISHED], 1);
+          atomicMax(&A.stats[DPR1_STAT_POLISH_STEPS_MAX], min(pit + 1, 48));
+        }
         if (it.flags & FIX_CONTINUE) atomicAdd(&A.stats[DPR1_STAT_CONTINUED], 1);
         if (nz) atomicAdd(&A.stats[DPR1_STAT_NEARZERO], 1);
         if (singular) atomicAdd(&A.stats[DPR1_STAT_SINGULAR], 1);
@@ -1445,9 +1462,10 @@ __global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ la
                                                 int32_t* __restrict__ idx_out, double* __restrict__ mu_out,
                                                 double* __restrict__ xn_out, double* __restrict__ V,
                                                 const int64_t* __restrict__ voffs, int64_t ldv) {
-  const int cnt = A.ctr[0];
+  const int n0 = A.ctr[0];
+  const int cnt = n0 + A.ctr[3];
   for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
-    const FixItem it = A.fix[e];
+    const FixItem it = A.fix[fix_slot(A, n0, e)];
     const Meta M = A.meta[it.p];
     const int n = M.n, k = it.k;
     const int64_t a = M.off + k;
@@ -1645,6 +1663,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   A.stats = stats;
   A.items = persistent_grid ? (const int2*)(w + L.items) : nullptr;
   A.nitems = (int32_t)nitems;
+  A.nfixcap = (int32_t)N;
   A.W = W;
   A.mode_b = o.mode_b;
   A.root = o.root;

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libdpr1.so")
 INFO_TEXT = {0: "ok", 1: "d is not strictly decreasing", 2: "some z_j is zero (reducible)",
              3: "non-finite input", 4: "rho is zero or not finite"}
 NSTATS = 8
-STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "iters_sum", "continued", "r7"]
+STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "iters_sum", "continued",
+              "polish_steps_max"]
 
 
 class Opts(C.Structure):
