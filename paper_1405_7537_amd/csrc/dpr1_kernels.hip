@@ -1111,7 +1111,13 @@ __device__ void fix_items(const KArgs& A) {
           dd dl = two_sum(s * dj, -s * sigma);                   // delta'_j exactly
           dd pp = dd_add(dd_mul_d(dl, cur), dd{-1.0, 0.0});       // nu delta' - 1
           dd q = dd_mul(dl, pp);
-          dd t = dd_div(dd{z2, Zl[j]}, q);
+          // (zeta_j^2 hi + lo)/q: leading quotient from the refined
+          // reciprocal (2^-48.7) and one residual correction, about 2^-97
+          const double r = rcp_1nr(q.hi);
+          const double q1 = z2 * r;
+          double e = __builtin_fma(-q1, q.hi, z2);
+          e = __builtin_fma(-q1, q.lo, e + Zl[j]);
+          dd t = fast_two_sum(q1, e * r);
           acc = dd_add_same(acc, t);
           sp += z2 * rcp_1nr(pp.hi * pp.hi);  // g' only steers the step
         }

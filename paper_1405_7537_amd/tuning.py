@@ -53,9 +53,17 @@ def load(path: str | None = None) -> dict:
         return {}
 
 
-def store(key: str, entry: dict, path: str | None = None) -> None:
-    """Add one entry and rewrite the file atomically (write to a temporary file, then rename)."""
-    path = path or cache_path()
+def store(key: str, entry: dict, path: str | None = None) -> bool:
+    """Add one entry and rewrite the file atomically (write to a temporary file, then rename).
+    Returns False, keeping nothing, when the file cannot be written (the tuned choice is still used)."""
+    try:
+        _store(key, entry, path or cache_path())
+        return True
+    except OSError:
+        return False
+
+
+def _store(key: str, entry: dict, path: str) -> None:
     data = load(path)
     data[key] = {"split": int(entry["split"]), "main_passes": int(entry["main_passes"]),
                  "waves_per_simd": int(entry.get("waves_per_simd", 0)), "ms": float(entry["ms"])}

@@ -47,3 +47,11 @@ def test_corrupt_cache_reads_as_empty(tmp_path):
 def test_cache_path_honours_environment(monkeypatch, tmp_path):
     monkeypatch.setenv("DPR1_TUNING_CACHE", str(tmp_path / "x.json"))
     assert T.cache_path() == str(tmp_path / "x.json")
+
+
+def test_unwritable_cache_is_not_fatal(tmp_path):
+    blocker = tmp_path / "file"
+    blocker.write_text("x")
+    p = str(blocker / "sub" / "tuning.json")      # a directory below a regular file cannot be made
+    assert T.store("k", {"split": 8, "main_passes": 2, "ms": 1.0}, p) is False
+    assert T.load(p) == {}
