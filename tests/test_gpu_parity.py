@@ -203,3 +203,13 @@ def test_config_n32768_sampled(D, orc):
     assert worst_norm <= 1e-13
     # the residual's own rounding: the length-n product z^T v alone may round by n*u*||z||*||v||
     assert worst_res <= 1e-12
+
+
+@pytest.mark.parametrize("split,wps,mp", [(1, 0, 0), (3, 6, 2), (5, 8, 3), (16, 8, 2), (12, 4, 4), (8, 6, 1)])
+def test_launch_shapes_keep_parity(D, orc, split, wps, mp):
+    """Every split W (waves per 64-eigenvalue block, powers of two or not), register budget and
+    pass budget (1: every root continues in k_fix) gives the oracle's eigenpairs."""
+    r, *_ = compare(D, orc, *W.uniform(1000, 7), opts=D.opts(split=split, waves_per_simd=wps, main_passes=mp),
+                    tag=f"W{split}/occ{wps}/mp{mp}")
+    if mp == 1:
+        assert r.stats_dict()["continued"] > 500
