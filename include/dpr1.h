@@ -209,6 +209,12 @@ int dpr1_batched_autotune(dpr1_plan* plan, const int64_t* offs, const double* d,
  * FP64 matrix cores.  Problems of one batch have equal size n and are stored
  * with strides n (vectors) and n*n (matrices, column-major, ld = n).
  *   shift_idx, mu, xnorm: as returned by the forward call.
+ *   V: the forward's eigenvectors, or NULL: then every element the two
+ *     products need is recomputed from z and the shifted representation,
+ *     v_k[j] = z_j / (((d_j - d_{i_k}) - mu_k) ||x_k||) (eq. eigenvecAi),
+ *     inside the GEMM tile loads, so that V need not be kept (or even
+ *     written: a forward without eigenvectors suffices).  z may be NULL only
+ *     when V is given (-4 otherwise).
  *   lambda_bar, V_bar: either may be NULL (treated as zero).
  *   d_bar, z_bar [nbatch*n], rho_bar [nbatch]: outputs.                    */
 size_t dpr1_backward_workspace_size(int64_t n, int64_t nbatch);

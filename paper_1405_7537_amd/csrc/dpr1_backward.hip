@@ -50,7 +50,9 @@ enum { EPI_X = 0, EPI_D = 1 };
 struct GArgs {
   int64_t n;
   int nb;
-  const double* A;   // V (both GEMMs)
+  const double* A;   // V (both GEMMs), or null: V recomputed from (z, shift, mu, ||x||)
+  const double* z;      // [nb*n]  (used when A is null)
+  const double* xnorm;  // [nb*n]  (used when A is null)
   const double* B;   // V_bar (EPI_X, column-major) or X (EPI_D, row-major)
   double* C;         // X (EPI_X), stored row-major
   // EPI_X
@@ -68,6 +70,18 @@ struct GArgs {
   int has_B;              // 0: V_bar is null, P = 0
 };
 
+// Element (j, k) of V for problem offset vo, recomputed from the forward's
+// shifted representation in the arithmetic of the eigenvector writer:
+// v_k[j] = z_j / (((d_j - d_{i_k}) - mu_k) ||x_k||) (eq. eigenvecAi), so a
+// caller short of memory need not keep V between the forward and the
+// backward.  Shift indices are clamped to the problem.
+__device__ __forceinline__ double v_elem(const GArgs& g, int64_t vo, int64_t j, int64_t k) {
+  const int64_t n = g.n;
+  const int64_t ik = (int64_t)min(max(g.sidx[vo + k], 0), (int)(n - 1));
+  const double den = (g.d[vo + j] - g.d[vo + ik]) - g.mu[vo + k];
+  return (g.z[vo + j] / den) / g.xnorm[vo + k];
+}
+
 // Column-major n x n matrices (ld = n).  EPI_X computes op(A) = A^T (A = V),
 // EPI_D op(A) = A.  The linear block index is mapped so that all tiles of a
 // problem run on one XCD and share its L2.
@@ -83,7 +97,8 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   if (pb >= g.nb) return;
   const int tm = t % tiles, tn = t / tiles;
   const int64_t mo = (int64_t)pb * n * n;
-  const double* A = g.A + mo;
+  const int64_t vo = (int64_t)pb * n;
+  const double* A = g.A ? g.A + mo : nullptr;  // null: elements from v_elem
   const double* Bm = g.B + mo;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
@@ -116,12 +131,12 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
         kk = e % BK;   // A^T(m, k) = V[k + m n], contiguous along k
         m = e / BK;
         int64_t gm = m0 + m, gk = k0 + kk;
-        ra[e2] = (gm < n && gk < n) ? A[gk + gm * n] : 0.0;
+        ra[e2] = (gm < n && gk < n) ? (A ? A[gk + gm * n] : v_elem(g, vo, gk, gm)) : 0.0;
       } else {
         m = e % BM;    // A(m, k) = V[m + k n], contiguous along m
         kk = e / BM;
         int64_t gm = m0 + m, gk = k0 + kk;
-        ra[e2] = (gm < n && gk < n) ? A[gm + gk * n] : 0.0;
+        ra[e2] = (gm < n && gk < n) ? (A ? A[gm + gk * n] : v_elem(g, vo, gm, gk)) : 0.0;
       }
       if (EPI == EPI_X) {
         int kb = e % BK, c = e / BK;  // V_bar(k, c) = V_bar[k + c n], contiguous along k
@@ -196,7 +211,6 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   double* clb = cy + BN;
   double(*rowp)[WNW][BM] = reinterpret_cast<double(*)[WNW][BM]>(clb + BN);  // [quantity][wave along n][row]
   double(*colp)[BN] = reinterpret_cast<double(*)[BN]>(clb + BN + 2 * WNW * BM);  // [wave along m][col]
-  const int64_t vo = (int64_t)pb * n;
   // shift indices come from the caller: clamped so that a bad one cannot
   // address outside the problem
   auto sidx = [&](int64_t k) { return (int64_t)min(max(g.sidx[vo + k], 0), (int)(n - 1)); };
@@ -256,7 +270,7 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
           cs[b] += x * ry[rl];
         } else {
           // Q(row = j, col = k) V(j, k) for d_bar, V(j, k) u_k for z_bar
-          double vjk = A[row + col * n];
+          double vjk = A ? A[row + col * n] : v_elem(g, vo, row, col);
           rs1[q] += v * vjk;
           rs2[q] += vjk * cy[cl];
         }
@@ -404,12 +418,11 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
   if (nbatch < 1 || nbatch > 65535) return -1;
   if (n < 1 || n > (1 << 20)) return -2;
   if (!d) return -3;
-  (void)z;
+  if (!z && !V) return -4;
   if (!rho) return -5;
   if (!shift_idx) return -6;
   if (!mu) return -7;
   if (!xnorm) return -8;
-  if (!V) return -9;
   if (!d_bar) return -12;
   if (!z_bar) return -13;
   if (!rho_bar) return -14;
@@ -434,6 +447,8 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
   g.n = n;
   g.nb = (int)nbatch;
   g.A = V;
+  g.z = z;
+  g.xnorm = xnorm;
   g.B = V_bar;
   g.C = X;
   g.lam_bar = lambda_bar;

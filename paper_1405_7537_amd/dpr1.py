@@ -299,7 +299,8 @@ def backward_batched(d, z, rho, shift_idx, mu, xnorm, V, lam_bar=None, V_bar=Non
     """Reverse mode for nb problems of equal size n.
 
     d, z, shift_idx, mu, xnorm, lam_bar: [nb, n]; rho: [nb]; V, V_bar: column-major storage of
-    [nb] n x n matrices (tensors whose memory is V[b] with element (j, k) at j + k n).
+    [nb] n x n matrices (tensors whose memory is V[b] with element (j, k) at j + k n).  V may be
+    None: the kernels then recompute its elements from z and (shift_idx, mu, xnorm).
     Returns (d_bar [nb, n], z_bar [nb, n], rho_bar [nb])."""
     nb, n = d.shape
     dev = d.device
@@ -343,6 +344,29 @@ class DPR1Eig(torch.autograd.Function):
         Vb = V_bar.t().contiguous() if V_bar is not None else None
         db, zb, rb = backward_batched(d.view(1, n), z.view(1, n), rho, idx.view(1, n), mu.view(1, n),
                                       xn.view(1, n), Vs, lb, Vb)
+        return db.view(n), zb.view(n), rb.view(())
+
+
+class DPR1EigValues(torch.autograd.Function):
+    """lam = eigenvalues of D + rho z z^T, differentiable without ever storing V.
+
+    Forward: dpr1_eig without eigenvectors.  Backward: dpr1_eig_backward_batched with V = NULL,
+    whose GEMM tile loads recompute v_k[j] from the saved (shift_idx, mu, ||x||)."""
+
+    @staticmethod
+    def forward(ctx, d, z, rho):
+        rho_t = rho if torch.is_tensor(rho) else torch.tensor(float(rho), dtype=torch.float64, device=d.device)
+        r = eig(d.detach(), z.detach(), float(rho_t), vectors=False)
+        ctx.save_for_backward(d.detach(), z.detach(), rho_t.detach().reshape(1).to(d.device), r.shift_idx, r.mu,
+                              r.xnorm)
+        return r.lam
+
+    @staticmethod
+    def backward(ctx, lam_bar):
+        d, z, rho, idx, mu, xn = ctx.saved_tensors
+        n = d.numel()
+        db, zb, rb = backward_batched(d.contiguous().view(1, n), z.contiguous().view(1, n), rho, idx.view(1, n),
+                                      mu.view(1, n), xn.view(1, n), None, lam_bar.contiguous().view(1, n), None)
         return db.view(n), zb.view(n), rb.view(())
 
 

@@ -341,9 +341,13 @@ def test_backward_eigenvalue_part_closed_form(orc):
     np.testing.assert_allclose(zb, -2 * V @ (lb / xn), rtol=1e-11, atol=1e-13)
 
 
-def test_backward_finite_differences(orc):
-    """Central differences (h = 1e-6) of L = sum w*lambda + sum W o V on an n = 16 problem."""
-    d, z, rho = W.uniform(16, 5)
+@pytest.mark.parametrize("rho", [None, -0.6])
+def test_backward_finite_differences(orc, rho):
+    """Central differences (h = 1e-6) of L = sum w*lambda + sum W o V on an n = 16 problem, also
+    with rho < 0 (the diagnostics then describe the reduced problem: negated sigma and mu)."""
+    d, z, r0 = W.uniform(16, 5)
+    rho = r0 if rho is None else rho
+    sg = 1.0 if rho > 0 else -1.0
     rng = np.random.default_rng(5)
     w = rng.standard_normal(16)
     Wm = rng.standard_normal((16, 16))
@@ -353,7 +357,7 @@ def test_backward_finite_differences(orc):
         return float(np.dot(w, lam) + np.sum(Wm * V))
 
     lam, V, dg = orc.eig(d, z, rho, diags=True)
-    db, zb, rb = orc.backward(d, z, rho, [x["sigma"] for x in dg], [x["mu"] for x in dg],
+    db, zb, rb = orc.backward(d, z, rho, [sg * x["sigma"] for x in dg], [sg * x["mu"] for x in dg],
                               V, lam_bar=w, V_bar=Wm)
     h = 1e-6
     fd_d = np.array([(loss(d + h * e, z, rho) - loss(d - h * e, z, rho)) / (2 * h) for e in np.eye(16)])
