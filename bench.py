@@ -326,7 +326,8 @@ def bench_batched(D, W, torch, dev, args):
 
 def bench_fwd_bwd(D, W, torch, dev, args):
     r = D.bench_fwd_bwd(torch, dev, args.steps)
-    log(f"[bench] fwd+bwd 256 x n=512: {r['ms_per_step']:.3f} ms (forward {r['forward_ms']:.3f} ms)")
+    log(f"[bench] fwd+bwd 256 x n=512: {r['ms_per_step']:.3f} ms (forward {r['forward_ms']:.3f} ms); "
+        f"V not stored: {r['v_not_stored']['ms_per_step']:.3f} ms")
     return r
 
 

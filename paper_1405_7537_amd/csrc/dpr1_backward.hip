@@ -52,7 +52,8 @@ struct GArgs {
   int nb;
   const double* A;   // V (both GEMMs), or null: V recomputed from (z, shift, mu, ||x||)
   const double* z;      // [nb*n]  (used when A is null)
-  const double* xnorm;  // [nb*n]  (used when A is null)
+  const double* sig;    // [nb*n]  d_{i_k}, the shift of eigenvalue k (used when A is null)
+  const double* ixn;    // [nb*n]  1/||x_k|| (used when A is null)
   const double* B;   // V_bar (EPI_X, column-major) or X (EPI_D, row-major)
   double* C;         // X (EPI_X), stored row-major
   // EPI_X
@@ -71,15 +72,19 @@ struct GArgs {
 };
 
 // Element (j, k) of V for problem offset vo, recomputed from the forward's
-// shifted representation in the arithmetic of the eigenvector writer:
-// v_k[j] = z_j / (((d_j - d_{i_k}) - mu_k) ||x_k||) (eq. eigenvecAi), so a
-// caller short of memory need not keep V between the forward and the
-// backward.  Shift indices are clamped to the problem.
+// shifted representation: v_k[j] = z_j / (((d_j - d_{i_k}) - mu_k) ||x_k||)
+// (eq. eigenvecAi), so that a caller short of memory need not keep V between
+// the forward and the backward.  d_{i_k} and 1/||x_k|| come precomputed
+// (k_bwd_y); the quotient is the refined reciprocal with one residual
+// correction, as in the forward's eigenvector writer.
 __device__ __forceinline__ double v_elem(const GArgs& g, int64_t vo, int64_t j, int64_t k) {
-  const int64_t n = g.n;
-  const int64_t ik = (int64_t)min(max(g.sidx[vo + k], 0), (int)(n - 1));
-  const double den = (g.d[vo + j] - g.d[vo + ik]) - g.mu[vo + k];
-  return (g.z[vo + j] / den) / g.xnorm[vo + k];
+  const double den = (g.d[vo + j] - g.sig[vo + k]) - g.mu[vo + k];
+  const double zj = g.z[vo + j];
+  double r = __builtin_amdgcn_rcp(den);
+  r = __builtin_fma(r, __builtin_fma(-den, r, 1.0), r);
+  double q = zj * r;
+  q = __builtin_fma(__builtin_fma(-q, den, zj), r, q);
+  return q * g.ixn[vo + k];
 }
 
 // Column-major n x n matrices (ld = n).  EPI_X computes op(A) = A^T (A = V),
@@ -326,13 +331,21 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   }
 }
 
-// y_k = v_k^T z = -1/(rho ||x_k||)
+// y_k = v_k^T z = -1/(rho ||x_k||); for the products without a stored V also
+// the shift d_{i_k} (index clamped to the problem) and 1/||x_k||
 __global__ void __launch_bounds__(256) k_bwd_y(int64_t n, int64_t nb, const double* __restrict__ rho,
-                                               const double* __restrict__ xnorm, double* __restrict__ y) {
+                                               const double* __restrict__ xnorm, const double* __restrict__ d,
+                                               const int32_t* __restrict__ sidx, double* __restrict__ y,
+                                               double* __restrict__ sig, double* __restrict__ ixn) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * nb) return;
   int64_t p = t / n;
   y[t] = -1.0 / (rho[p] * xnorm[t]);
+  if (sig) {
+    const int64_t ik = (int64_t)min(max(sidx[t], 0), (int)(n - 1));
+    sig[t] = d[p * n + ik];
+    ixn[t] = 1.0 / xnorm[t];
+  }
 }
 
 // u = X y + X^T y and rho_bar = y^T X y from the partials of the first GEMM
@@ -381,7 +394,7 @@ __global__ void __launch_bounds__(256) k_bwd_final(int64_t n, int64_t nb, int nt
 }
 
 struct BLayout {
-  size_t X, y, u, pr, pc, pd, pz, total;
+  size_t X, y, u, pr, pc, pd, pz, sig, ixn, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 static BLayout blayout(int64_t n, int64_t nb) {
@@ -395,6 +408,8 @@ static BLayout blayout(int64_t n, int64_t nb) {
   L.pc = o; o = al(o + sizeof(double) * n * nt * nb);
   L.pd = o; o = al(o + sizeof(double) * n * nt * nb);
   L.pz = o; o = al(o + sizeof(double) * n * nt * nb);
+  L.sig = o; o = al(o + sizeof(double) * n * nb);
+  L.ixn = o; o = al(o + sizeof(double) * n * nb);
   L.total = o;
   return L;
 }
@@ -442,13 +457,17 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
   const int64_t nbpad = (nbatch + NXCD - 1) / NXCD * NXCD;
   const unsigned ggrid = (unsigned)(nbpad * tiles * tiles);
 
-  hipLaunchKernelGGL(k_bwd_y, dim3((unsigned)((n * nbatch + 255) / 256)), dim3(256), 0, st, n, nbatch, rho, xnorm, y);
+  double* sig = V ? nullptr : (double*)(w + L.sig);
+  double* ixn = V ? nullptr : (double*)(w + L.ixn);
+  hipLaunchKernelGGL(k_bwd_y, dim3((unsigned)((n * nbatch + 255) / 256)), dim3(256), 0, st, n, nbatch, rho, xnorm, d,
+                     shift_idx, y, sig, ixn);
   GArgs g;
   g.n = n;
   g.nb = (int)nbatch;
   g.A = V;
   g.z = z;
-  g.xnorm = xnorm;
+  g.sig = sig;
+  g.ixn = ixn;
   g.B = V_bar;
   g.C = X;
   g.lam_bar = lambda_bar;
