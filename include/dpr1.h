@@ -206,7 +206,10 @@ int dpr1_batched_autotune(dpr1_plan* plan, const int64_t* offs, const double* d,
  *   d_bar_j = Abar_jj, rho_bar = z^T Abar z, z_bar = rho (Abar + Abar^T) z,
  * evaluated as d_bar_j = sum_k (V X)_jk V_jk, y_k = v_k^T z = -1/(rho ||x_k||),
  * rho_bar = y^T X y, z_bar = rho V (X + X^T) y.  The two n^3 products use
- * FP64 matrix cores.  Problems of one batch have equal size n and are stored
+ * FP64 matrix cores.  Without V_bar only the eigenvalue part remains and is
+ * evaluated in closed form in O(n^2): d_bar_j = sum_k lambda_bar_k V_jk^2,
+ * z_bar_j = -2 sum_k lambda_bar_k V_jk / ||x_k||,
+ * rho_bar = sum_k lambda_bar_k / (rho ||x_k||)^2.  Problems of one batch have equal size n and are stored
  * with strides n (vectors) and n*n (matrices, column-major, ld = n).
  *   shift_idx, mu, xnorm: as returned by the forward call.
  *   V: the forward's eigenvectors, or NULL: then every element the two

@@ -393,6 +393,48 @@ __global__ void __launch_bounds__(256) k_bwd_final(int64_t n, int64_t nb, int nt
   z_bar[t] = rho[pb] * sz;
 }
 
+// Without V_bar only the eigenvalue part remains, in closed form (O(n^2) per
+// problem instead of two n^3 products): d_bar_j = sum_k lam_bar_k v_jk^2,
+// z_bar_j = -2 sum_k lam_bar_k v_jk / ||x_k|| (from v_k^T z = -1/(rho ||x_k||)),
+// rho_bar = sum_k lam_bar_k / (rho ||x_k||)^2.  Grid (row blocks, problems);
+// the first row block of a problem also forms rho_bar.
+__global__ void __launch_bounds__(256) k_bwd_eigonly(GArgs g, const double* __restrict__ lam_bar,
+                                                     const double* __restrict__ xnorm,
+                                                     const double* __restrict__ rho, double* __restrict__ d_bar,
+                                                     double* __restrict__ z_bar, double* __restrict__ rho_bar) {
+  const int64_t n = g.n;
+  const int64_t p = blockIdx.y;
+  const int64_t vo = p * n, mo = p * n * n;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+      const double lb = lam_bar ? lam_bar[vo + k] : 0.0;
+      const double yk = 1.0 / (rho[p] * xnorm[vo + k]);
+      acc += lb * (yk * yk);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) rho_bar[p] = red[0];
+  }
+  if (j >= n) return;
+  double sd = 0.0, sz = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double lb = lam_bar ? lam_bar[vo + k] : 0.0;
+    const double v = g.A ? g.A[mo + j + k * n] : v_elem(g, vo, j, k);
+    const double t = lb * v;
+    sd = __builtin_fma(t, v, sd);
+    sz += t / xnorm[vo + k];
+  }
+  d_bar[vo + j] = sd;
+  z_bar[vo + j] = -2.0 * sz;
+}
+
 struct BLayout {
   size_t X, y, u, pr, pc, pd, pz, sig, ixn, total;
 };
@@ -481,6 +523,12 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
   g.part_d = pd;
   g.part_z = pz;
   g.has_B = V_bar != nullptr;
+  if (!V_bar) {
+    hipLaunchKernelGGL(k_bwd_eigonly, dim3((unsigned)((n + 255) / 256), (unsigned)nbatch), dim3(256), 0, st, g,
+                       lambda_bar, xnorm, rho, d_bar, z_bar, rho_bar);
+    if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
+    return DPR1_OK;
+  }
   hipLaunchKernelGGL(k_gemm<EPI_X>, dim3(ggrid), dim3(NT), 0, st, g);
   if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
   hipLaunchKernelGGL(k_bwd_u, dim3((unsigned)nbatch), dim3(256), 0, st, n, tiles, pr, pc, y, u, rho_bar);
