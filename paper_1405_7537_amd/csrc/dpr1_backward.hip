@@ -90,7 +90,9 @@ __device__ __forceinline__ double v_elem(const GArgs& g, int64_t vo, int64_t j, 
 // Column-major n x n matrices (ld = n).  EPI_X computes op(A) = A^T (A = V),
 // EPI_D op(A) = A.  The linear block index is mapped so that all tiles of a
 // problem run on one XCD and share its L2.
-template <int EPI>
+// RV: V is not passed in; its elements are rebuilt by v_elem (a separate
+// instance, so that the path with V keeps its plain loads).
+template <int EPI, bool RV>
 __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   const int64_t n = g.n;
   const int tiles = (int)((n + BM - 1) / BM);
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   const int tm = t % tiles, tn = t / tiles;
   const int64_t mo = (int64_t)pb * n * n;
   const int64_t vo = (int64_t)pb * n;
-  const double* A = g.A ? g.A + mo : nullptr;  // null: elements from v_elem
+  const double* A = RV ? nullptr : g.A + mo;
   const double* Bm = g.B + mo;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
@@ -136,12 +138,12 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
         kk = e % BK;   // A^T(m, k) = V[k + m n], contiguous along k
         m = e / BK;
         int64_t gm = m0 + m, gk = k0 + kk;
-        ra[e2] = (gm < n && gk < n) ? (A ? A[gk + gm * n] : v_elem(g, vo, gk, gm)) : 0.0;
+        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gk, gm) : A[gk + gm * n]) : 0.0;
       } else {
         m = e % BM;    // A(m, k) = V[m + k n], contiguous along m
         kk = e / BM;
         int64_t gm = m0 + m, gk = k0 + kk;
-        ra[e2] = (gm < n && gk < n) ? (A ? A[gm + gk * n] : v_elem(g, vo, gm, gk)) : 0.0;
+        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gm, gk) : A[gm + gk * n]) : 0.0;
       }
       if (EPI == EPI_X) {
         int kb = e % BK, c = e / BK;  // V_bar(k, c) = V_bar[k + c n], contiguous along k
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
           cs[b] += x * ry[rl];
         } else {
           // Q(row = j, col = k) V(j, k) for d_bar, V(j, k) u_k for z_bar
-          double vjk = A ? A[row + col * n] : v_elem(g, vo, row, col);
+          double vjk = RV ? v_elem(g, vo, row, col) : A[row + col * n];
           rs1[q] += v * vjk;
           rs2[q] += vjk * cy[cl];
         }
@@ -529,11 +531,17 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
     if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
     return DPR1_OK;
   }
-  hipLaunchKernelGGL(k_gemm<EPI_X>, dim3(ggrid), dim3(NT), 0, st, g);
+  if (V)
+    hipLaunchKernelGGL((k_gemm<EPI_X, false>), dim3(ggrid), dim3(NT), 0, st, g);
+  else
+    hipLaunchKernelGGL((k_gemm<EPI_X, true>), dim3(ggrid), dim3(NT), 0, st, g);
   if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
   hipLaunchKernelGGL(k_bwd_u, dim3((unsigned)nbatch), dim3(256), 0, st, n, tiles, pr, pc, y, u, rho_bar);
   g.B = X;
-  hipLaunchKernelGGL(k_gemm<EPI_D>, dim3(ggrid), dim3(NT), 0, st, g);
+  if (V)
+    hipLaunchKernelGGL((k_gemm<EPI_D, false>), dim3(ggrid), dim3(NT), 0, st, g);
+  else
+    hipLaunchKernelGGL((k_gemm<EPI_D, true>), dim3(ggrid), dim3(NT), 0, st, g);
   if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
   hipLaunchKernelGGL(k_bwd_final, dim3((unsigned)((n * nbatch + 255) / 256)), dim3(256), 0, st, n, nbatch, tiles,
                      rho, pd, pz, d_bar, z_bar);
