@@ -973,6 +973,43 @@ __device__ __forceinline__ double block_sum_comp(double s, double c, double* sm)
 
 // One block of FIXT threads per flagged eigenpair at a time; the inner index
 // is strided over the block and every pass ends in a block-wide sum.
+// The four sums of a continued pass in one exchange: the Neumaier partials
+// (s, c) combined as in block_sum_comp and three plain sums a, b, e as in
+// block_sum (same orders, so the same results), with one pair of barriers
+// instead of four.  sm holds 20 values.
+__device__ __forceinline__ double block_sum_comp3(double s, double c, double& a, double& b, double& e,
+                                                  double* sm) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
+    const dd t = two_sum(s, s2);
+    s = t.hi;
+    c = c + c2 + t.lo;
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  e = wave_sum(e);
+  const int wv = threadIdx.x / WAVE;
+  __syncthreads();
+  if (threadIdx.x % WAVE == 0) {
+    sm[wv] = s;
+    sm[4 + wv] = c;
+    sm[8 + wv] = a;
+    sm[12 + wv] = b;
+    sm[16 + wv] = e;
+  }
+  __syncthreads();
+  double S = sm[0], C = sm[4];
+  for (int w = 1; w < 4; ++w) {
+    dd t = two_sum(S, sm[w]);
+    S = t.hi;
+    C += sm[4 + w] + t.lo;
+  }
+  a = (sm[8] + sm[9]) + (sm[10] + sm[11]);
+  b = (sm[12] + sm[13]) + (sm[14] + sm[15]);
+  e = (sm[16] + sm[17]) + (sm[18] + sm[19]);
+  return S + C;
+}
+
 // Item e of the list: the n0 long items sit at the front, the others at the
 // back in reverse order.
 __device__ __forceinline__ int fix_slot(const KArgs& A, int n0, int e) {
@@ -980,7 +1017,7 @@ __device__ __forceinline__ int fix_slot(const KArgs& A, int n0, int e) {
 }
 
 __device__ void fix_items(const KArgs& A) {
-  __shared__ double sm[8];
+  __shared__ double sm[20];
   __shared__ int next;
   const int tid = threadIdx.x;
   const int n0 = A.ctr[0];
@@ -1061,10 +1098,7 @@ __device__ void fix_items(const KArgs& A) {
           sp3 += tp3;
           sp4 += tp3 * u;
         }
-        Sz = block_sum_comp(cs, cc, sm) / zi2;
-        sp = block_sum(sp, sm);
-        sp3 = block_sum(sp3, sm);
-        sp4 = block_sum(sp4, sm);
+        Sz = block_sum_comp3(cs, cc, sp, sp3, sp4, sm) / zi2;
         ++iters;
         const double g = (bp - m) + Sz;
         if (g > 0) L = m; else if (g < 0) U = m;
