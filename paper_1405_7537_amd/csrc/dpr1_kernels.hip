@@ -14,6 +14,9 @@
 //              Per eigenvalue: shift test, tip b in double-double, extreme
 //              root of the arrowhead secular function (model passes, the
 //              last one with compensated summation), near-zero test, ||x||.
+//              Instances for 4, 6 and 8 waves per SIMD (register budgets);
+//              the split W, the budget and the pass count are options that
+//              dpr1_autotune / dpr1_batched_autotune choose by timing.
 //   k_out   -- user outputs in the caller's index order.
 //   k_fix   -- one 256-thread block at a time per flagged eigenpair: root
 //              search continued past k_eig's pass budget, double-double
