@@ -179,3 +179,71 @@ def tip(d, z, rho, i, mode=0):
     if rc != 0:
         raise ValueError(f"oracle_tip failed with code {rc}")
     return b.value, kb.value
+
+
+def eig_general(d, z, rho, vectors=True):
+    """All eigenpairs of D + rho z z^T for any finite d (any order, repeated values) and any finite
+    z (zeros allowed), by the reduction of Sec. 1 of the paper: sort the poles decreasingly (the
+    same permutation applied to z), deflate a pole whose z_j is zero (eigenpair (d_j, e_j)), and
+    merge a group of equal poles by an orthogonal transformation of its block that maps its part
+    w of z onto ||w|| e_first (a Householder reflection): the pole then appears once in the reduced
+    problem, with z = ||w||, and the other vectors of the reflection give ||w||-orthogonal
+    eigenvectors for the same eigenvalue.  The reduced problem (strictly decreasing poles, no zero
+    z) is solved by Algorithm 1 (``eig``).  Returns (lam decreasing, V with V[:, k] = v_k).
+    Ties between equal eigenvalues are in no particular order."""
+    d = np.asarray(d, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    n = d.size
+    order = np.argsort(-d, kind="stable")            # sorted position s -> original row order[s]
+    ds, zs = d[order], z[order]
+    red_d, red_z = [], []
+    cols = []          # (value, kind, payload): kind 0 reduced k; 1 unit vector at s; 2 reflection column
+    members = []       # per reduced entry: list of (s, scale) rows it spreads to
+    s = 0
+    while s < n:
+        e = s + 1
+        while e < n and ds[e] == ds[s]:
+            e += 1
+        w = zs[s:e]
+        nw = float(np.sqrt(np.sum(w * w)))
+        if nw == 0.0:
+            for t in range(s, e):
+                cols.append((ds[s], 1, t))
+        elif e - s == 1:
+            members.append([(s, 1.0)])
+            red_d.append(ds[s])
+            red_z.append(zs[s])
+        else:
+            members.append([(t, zs[t] / nw) for t in range(s, e)])
+            red_d.append(ds[s])
+            red_z.append(nw)
+            u = w / nw
+            u[0] += 1.0 if u[0] >= 0 else -1.0
+            H = np.eye(e - s) - (2.0 / float(u @ u)) * np.outer(u, u)
+            for t in range(1, e - s):
+                cols.append((ds[s], 2, (s, H[:, t])))
+        s = e
+    m = len(red_d)
+    lam_r, V_r = (np.empty(0), np.empty((0, 0)))
+    if m:
+        lam_r, V_r = eig(np.array(red_d), np.array(red_z), rho, vectors=True)
+    for k in range(m):
+        cols.append((lam_r[k], 0, k))
+    cols.sort(key=lambda c: -c[0])
+    lam = np.array([c[0] for c in cols])
+    if not vectors:
+        return lam, None
+    U = np.zeros((n, n))                              # rows in sorted positions
+    for c, (_, kind, pay) in enumerate(cols):
+        if kind == 0:
+            for r, mem in enumerate(members):
+                for (t, sc) in mem:
+                    U[t, c] = V_r[r, pay] * sc
+        elif kind == 1:
+            U[pay, c] = 1.0
+        else:
+            s0, h = pay
+            U[s0:s0 + h.size, c] = h
+    V = np.empty((n, n))
+    V[order, :] = U
+    return lam, V

@@ -367,3 +367,51 @@ def test_backward_finite_differences(orc, rho):
     assert np.max(np.abs(fd_d - db)) < 1e-6 * scale
     assert np.max(np.abs(fd_z - zb)) < 1e-6 * scale
     assert abs(fd_r - rb) < 1e-6 * scale
+
+
+# ------------------------------------------------------ reducible inputs (front end)
+def _reducible(n, seed, reps=3, zeros=3):
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-1, 1, n)
+    for _ in range(reps):                       # groups of equal poles
+        a, b = rng.choice(n, 2, replace=False)
+        d[b] = d[a]
+    z = rng.standard_normal(n)
+    z[rng.choice(n, zeros, replace=False)] = 0.0
+    return d, z
+
+
+@pytest.mark.parametrize("seed,rho", [(0, 1.0), (1, -0.8), (2, 5.0), (3, 0.3)])
+def test_general_front_end_against_dense(orc, seed, rho):
+    """Unsorted poles, repeated poles and zero z_j: eigenvalues match a dense symmetric
+    eigensolver, eigenvectors are orthonormal with a small residual, in 60-digit arithmetic."""
+    d, z = _reducible(14, seed)
+    lam, V = orc.eig_general(d, z, rho)
+    L = T.dense_values(d, z, rho, dps=60)
+    A = np.diag(d) + rho * np.outer(z, z)
+    scale = np.max(np.abs(np.linalg.eigvalsh(A)))
+    for k in range(14):
+        assert abs(lam[k] - float(L[k])) <= 1e-14 * scale
+    assert np.all(np.diff(lam) <= 0)
+    assert np.max(np.abs(V.T @ V - np.eye(14))) <= 1e-14
+    assert np.max(np.abs(A @ V - V * lam)) <= 1e-14 * scale
+
+
+def test_general_front_end_special_cases(orc):
+    # all z zero: A = D
+    lam, V = orc.eig_general([0.3, -1.0, 2.0], [0.0, 0.0, 0.0], 1.0)
+    assert list(lam) == [2.0, 0.3, -1.0]
+    assert np.array_equal(np.abs(V), np.abs(np.eye(3)[:, [2, 0, 1]]))
+    # one pole repeated three times with z = (a, b, c): eigenvalue d twice, the rest from 2x2-free
+    d = [0.5, 0.5, 0.5, -0.25]
+    z = [1.0, 2.0, 2.0, 1.0]
+    lam, V = orc.eig_general(d, z, 1.0)
+    assert np.sum(np.abs(lam - 0.5) == 0.0) == 2
+    A = np.diag(d) + np.outer(z, z)
+    assert np.max(np.abs(A @ V - V * lam)) <= 1e-14 * np.max(np.abs(lam))
+    # strictly decreasing input with no zero z: the same as Algorithm 1 directly
+    d, z, rho = W.uniform(40, 3)
+    l1, V1 = orc.eig_general(d[::-1].copy(), z[::-1].copy(), rho)
+    l2, V2 = orc.eig(d, z, rho)
+    assert np.array_equal(l1, l2)
+    assert np.array_equal(V1, V2[::-1, :])

@@ -139,3 +139,16 @@ def rel(a, b):
         if b == 0:
             return float(abs(a))
         return float(abs(a - b) / abs(b))
+
+
+def dense_values(d, z, rho, dps=60):
+    """Eigenvalues (descending) of the explicit matrix via mp.eigsy, for any d and z (reducible
+    inputs included: no eigenvector normalisation, which needs d_j != lambda)."""
+    with mp.workdps(dps):
+        n = len(d)
+        A = mp.matrix(n, n)
+        for r in range(n):
+            for c in range(n):
+                A[r, c] = _mp(rho) * _mp(z[r]) * _mp(z[c]) + (_mp(d[r]) if r == c else 0)
+        E = mp.eigsy(A, eigvals_only=True)
+        return sorted([E[t] for t in range(n)], key=lambda x: -x)
