@@ -19,13 +19,13 @@
  *    return.  Workspace contents need not be initialised.
  *  - All work is enqueued asynchronously on `stream` (a hipStream_t passed as
  *    void*; NULL = the default stream).  No call synchronises the host, so the
- *    launches may be captured into a hipGraph.  Only dpr1_batched_plan copies
- *    from host memory.
+ *    launches may be captured into a hipGraph, except dpr1_batched_plan (it
+ *    copies from host memory), the autotuners and dpr1_eig_general.
  *  - Inputs (Sec. 1 of the paper): n >= 1, d strictly decreasing, every
  *    z_j != 0, rho != 0 and finite.  rho < 0 is reduced to rho > 0 as in
  *    Sec. 1 by solving with (-d reversed, z reversed, -rho) and mapping back.
- *    Sorting and deflation are the caller's job (reducible problems are
- *    reported, not solved).
+ *    dpr1_eig and the batched path report reducible problems (info) rather
+ *    than solve them; dpr1_eig_general sorts and deflates first.
  *  - Outputs: lambda[k] decreasing (strict interlacing, eq. interlace);
  *    V column-major, column k (k = 0..n-1) = v_k at V + k*ldv, with the sign
  *    of eq. (Aeigenvec): v_k has the direction of (D - lambda_k I)^{-1} z.
@@ -226,6 +226,40 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
                               const double* xnorm, const double* V, const double* lambda_bar,
                               const double* V_bar, double* d_bar, double* z_bar,
                               double* rho_bar, void* work, size_t work_bytes, void* stream);
+
+/* Reducible inputs (Sec. 1): any finite d (any order, repeated values) and
+ * any finite z (zeros allowed).  The poles are sorted decreasingly; a pole
+ * with z_j == 0 is deflated (eigenpair (d_j, e_j)); a group of equal poles
+ * d_j with part w of z is merged by a Householder reflection H of its block
+ * with H w = -sign(w_first) ||w|| e_first: the pole enters the reduced problem
+ * once, with z = ||w||, and the other columns of H are eigenvectors for the
+ * eigenvalue d_j (orthogonal to w).  The reduced problem, strictly decreasing
+ * with no zero z, is solved by dpr1_eig on the device (eigenvalues and the
+ * shifted representation only); its eigenvectors are then written directly
+ * in the caller's row order from eq. (eigenvecAi) evaluated on the original
+ * d and z.
+ *   d, z         [n] input (device, float64), rows in the caller's order
+ *   rho          scalar (host), != 0 and finite
+ *   lambda       [n] output, decreasing
+ *   V            [ldv*n] output or NULL; column k = v_k with rows in the
+ *                caller's order (V^T A V = diag(lambda) for the unsorted A);
+ *                columns of equal eigenvalues form an orthonormal basis of
+ *                the eigenspace, in no particular order
+ *   info         [1] device int32: 0, DPR1_INFO_NONFINITE, or a code of the
+ *                reduced solve
+ *   opts         options of the reduced solve (NULL = defaults; an invalid
+ *                waves_per_simd is argument -9)
+ *   work, work_bytes  device workspace (>= dpr1_general_workspace_size(n),
+ *                O(n) bytes)
+ * Unlike every other entry point this one SYNCHRONISES the host with
+ * `stream`: the reduction (a sort and a scan of n numbers) runs on the host
+ * from a device-to-host copy of d and z, and the reduced eigenvalues are
+ * merged with the deflated poles on the host.  It cannot be captured in a
+ * hipGraph.  Returns 0, -p for an invalid argument p, or DPR1_EHIP.         */
+size_t dpr1_general_workspace_size(int64_t n);
+int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, double* lambda,
+                     double* V, int64_t ldv, int32_t* info, const dpr1_opts* opts, void* work,
+                     size_t work_bytes, void* stream);
 
 /* Text for a return code or an info code.                                   */
 const char* dpr1_strerror(int code);

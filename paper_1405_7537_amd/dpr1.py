@@ -65,6 +65,10 @@ def lib():
             L.dpr1_backward_workspace_size.argtypes = [i64, i64]
             L.dpr1_backward_workspace_size.restype = C.c_size_t
             L.dpr1_eig_backward_batched.argtypes = [i64, i64] + [vp] * 12 + [vp, C.c_size_t, vp]
+        L.dpr1_general_workspace_size.argtypes = [i64]
+        L.dpr1_general_workspace_size.restype = C.c_size_t
+        L.dpr1_eig_general.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, C.POINTER(Opts), vp,
+                                       C.c_size_t, vp]
         L.dpr1_strerror.argtypes = [C.c_int]
         L.dpr1_strerror.restype = C.c_char_p
         _lib = L
@@ -183,6 +187,32 @@ def eig(d, z, rho, vectors=True, opts: Opts | None = None, check=True, want_stat
         code = int(info.item())
         if code != 0:
             raise ValueError(f"dpr1_eig: info = {code} ({INFO_TEXT.get(code, '?')})")
+    return r
+
+
+def eig_general(d, z, rho, vectors=True, opts: Opts | None = None, check=True, device="cuda"):
+    """All eigenpairs of D + rho z z^T for any finite d (any order, repeated values) and z (zeros
+    allowed): dpr1_eig_general sorts, deflates zero z_j, merges equal poles and solves the reduced
+    problem on the device.  Synchronises the stream.  Returns a Result with lam [n] decreasing,
+    V [n, n] (rows in the input order; equal eigenvalues get an orthonormal basis of their
+    eigenspace) and info."""
+    d = _dev(d, device)
+    z = _dev(z, device)
+    n = d.numel()
+    dev = d.device
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Vt = torch.empty((n, n), dtype=torch.float64, device=dev) if vectors else None
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    wb = int(lib().dpr1_general_workspace_size(n))
+    work = torch.empty(max(wb, 1), dtype=torch.uint8, device=dev)
+    rc = lib().dpr1_eig_general(_ptr(d), _ptr(z), float(rho), n, _ptr(lam), _ptr(Vt), max(n, 1), _ptr(info),
+                                C.byref(opts) if opts is not None else None, _ptr(work), wb, _stream())
+    _rc(rc, "dpr1_eig_general")
+    r = Result(lam=lam, V=Vt.t() if Vt is not None else None, info=info)
+    if check:
+        code = int(info.item())
+        if code != 0:
+            raise ValueError(f"dpr1_eig_general: info = {code} ({INFO_TEXT.get(code, '?')})")
     return r
 
 

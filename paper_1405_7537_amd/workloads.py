@@ -124,3 +124,21 @@ def example4(beta, m=100):
     dd, zz = np.array(dd), np.array(zz)
     order = np.argsort(-dd, kind="stable")
     return dd[order].copy(), zz[order].copy(), 1.0
+
+
+def reducible(n, seed, groups=None, zeros=None, rho=1.0):
+    """Unsorted poles with repeated values and some zero z_j (the input of the front end of Sec. 1):
+    `groups` poles get the value of another pole (groups of 2 and more), `zeros` entries of z are 0.
+    Defaults: n // 10 of each."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-1.0, 1.0, n)
+    groups = n // 10 if groups is None else groups
+    zeros = n // 10 if zeros is None else zeros
+    if n >= 2:
+        for _ in range(groups):
+            a, b = rng.choice(n, 2, replace=False)
+            d[b] = d[a]
+    z = rng.standard_normal(n)
+    if zeros:
+        z[rng.choice(n, min(zeros, n), replace=False)] = 0.0
+    return d, z, rho

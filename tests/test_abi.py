@@ -21,7 +21,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ["dpr1_eig", "dpr1_eig_batched", "dpr1_batched_plan", "dpr1_workspace_size",
                  "dpr1_batched_workspace_size", "dpr1_eig_backward_batched",
-                 "dpr1_backward_workspace_size", "dpr1_default_opts", "dpr1_strerror"]:
+                 "dpr1_backward_workspace_size", "dpr1_default_opts", "dpr1_strerror",
+                 "dpr1_eig_general", "dpr1_general_workspace_size"]:
         assert must in names, must
 
 
@@ -87,3 +88,33 @@ def test_invalid_register_budget_is_rejected_before_launch(lib):
     offs = (ctypes.c_int64 * 3)(0, 5, 9)
     plan = Plan()
     assert lib.dpr1_batched_plan(2, offs, ctypes.byref(o), ctypes.byref(plan), fake, 1 << 24, None) == -3
+
+
+def test_general_front_end_argument_errors_need_no_gpu(lib):
+    """dpr1_eig_general checks its arguments before its first device-to-host copy."""
+    from paper_1405_7537_amd.dpr1 import Opts
+    vp = ctypes.c_void_p
+    lib.dpr1_general_workspace_size.argtypes = [ctypes.c_int64]
+    lib.dpr1_general_workspace_size.restype = ctypes.c_size_t
+    assert lib.dpr1_general_workspace_size(0) == 0
+    a, b = lib.dpr1_general_workspace_size(1000), lib.dpr1_general_workspace_size(2000)
+    assert 0 < a < b < 2000 * 1000   # O(n): no n x n scratch
+    lib.dpr1_eig_general.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64, vp,
+                                     ctypes.POINTER(Opts), vp, ctypes.c_size_t, vp]
+    fake = vp(0x1000)
+    big = 1 << 30
+    assert lib.dpr1_eig_general(None, fake, 1.0, 4, fake, None, 4, fake, None, fake, big, None) == -1
+    assert lib.dpr1_eig_general(fake, None, 1.0, 4, fake, None, 4, fake, None, fake, big, None) == -2
+    assert lib.dpr1_eig_general(fake, fake, 0.0, 4, fake, None, 4, fake, None, fake, big, None) == -3
+    assert lib.dpr1_eig_general(fake, fake, float("inf"), 4, fake, None, 4, fake, None, fake, big, None) == -3
+    assert lib.dpr1_eig_general(fake, fake, 1.0, 0, fake, None, 4, fake, None, fake, big, None) == -4
+    assert lib.dpr1_eig_general(fake, fake, 1.0, 4, None, None, 4, fake, None, fake, big, None) == -5
+    assert lib.dpr1_eig_general(fake, fake, 1.0, 8, fake, fake, 4, fake, None, fake, big, None) == -7
+    assert lib.dpr1_eig_general(fake, fake, 1.0, 4, fake, None, 4, None, None, fake, big, None) == -8
+    o = Opts()
+    lib.dpr1_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.dpr1_default_opts(ctypes.byref(o))
+    o.waves_per_simd = 3
+    assert lib.dpr1_eig_general(fake, fake, 1.0, 4, fake, None, 4, fake, ctypes.byref(o), fake, big, None) == -9
+    assert lib.dpr1_eig_general(fake, fake, 1.0, 4, fake, None, 4, fake, None, None, big, None) == -10
+    assert lib.dpr1_eig_general(fake, fake, 1.0, 4, fake, None, 4, fake, None, fake, 16, None) == -11
