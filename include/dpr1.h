@@ -256,10 +256,25 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
  * from a device-to-host copy of d and z, and the reduced eigenvalues are
  * merged with the deflated poles on the host.  It cannot be captured in a
  * hipGraph.  Returns 0, -p for an invalid argument p, or DPR1_EHIP.         */
-size_t dpr1_general_workspace_size(int64_t n);
+size_t dpr1_general_workspace_size(int64_t n);   /* also for dpr1_eig_hermitian */
 int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, double* lambda,
                      double* V, int64_t ldv, int32_t* info, const dpr1_opts* opts, void* work,
                      size_t work_bytes, void* stream);
+
+/* Hermitian DPR1 (the extension named in the paper's conclusions):
+ * A = D + rho z z^H with real d, complex z.  With Phi = diag(z_j / |z_j|)
+ * (1 where z_j = 0), Phi is unitary, Phi D Phi^H = D and z = Phi |z|, so
+ * A = Phi (D + rho |z| |z|^T) Phi^H: the eigenvalues are those of the real
+ * problem with |z| (solved as by dpr1_eig_general: any order, repeated poles,
+ * zero z_j) and v_k = Phi v_k^real.
+ *   z    [2n] device, interleaved (re, im) -- complex128
+ *   V    [2*ldv*n] device complex128 or NULL: element (i, k) at V[2 (i + k ldv)]
+ *        (re) and V[2 (i + k ldv) + 1] (im); column k = v_k, V^H A V = diag(lambda)
+ * Everything else (lambda, info, opts, workspace, errors, host
+ * synchronisation) as for dpr1_eig_general.                                 */
+int dpr1_eig_hermitian(const double* d, const double* z, double rho, int64_t n, double* lambda,
+                       double* V, int64_t ldv, int32_t* info, const dpr1_opts* opts, void* work,
+                       size_t work_bytes, void* stream);
 
 /* Text for a return code or an info code.                                   */
 const char* dpr1_strerror(int code);

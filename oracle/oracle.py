@@ -247,3 +247,21 @@ def eig_general(d, z, rho, vectors=True):
     V = np.empty((n, n))
     V[order, :] = U
     return lam, V
+
+
+def eig_hermitian(d, z, rho, vectors=True):
+    """All eigenpairs of D + rho z z^H with real d and complex z, the extension of Algorithm 1 to the
+    Hermitian case that the paper states after Algorithm 1 (and in the abstract).  Phi = diag(z_j/|z_j|)
+    (1 where z_j = 0) is unitary with Phi D Phi^H = D and z = Phi |z|, so
+    D + rho z z^H = Phi (D + rho |z||z|^T) Phi^H: the eigenvalues are those of the real problem with
+    |z| (eig_general), and v_k = Phi v_k^real.  Returns (lam decreasing, V complex, V[:, k] = v_k)."""
+    d = np.asarray(d, dtype=np.float64)
+    z = np.asarray(z, dtype=np.complex128)
+    a = np.abs(z)
+    safe = np.where(a > 0, a, 1.0)
+    # the phase componentwise (real over real), so that a real z_j gives exactly +-1
+    ph = np.where(a > 0, z.real / safe + 1j * (z.imag / safe), 1.0 + 0.0j)
+    lam, Vr = eig_general(d, a, rho, vectors=vectors)
+    if not vectors:
+        return lam, None
+    return lam, ph[:, None] * Vr

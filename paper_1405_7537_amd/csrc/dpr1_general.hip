@@ -1,5 +1,8 @@
 // Front end for reducible inputs (Sec. 1 of the paper): any finite d (any
-// order, repeated values) and any finite z (zeros allowed).
+// order, repeated values) and any finite z (zeros allowed); and the Hermitian
+// case A = D + rho z z^H with complex z, which a diagonal unitary similarity
+// turns into the real problem with |z| (the extension the paper's closing
+// remarks mention).
 //
 // The reduction is host work on n numbers: sort the poles decreasingly,
 // deflate a pole whose z_j is zero (eigenpair (d_j, e_j)), and merge a group of
@@ -22,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 #include <vector>
 
@@ -54,6 +58,7 @@ struct AsmArgs {
   const double* cmu;
   const double* cic;
   const double* cub;
+  const double* ph;  // [2n] unit phases z_i / |z_i| (Hermitian case), else null
   double* V;
 };
 
@@ -62,39 +67,139 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 }
 
-__global__ void __launch_bounds__(256) k_assemble(AsmArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const double di = a.d[i], zi = a.z[i];
-  const int g = a.rgrp[i], p = a.rpos[i];
-  const double u = a.ru[i];
-  for (int64_t c = blockIdx.y; c < a.n; c += gridDim.y) {
-    const int kind = a.ckind[c];
-    double v = 0.0;
-    if (kind == COL_REDUCED) {
-      if (zi != 0.0) {
-        // mu / den with one residual correction, then the scaled norm
-        const double m = a.cmu[c];
-        const double den = (di - a.csig[c]) - m;
-        const double rc = rcp_nr(den);
-        double q = m * rc;
-        q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);
-        v = (zi * q) * a.cic[c];
-      }
-    } else if (kind == COL_UNIT) {
-      v = (i == a.cidx[c]) ? 1.0 : 0.0;
-    } else if (g == a.cidx[c]) {
-      // column t of H = I - beta u u^T restricted to the group
-      v = (p == a.ct[c] ? 1.0 : 0.0) - a.cub[c] * u;
+// Tile: ASM_CB columns x ASM_T * ASM_R rows.  The block stages the column
+// parameters in LDS once; each thread keeps ASM_R rows in registers and, per
+// column, issues ASM_R streaming stores, each a contiguous, aligned 512-byte
+// window per wave when ldv is a multiple of 64.
+constexpr int ASM_T = 256, ASM_R = 4, ASM_CB = 16;
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// CPLX: V is complex (interleaved re, im; element (i, c) at 2 (i + c ldv)) and
+// row i is multiplied by the phase of z_i.
+template <bool CPLX>
+__global__ void __launch_bounds__(ASM_T) k_assemble(AsmArgs a) {
+  __shared__ int s_kind[ASM_CB], s_idx[ASM_CB], s_t[ASM_CB];
+  __shared__ double s_sig[ASM_CB], s_mu[ASM_CB], s_ic[ASM_CB], s_ub[ASM_CB];
+  const int64_t n = a.n;
+  const int64_t r0 = (int64_t)blockIdx.x * (ASM_T * ASM_R);
+  double di[ASM_R], zi[ASM_R], ui[ASM_R], pr[ASM_R], pm[ASM_R];
+  int gi[ASM_R], pi[ASM_R];
+#pragma unroll
+  for (int j = 0; j < ASM_R; ++j) {
+    const int64_t i = r0 + threadIdx.x + j * ASM_T;
+    const bool ok = i < n;
+    if (CPLX) {
+      pr[j] = ok ? a.ph[2 * i] : 0.0;
+      pm[j] = ok ? a.ph[2 * i + 1] : 0.0;
     }
-    __builtin_nontemporal_store(v, &a.V[i + c * a.ldv]);
+    di[j] = ok ? a.d[i] : 0.0;
+    zi[j] = ok ? a.z[i] : 0.0;
+    ui[j] = ok ? a.ru[i] : 0.0;
+    gi[j] = ok ? a.rgrp[i] : -1;
+    pi[j] = ok ? a.rpos[i] : -1;
+  }
+  const int64_t ncg = (n + ASM_CB - 1) / ASM_CB;
+  for (int64_t cg = blockIdx.y; cg < ncg; cg += gridDim.y) {
+    const int64_t c0 = cg * ASM_CB;
+    const int nc = (int)min((int64_t)ASM_CB, n - c0);
+    __syncthreads();  // the previous group's parameters are no longer read
+    if (threadIdx.x < nc) {
+      const int64_t c = c0 + threadIdx.x;
+      s_kind[threadIdx.x] = a.ckind[c];
+      s_idx[threadIdx.x] = a.cidx[c];
+      s_t[threadIdx.x] = a.ct[c];
+      s_sig[threadIdx.x] = a.csig[c];
+      s_mu[threadIdx.x] = a.cmu[c];
+      s_ic[threadIdx.x] = a.cic[c];
+      s_ub[threadIdx.x] = a.cub[c];
+    }
+    __syncthreads();
+    for (int cc = 0; cc < nc; ++cc) {
+      const int kind = s_kind[cc];
+      const int64_t e0 = (c0 + cc) * a.ldv + r0 + threadIdx.x;
+      double v[ASM_R];
+      if (kind == COL_REDUCED) {
+        const double m = s_mu[cc], sg = s_sig[cc], ic = s_ic[cc];
+#pragma unroll
+        for (int j = 0; j < ASM_R; ++j) {
+          // mu / den with one residual correction, then the scaled norm; a
+          // row with z_i == 0 (deflated, or a zero member of a merged group)
+          // is exactly 0 whatever den is
+          const double den = (di[j] - sg) - m;
+          const double rc = rcp_nr(den);
+          double q = m * rc;
+          q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);
+          v[j] = zi[j] != 0.0 ? (zi[j] * q) * ic : 0.0;
+        }
+      } else if (kind == COL_UNIT) {
+        const int64_t at = s_idx[cc];
+#pragma unroll
+        for (int j = 0; j < ASM_R; ++j) v[j] = (r0 + threadIdx.x + j * ASM_T == at) ? 1.0 : 0.0;
+      } else {
+        // column t of H = I - beta u u^T restricted to the group
+        const int g = s_idx[cc], t = s_t[cc];
+        const double ub = s_ub[cc];
+#pragma unroll
+        for (int j = 0; j < ASM_R; ++j) v[j] = gi[j] == g ? (pi[j] == t ? 1.0 : 0.0) - ub * ui[j] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < ASM_R; ++j) {
+        if (r0 + threadIdx.x + j * ASM_T >= n) continue;
+        if (CPLX) {
+          const dbl2 cv = {v[j] * pr[j], v[j] * pm[j]};
+          __builtin_nontemporal_store(cv, (dbl2*)(a.V + 2 * (e0 + j * ASM_T)));
+        } else {
+          __builtin_nontemporal_store(v[j], a.V + e0 + j * ASM_T);
+        }
+      }
+    }
+  }
+}
+
+// Stable sort of the poles in decreasing order: order[s] = the row with the
+// s-th largest d (equal values keep their row order, -0 and +0 are equal).
+// LSD radix sort on order-preserving 64-bit keys, 11 bits a pass; a pass
+// whose digit is the same for every key is skipped.
+static void sort_decreasing(const std::vector<double>& d, std::vector<int64_t>& order) {
+  const int64_t n = (int64_t)d.size();
+  std::vector<uint64_t> k(n), k2(n);
+  std::vector<int64_t> o2(n);
+  order.resize(n);
+  for (int64_t j = 0; j < n; ++j) {
+    const double x = d[j] == 0.0 ? 0.0 : d[j];
+    uint64_t b;
+    memcpy(&b, &x, 8);
+    b = (b >> 63) ? ~b : (b | (uint64_t(1) << 63));  // increasing with x
+    k[j] = ~b;                                        // decreasing with x
+    order[j] = j;
+  }
+  std::vector<int64_t> cnt(2048);
+  for (int sh = 0; sh < 64; sh += 11) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t j = 0; j < n; ++j) ++cnt[(k[j] >> sh) & 2047];
+    if (cnt[(k[0] >> sh) & 2047] == n) continue;
+    int64_t acc = 0;
+    for (int b = 0; b < 2048; ++b) {
+      const int64_t c = cnt[b];
+      cnt[b] = acc;
+      acc += c;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t at = cnt[(k[j] >> sh) & 2047]++;
+      k2[at] = k[j];
+      o2[at] = order[j];
+    }
+    k.swap(k2);
+    order.swap(o2);
   }
 }
 
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct GLayout {
-  size_t dr, zr, lamr, sidx, mu, xn, inf, rgrp, rpos, ru, ckind, cidx, ct, csig, cmu, cic, cub, solver, total;
+  size_t dr, zr, lamr, sidx, mu, xn, inf, rgrp, rpos, ru, ckind, cidx, ct, csig, cmu, cic, cub, zabs, ph, solver,
+      total;
 };
 static GLayout glayout(int64_t n) {
   GLayout L;
@@ -116,6 +221,8 @@ static GLayout glayout(int64_t n) {
   L.cmu = o; o = al(o + 8 * n);
   L.cic = o; o = al(o + 8 * n);
   L.cub = o; o = al(o + 8 * n);
+  L.zabs = o; o = al(o + 8 * n);
+  L.ph = o; o = al(o + 16 * n);
   L.solver = o; o = al(o + dpr1_workspace_size(n));
   L.total = o;
   return L;
@@ -138,9 +245,12 @@ size_t dpr1_general_workspace_size(int64_t n) {
   return glayout(n).total;
 }
 
-int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V,
-                     int64_t ldv, int32_t* info, const dpr1_opts* opts, void* work, size_t work_bytes,
-                     void* stream) {
+}  // extern "C"
+
+// Argument checks shared by the two entry points (same positions).
+static int check_args(const double* d, const void* z, double rho, int64_t n, const double* lambda,
+                      const double* V, int64_t ldv, const int32_t* info, const dpr1_opts* opts, const void* work,
+                      size_t work_bytes) {
   if (!d) return -1;
   if (!z) return -2;
   if (!(rho == rho) || rho == 0.0 || rho == INFINITY || rho == -INFINITY) return -3;
@@ -152,28 +262,26 @@ int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, do
       opts->waves_per_simd != 8)
     return -9;
   if (!work) return -10;
-  const GLayout L = glayout(n);
-  if (work_bytes < L.total) return -11;
-  hipStream_t st = (hipStream_t)stream;
-  char* w = (char*)work;
+  if (work_bytes < glayout(n).total) return -11;
+  return 0;
+}
 
-  std::vector<double> hd(n), hz(n);
-  GCHECK(hipMemcpyAsync(hd.data(), d, 8 * n, hipMemcpyDeviceToHost, st));
-  GCHECK(hipMemcpyAsync(hz.data(), z, 8 * n, hipMemcpyDeviceToHost, st));
+static int set_info(int32_t* info, int32_t code, hipStream_t st) {
+  GCHECK(hipMemcpyAsync(info, &code, 4, hipMemcpyHostToDevice, st));
   GCHECK(hipStreamSynchronize(st));
-  int32_t code = DPR1_INFO_OK;
-  for (int64_t j = 0; j < n; ++j)
-    if (!std::isfinite(hd[j]) || !std::isfinite(hz[j])) code = DPR1_INFO_NONFINITE;
-  if (code != DPR1_INFO_OK) {
-    GCHECK(hipMemcpyAsync(info, &code, 4, hipMemcpyHostToDevice, st));
-    GCHECK(hipStreamSynchronize(st));
-    return DPR1_OK;
-  }
+  return DPR1_OK;
+}
 
+// The reduction, the reduced solve and the assembly.  hd, hz: host copies of
+// the poles and of the (real, here nonnegative in the Hermitian case) z; zdev
+// the same z on the device; ph the device phases for a complex V, else null.
+static int front_end(const double* d, const double* zdev, const std::vector<double>& hd,
+                     const std::vector<double>& hz, const double* ph, double rho, int64_t n, double* lambda,
+                     double* V, int64_t ldv, int32_t* info, const dpr1_opts* opts, char* w, const GLayout& L,
+                     hipStream_t st, void* stream) {
   // sorted position s -> original row order[s]
-  std::vector<int64_t> order(n);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return hd[a] > hd[b]; });
+  std::vector<int64_t> order;
+  sort_decreasing(hd, order);
   std::vector<double> rd, rz;
   std::vector<int32_t> rgrp(n, -1), rpos(n, 0);
   std::vector<double> ru(n, 0.0);
@@ -184,6 +292,7 @@ int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, do
   };
   std::vector<Col> cols;
   cols.reserve(n);
+  std::vector<double> u;
   int32_t ngrp = 0;
   for (int64_t s = 0; s < n;) {
     int64_t e = s + 1;
@@ -214,7 +323,7 @@ int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, do
       rd.push_back(dv);
       rz.push_back(nw);
       // u = w/||w|| + sign(u_first) e_first, H = I - beta u u^T, beta = 2/(u^T u)
-      std::vector<double> u(e - s);
+      u.resize(e - s);
       for (int64_t t = s; t < e; ++t) u[t - s] = hz[order[t]] / nw;
       u[0] += u[0] >= 0.0 ? 1.0 : -1.0;
       double uu = 0.0;
@@ -253,14 +362,18 @@ int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, do
     }
     GCHECK(hipMemcpyAsync(&hinf, dinf, 4, hipMemcpyDeviceToHost, st));
     GCHECK(hipStreamSynchronize(st));
-    if (hinf != DPR1_INFO_OK) {
-      GCHECK(hipMemcpyAsync(info, &hinf, 4, hipMemcpyHostToDevice, st));
-      GCHECK(hipStreamSynchronize(st));
-      return DPR1_OK;
-    }
-    for (int64_t k = 0; k < m; ++k) cols.push_back({lamr[k], COL_REDUCED, (int32_t)k, 0, 0.0});
+    if (hinf != DPR1_INFO_OK) return set_info(info, hinf, st);
   }
-  std::stable_sort(cols.begin(), cols.end(), [](const Col& a, const Col& b) { return a.val > b.val; });
+  // both lists are decreasing: merge them (deflated and reflected columns
+  // first among equal values)
+  {
+    std::vector<Col> red(m);
+    for (int64_t k = 0; k < m; ++k) red[k] = {lamr[k], COL_REDUCED, (int32_t)k, 0, 0.0};
+    std::vector<Col> all(n);
+    std::merge(cols.begin(), cols.end(), red.begin(), red.end(), all.begin(),
+               [](const Col& a, const Col& b) { return a.val > b.val; });
+    cols.swap(all);
+  }
 
   std::vector<double> lam(n), csig(n, 0.0), cmu(n, 0.0), cic(n, 0.0), cub(n, 0.0);
   std::vector<int32_t> ckind(n), cidx(n), ct(n);
@@ -283,7 +396,8 @@ int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, do
     a.n = n;
     a.ldv = ldv;
     a.d = d;
-    a.z = z;
+    a.z = zdev;
+    a.ph = ph;
     a.rgrp = (int32_t*)(w + L.rgrp);
     a.rpos = (int32_t*)(w + L.rpos);
     a.ru = (double*)(w + L.ru);
@@ -305,15 +419,69 @@ int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, do
     GCHECK(hipMemcpyAsync((void*)a.cmu, cmu.data(), 8 * n, hipMemcpyHostToDevice, st));
     GCHECK(hipMemcpyAsync((void*)a.cic, cic.data(), 8 * n, hipMemcpyHostToDevice, st));
     GCHECK(hipMemcpyAsync((void*)a.cub, cub.data(), 8 * n, hipMemcpyHostToDevice, st));
-    const unsigned gy = (unsigned)std::min<int64_t>(n, 4096);
-    hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + 255) / 256), gy), dim3(256), 0, st, a);
+    const int64_t rows = ASM_T * ASM_R;
+    const unsigned gy = (unsigned)std::min<int64_t>((n + ASM_CB - 1) / ASM_CB, 65535);
+    const dim3 grid((unsigned)((n + rows - 1) / rows), gy);
+    if (ph)
+      hipLaunchKernelGGL(k_assemble<true>, grid, dim3(ASM_T), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_assemble<false>, grid, dim3(ASM_T), 0, st, a);
     GCHECK(hipGetLastError());
   }
-  code = DPR1_INFO_OK;
-  GCHECK(hipMemcpyAsync(info, &code, 4, hipMemcpyHostToDevice, st));
-  // the host vectors above are sources of the copies: wait before they go
+  // set_info waits for the stream: the host vectors above are sources of the
+  // copies and must outlive them
+  return set_info(info, DPR1_INFO_OK, st);
+}
+
+extern "C" {
+
+int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V,
+                     int64_t ldv, int32_t* info, const dpr1_opts* opts, void* work, size_t work_bytes,
+                     void* stream) {
+  const int bad = check_args(d, z, rho, n, lambda, V, ldv, info, opts, work, work_bytes);
+  if (bad) return bad;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> hd(n), hz(n);
+  GCHECK(hipMemcpyAsync(hd.data(), d, 8 * n, hipMemcpyDeviceToHost, st));
+  GCHECK(hipMemcpyAsync(hz.data(), z, 8 * n, hipMemcpyDeviceToHost, st));
   GCHECK(hipStreamSynchronize(st));
-  return DPR1_OK;
+  for (int64_t j = 0; j < n; ++j)
+    if (!std::isfinite(hd[j]) || !std::isfinite(hz[j])) return set_info(info, DPR1_INFO_NONFINITE, st);
+  return front_end(d, z, hd, hz, nullptr, rho, n, lambda, V, ldv, info, opts, (char*)work, glayout(n), st, stream);
+}
+
+int dpr1_eig_hermitian(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V,
+                       int64_t ldv, int32_t* info, const dpr1_opts* opts, void* work, size_t work_bytes,
+                       void* stream) {
+  const int bad = check_args(d, z, rho, n, lambda, V, ldv, info, opts, work, work_bytes);
+  if (bad) return bad;
+  hipStream_t st = (hipStream_t)stream;
+  const GLayout L = glayout(n);
+  char* w = (char*)work;
+  std::vector<double> hd(n), hzc(2 * n);
+  GCHECK(hipMemcpyAsync(hd.data(), d, 8 * n, hipMemcpyDeviceToHost, st));
+  GCHECK(hipMemcpyAsync(hzc.data(), z, 16 * n, hipMemcpyDeviceToHost, st));
+  GCHECK(hipStreamSynchronize(st));
+  for (int64_t j = 0; j < n; ++j)
+    if (!std::isfinite(hd[j]) || !std::isfinite(hzc[2 * j]) || !std::isfinite(hzc[2 * j + 1]))
+      return set_info(info, DPR1_INFO_NONFINITE, st);
+  // z = Phi |z| with Phi = diag(z_j / |z_j|) unitary (1 where z_j = 0), and
+  // Phi D Phi^H = D: A = Phi (D + rho |z| |z|^T) Phi^H, so the eigenvalues are
+  // those of the real problem with |z| and v = Phi v_real
+  std::vector<double> ha(n), hph(2 * n);
+  for (int64_t j = 0; j < n; ++j) {
+    const double re = hzc[2 * j], im = hzc[2 * j + 1];
+    const double r = std::hypot(re, im);
+    ha[j] = r;
+    hph[2 * j] = r > 0.0 ? re / r : 1.0;
+    hph[2 * j + 1] = r > 0.0 ? im / r : 0.0;
+  }
+  double* za = (double*)(w + L.zabs);
+  double* ph = (double*)(w + L.ph);
+  GCHECK(hipMemcpyAsync(za, ha.data(), 8 * n, hipMemcpyHostToDevice, st));
+  GCHECK(hipMemcpyAsync(ph, hph.data(), 16 * n, hipMemcpyHostToDevice, st));
+  // front_end synchronises before it returns, so ha and hph outlive the copies
+  return front_end(d, za, hd, ha, ph, rho, n, lambda, V, ldv, info, opts, w, L, st, stream);
 }
 
 }  // extern "C"

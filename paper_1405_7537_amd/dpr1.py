@@ -69,6 +69,8 @@ def lib():
         L.dpr1_general_workspace_size.restype = C.c_size_t
         L.dpr1_eig_general.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, C.POINTER(Opts), vp,
                                        C.c_size_t, vp]
+        L.dpr1_eig_hermitian.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, C.POINTER(Opts), vp,
+                                         C.c_size_t, vp]
         L.dpr1_strerror.argtypes = [C.c_int]
         L.dpr1_strerror.restype = C.c_char_p
         _lib = L
@@ -213,6 +215,33 @@ def eig_general(d, z, rho, vectors=True, opts: Opts | None = None, check=True, d
         code = int(info.item())
         if code != 0:
             raise ValueError(f"dpr1_eig_general: info = {code} ({INFO_TEXT.get(code, '?')})")
+    return r
+
+
+def eig_hermitian(d, z, rho, vectors=True, opts: Opts | None = None, check=True, device="cuda"):
+    """All eigenpairs of D + rho z z^H with real d and complex z (dpr1_eig_hermitian): the real
+    problem with |z| through the front end, then v = diag(z_j/|z_j|) v_real.  Synchronises the
+    stream.  Returns a Result with lam [n] float64 decreasing, V [n, n] complex128 (V[:, k] = v_k,
+    rows in the input order) and info."""
+    d = _dev(d, device)
+    z = torch.as_tensor(z, dtype=torch.complex128).to(device).contiguous()
+    n = d.numel()
+    if z.numel() != n:
+        raise ValueError("z must have n entries")
+    dev = d.device
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Vt = torch.empty((n, n), dtype=torch.complex128, device=dev) if vectors else None
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    wb = int(lib().dpr1_general_workspace_size(n))
+    work = torch.empty(max(wb, 1), dtype=torch.uint8, device=dev)
+    rc = lib().dpr1_eig_hermitian(_ptr(d), _ptr(z), float(rho), n, _ptr(lam), _ptr(Vt), max(n, 1), _ptr(info),
+                                  C.byref(opts) if opts is not None else None, _ptr(work), wb, _stream())
+    _rc(rc, "dpr1_eig_hermitian")
+    r = Result(lam=lam, V=Vt.t() if Vt is not None else None, info=info)
+    if check:
+        code = int(info.item())
+        if code != 0:
+            raise ValueError(f"dpr1_eig_hermitian: info = {code} ({INFO_TEXT.get(code, '?')})")
     return r
 
 

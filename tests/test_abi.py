@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
     for must in ["dpr1_eig", "dpr1_eig_batched", "dpr1_batched_plan", "dpr1_workspace_size",
                  "dpr1_batched_workspace_size", "dpr1_eig_backward_batched",
                  "dpr1_backward_workspace_size", "dpr1_default_opts", "dpr1_strerror",
-                 "dpr1_eig_general", "dpr1_general_workspace_size"]:
+                 "dpr1_eig_general", "dpr1_general_workspace_size", "dpr1_eig_hermitian"]:
         assert must in names, must
 
 
@@ -118,3 +118,8 @@ def test_general_front_end_argument_errors_need_no_gpu(lib):
     assert lib.dpr1_eig_general(fake, fake, 1.0, 4, fake, None, 4, fake, ctypes.byref(o), fake, big, None) == -9
     assert lib.dpr1_eig_general(fake, fake, 1.0, 4, fake, None, 4, fake, None, None, big, None) == -10
     assert lib.dpr1_eig_general(fake, fake, 1.0, 4, fake, None, 4, fake, None, fake, 16, None) == -11
+
+    lib.dpr1_eig_hermitian.argtypes = lib.dpr1_eig_general.argtypes
+    assert lib.dpr1_eig_hermitian(None, fake, 1.0, 4, fake, None, 4, fake, None, fake, big, None) == -1
+    assert lib.dpr1_eig_hermitian(fake, fake, float("nan"), 4, fake, None, 4, fake, None, fake, big, None) == -3
+    assert lib.dpr1_eig_hermitian(fake, fake, 1.0, 4, fake, None, 4, fake, None, fake, 16, None) == -11

@@ -40,12 +40,12 @@ def tie_groups(lam):
     return out
 
 
-def check(D, orc, d, z, rho, tag):
-    print(f"[general] {tag} n={len(d)} rho={rho}", flush=True)
-    r = D.eig_general(d, z, rho)
+def check(D, orc, d, z, rho, tag, hermitian=False):
+    print(f"[general] {tag} n={len(d)} rho={rho} hermitian={hermitian}", flush=True)
+    r = (D.eig_hermitian if hermitian else D.eig_general)(d, z, rho)
     lam = r.lam.cpu().numpy()
     V = r.V.cpu().numpy()
-    lo, Vo = orc.eig_general(d, z, rho)
+    lo, Vo = (orc.eig_hermitian if hermitian else orc.eig_general)(d, z, rho)
     den = np.where(lo == 0, 1.0, np.abs(lo))
     el = np.abs(lam - lo) / den
     assert el.max() <= LAM_TOL, (tag, int(np.argmax(el)), el.max())
@@ -63,12 +63,12 @@ def check(D, orc, d, z, rho, tag):
             worst_v = max(worst_v, ev)
             assert ev <= VEC_TOL, (tag, s, ev)
         else:
-            P = V[:, s:e] @ V[:, s:e].T
-            Po = Vo[:, s:e] @ Vo[:, s:e].T
+            P = V[:, s:e] @ V[:, s:e].conj().T
+            Po = Vo[:, s:e] @ Vo[:, s:e].conj().T
             ep = np.max(np.abs(P - Po))
             worst_p = max(worst_p, ep)
             assert ep <= PROJ_TOL, (tag, s, e, ep)
-    orth = np.max(np.abs(V.T @ V - np.eye(n)))
+    orth = np.max(np.abs(V.conj().T @ V - np.eye(n)))
     assert orth <= 1e-13, (tag, orth)
     print(f"[general] {tag}: lam {el.max():.2e} V {worst_v:.2e} proj {worst_p:.2e} orth {orth:.2e}", flush=True)
     return lam, V
@@ -158,3 +158,52 @@ def test_large_reducible_properties(D):
 def test_nonfinite_input_is_reported(D):
     r = D.eig_general([1.0, np.nan, 0.0], [1.0, 1.0, 1.0], 1.0, check=False)
     assert int(r.info.item()) == 3
+
+
+def _complex_z(z, seed):
+    return np.asarray(z) * np.exp(1j * np.random.default_rng(seed).uniform(0, 2 * np.pi, len(z)))
+
+
+@pytest.mark.parametrize("n,seed,rho", [(40, 30, 1.0), (300, 31, -0.8), (777, 32, 2.5)])
+def test_hermitian_against_oracle(D, orc, n, seed, rho):
+    """Complex z with repeated poles and zero entries: the Hermitian entry point against the oracle."""
+    d, z, _ = W.reducible(n, seed, rho=rho)
+    check(D, orc, d, _complex_z(z, seed), rho, f"hermitian seed {seed}", hermitian=True)
+
+
+def test_hermitian_degenerate(D, orc):
+    check(D, orc, [0.5], [0.0 + 0.0j], 1.0, "hermitian n1 zero", hermitian=True)
+    check(D, orc, [0.5], [0.3 - 0.4j], 2.0, "hermitian n1", hermitian=True)
+    check(D, orc, np.full(5, -0.25), [1j, 0, -1, 0.5 + 0.5j, 2], 1.0, "hermitian one pole", hermitian=True)
+
+
+def test_hermitian_real_z_is_the_real_problem(D):
+    """Real z: the same eigenvalues as the real front end with |z|, and V the real V with each row
+    multiplied by sign(z_j), bit for bit (the same kernels on the same |z|)."""
+    d, z, rho = W.reducible(600, 33, rho=0.7)
+    h = D.eig_hermitian(d, z.astype(complex), rho)
+    g = D.eig_general(d, np.abs(z), rho)
+    assert np.array_equal(h.lam.cpu().numpy(), g.lam.cpu().numpy())
+    Vh = h.V.cpu().numpy()
+    sgn = np.where(z < 0, -1.0, 1.0)
+    assert np.array_equal(Vh.real, sgn[:, None] * g.V.cpu().numpy())
+    assert np.all(Vh.imag == 0)
+
+
+def test_hermitian_large_properties(D):
+    """n = 4096 complex: V^H V = I, and A v = lambda v on sampled columns."""
+    import torch
+    d, z, rho = W.reducible(4096, 34, rho=1.3)
+    zc = _complex_z(z, 34)
+    print("[general] hermitian n=4096 properties", flush=True)
+    r = D.eig_hermitian(d, zc, rho)
+    lam = r.lam.cpu().numpy()
+    G = (r.V.conj().T @ r.V).cpu().numpy()
+    orth = np.max(np.abs(G - np.eye(4096)))
+    assert orth <= 1e-12, orth
+    idx = np.random.default_rng(34).choice(4096, 64, replace=False)
+    Vs = r.V[:, torch.as_tensor(idx, device=r.V.device)].cpu().numpy()
+    res = d[:, None] * Vs + rho * np.outer(zc, zc.conj() @ Vs) - Vs * lam[idx]
+    scale = max(np.max(np.abs(d)), abs(rho) * np.sum(np.abs(zc) ** 2))
+    assert np.max(np.abs(res)) <= 1e-13 * scale, np.max(np.abs(res))
+    print(f"[general] hermitian n=4096: orth {orth:.2e} residual {np.max(np.abs(res)) / scale:.2e}", flush=True)

@@ -415,3 +415,32 @@ def test_general_front_end_special_cases(orc):
     l2, V2 = orc.eig(d, z, rho)
     assert np.array_equal(l1, l2)
     assert np.array_equal(V1, V2[::-1, :])
+
+
+@pytest.mark.parametrize("seed,rho", [(0, 1.0), (1, -0.7), (2, 3.0)])
+def test_hermitian_against_dense(orc, seed, rho):
+    """Complex z (with repeated poles and a zero z_j): eigenvalues match a 60-digit dense Hermitian
+    eigensolver on D + rho z z^H formed from the complex entries; V is unitary with a small residual."""
+    rng = np.random.default_rng(40 + seed)
+    d, zr = _reducible(12, seed, reps=2, zeros=2)
+    z = zr * np.exp(1j * rng.uniform(0, 2 * np.pi, 12))
+    lam, V = orc.eig_hermitian(d, z, rho)
+    L = T.dense_values_hermitian(d, z, rho, dps=60)
+    A = np.diag(d).astype(complex) + rho * np.outer(z, z.conj())
+    scale = np.max(np.abs(np.linalg.eigvalsh(A)))
+    for k in range(12):
+        assert abs(lam[k] - float(L[k])) <= 1e-14 * scale
+    assert np.max(np.abs(V.conj().T @ V - np.eye(12))) <= 1e-14
+    assert np.max(np.abs(A @ V - V * lam)) <= 1e-14 * scale
+
+
+def test_hermitian_real_z_reduces_to_general(orc):
+    """With real z the phases are the signs of z_j: same eigenvalues as the real front end, and each
+    row of V multiplied by sign(z_j)."""
+    d, z = _reducible(20, 9)
+    lam_h, Vh = orc.eig_hermitian(d, z.astype(complex), 0.9)
+    lam_g, Vg = orc.eig_general(d, np.abs(z), 0.9)
+    assert np.array_equal(lam_h, lam_g)
+    sgn = np.where(z < 0, -1.0, 1.0)
+    assert np.array_equal(Vh, sgn[:, None] * Vg)
+    assert np.max(np.abs(Vh.imag)) == 0.0

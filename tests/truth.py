@@ -152,3 +152,17 @@ def dense_values(d, z, rho, dps=60):
                 A[r, c] = _mp(rho) * _mp(z[r]) * _mp(z[c]) + (_mp(d[r]) if r == c else 0)
         E = mp.eigsy(A, eigvals_only=True)
         return sorted([E[t] for t in range(n)], key=lambda x: -x)
+
+
+def dense_values_hermitian(d, z, rho, dps=60):
+    """Eigenvalues (descending) of the explicit Hermitian matrix D + rho z z^H (complex z) via
+    mp.eighe, formed from the complex entries directly (no use of |z|)."""
+    with mp.workdps(dps):
+        n = len(d)
+        A = mp.matrix(n, n)
+        zc = [mp.mpc(_mp(complex(x).real), _mp(complex(x).imag)) for x in z]
+        for r in range(n):
+            for c in range(n):
+                A[r, c] = _mp(rho) * zc[r] * mp.conj(zc[c]) + (_mp(d[r]) if r == c else 0)
+        E = mp.eighe(A, eigvals_only=True)
+        return sorted([mp.re(E[t]) for t in range(n)], key=lambda x: -x)
