@@ -265,3 +265,38 @@ def eig_hermitian(d, z, rho, vectors=True):
     if not vectors:
         return lam, None
     return lam, ph[:, None] * Vr
+
+
+def tridiag_eig(a, b):
+    """All eigenpairs of the symmetric tridiagonal T (diagonal a [n], off-diagonal b [n-1]) by
+    divide and conquer with rank-one merges, the application the paper gives for DPR1 problems
+    (Sec. 1): split at m = n // 2 with beta = b[m-1],
+        T = diag(T1 - beta e_m e_m^T, T2 - beta e_1 e_1^T) + beta u u^T,  u = e_m + e_{m+1},
+    solve the halves, and with T_h = Q_h Lambda_h Q_h^T merge through the DPR1 problem
+        D = diag(Lambda1, Lambda2),  z = Q^T u = [last row of Q1, first row of Q2],  rho = beta
+    (eig_general: unsorted poles, equal poles and zero z_j handled as in Sec. 1); the eigenvectors
+    of T are diag(Q1, Q2) V.  beta = 0 decouples the halves (every z_j treated as 0).
+    Returns (lam decreasing, Q with Q[:, k] = q_k)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = a.size
+    if n == 1:
+        return a.copy(), np.ones((1, 1))
+    m = n // 2
+    beta = float(b[m - 1])
+    a1 = a[:m].copy()
+    a1[-1] -= beta
+    a2 = a[m:].copy()
+    a2[0] -= beta
+    l1, Q1 = tridiag_eig(a1, b[:m - 1])
+    l2, Q2 = tridiag_eig(a2, b[m:])
+    d = np.concatenate([l1, l2])
+    z = np.concatenate([Q1[-1, :], Q2[0, :]])
+    if beta == 0.0:
+        lam, V = eig_general(d, np.zeros(n), 1.0)
+    else:
+        lam, V = eig_general(d, z, beta)
+    Q = np.zeros((n, n))
+    Q[:m, :] = Q1 @ V[:m, :]
+    Q[m:, :] = Q2 @ V[m:, :]
+    return lam, Q

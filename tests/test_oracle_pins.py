@@ -11,6 +11,7 @@ from fractions import Fraction
 
 import mpmath as mp
 import numpy as np
+import mpmath as T_mp
 import pytest
 
 import truth as T
@@ -444,3 +445,64 @@ def test_hermitian_real_z_reduces_to_general(orc):
     sgn = np.where(z < 0, -1.0, 1.0)
     assert np.array_equal(Vh, sgn[:, None] * Vg)
     assert np.max(np.abs(Vh.imag)) == 0.0
+
+
+def _tridiag_dense(a, b):
+    return np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+
+
+@pytest.mark.parametrize("n,seed", [(2, 0), (3, 1), (7, 2), (12, 3), (13, 4)])
+def test_tridiag_dc_against_dense(orc, n, seed):
+    """Divide and conquer through the front end: eigenvalues against a 60-digit dense symmetric
+    eigensolver on T, Q orthogonal, TQ = Q Lambda."""
+    rng = np.random.default_rng(70 + seed)
+    a, b = rng.standard_normal(n), rng.standard_normal(n - 1)
+    lam, Q = orc.tridiag_eig(a, b)
+    T = _tridiag_dense(a, b)
+    L = T_truth_eigs(T)
+    scale = np.max(np.abs(L))
+    assert np.max(np.abs(lam - L)) <= 1e-14 * scale
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-14 * n
+    assert np.max(np.abs(T @ Q - Q * lam)) <= 1e-14 * scale * n
+
+
+def T_truth_eigs(T):
+    n = T.shape[0]
+    with T_mp.workdps(60):
+        A = T_mp.matrix(n, n)
+        for r in range(n):
+            for c in range(n):
+                A[r, c] = T_mp.mpf(float(T[r, c]))
+        E = T_mp.eigsy(A, eigvals_only=True)
+        return np.array(sorted([float(E[t]) for t in range(n)], reverse=True))
+
+
+def test_tridiag_dc_closed_forms_and_splits(orc):
+    # 2x2: eigenvalues (a1 + a2)/2 +- sqrt(((a1 - a2)/2)^2 + b^2)
+    lam, Q = orc.tridiag_eig([1.0, -2.0], [0.5])
+    h, r = -0.5, np.hypot(1.5, 0.5)
+    assert abs(lam[0] - (h + r)) <= 4e-16 * 2 and abs(lam[1] - (h - r)) <= 4e-16 * 2
+    # a zero off-diagonal decouples: the spectrum is the union of the blocks'
+    a = np.array([3.0, 1.0, -1.0, 2.0, 0.5, -4.0])
+    b = np.array([0.7, -0.2, 0.0, 1.1, 0.3])
+    lam, Q = orc.tridiag_eig(a, b)
+    L = np.sort(np.concatenate([np.linalg.eigvalsh(_tridiag_dense(a[:3], b[:2])),
+                                np.linalg.eigvalsh(_tridiag_dense(a[3:], b[3:]))]))[::-1]
+    assert np.max(np.abs(lam - L)) <= 1e-14 * 4
+    assert np.all((Q[:3] == 0).all(0) | (Q[3:] == 0).all(0))   # each column lives in one block
+    # diagonal T: Q a permutation, lambda the sorted diagonal
+    lam, Q = orc.tridiag_eig([0.3, 2.0, -1.0, 2.0], [0.0, 0.0, 0.0])
+    assert list(lam) == [2.0, 2.0, 0.3, -1.0]
+    assert np.array_equal(np.abs(Q).sum(0), np.ones(4)) and np.array_equal(np.abs(Q).sum(1), np.ones(4))
+
+
+def test_tridiag_dc_wilkinson(orc):
+    """Wilkinson W21+: pairs of eigenvalues agreeing to many digits (close poles in the merges)."""
+    m = 10
+    a = np.abs(np.arange(-m, m + 1, dtype=float))
+    b = np.ones(2 * m)
+    lam, Q = orc.tridiag_eig(a, b)
+    T = _tridiag_dense(a, b)
+    L = T_truth_eigs(T)
+    assert np.max(np.abs(lam - L)) <= 1e-14 * np.max(np.abs(L))
+    assert np.max(np.abs(Q.T @ Q - np.eye(2 * m + 1))) <= 1e-13
