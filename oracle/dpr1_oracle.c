@@ -293,19 +293,33 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
    * (resp. min(b,x) - ...) so that b never cancels against the square root:
    * with a tiny zeta_i, |b| can exceed nu by fifteen orders of magnitude.
    * The final sum can still cancel (for k = 1 when nu << |x|), so a bound on
-   * its rounding error, 8 eps (|max(b,x)| + the quotient), is added. */
-  double wn2 = 0.0, xmax = -INFINITY, xmin = INFINITY;
+   * its rounding error, 8 eps (|max(b,x)| + the quotient), is added.
+   * Neither h^2 nor ||w||^2 is formed: with a tiny zeta_i, |b| and ||w|| can
+   * exceed 1e154 (a squared 1e184 overflows and would collapse the bound
+   * onto the pole), so the quotient is ||w|| (||w|| / (|h| + hypot(h, ||w||)))
+   * with ||w|| summed scaled by its largest entry. */
+  double wmax = 0.0, xmax = -INFINITY, xmin = INFINITY;
   for (int64_t j = 0; j < n; ++j) {
     if (j == i) continue;
-    wn2 += A.w[j] * A.w[j];
+    if (fabs(A.w[j]) > wmax) wmax = fabs(A.w[j]);
     if (A.xi[j] > xmax) xmax = A.xi[j];
     if (A.xi[j] < xmin) xmin = A.xi[j];
+  }
+  double wn = 0.0;
+  if (wmax > 0.0) {
+    double acc = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double q = A.w[j] / wmax;
+      acc += q * q;
+    }
+    wn = wmax * sqrt(acc);
   }
   const double grow = 1.0 + 0x1p-40;
   double L, U;
   if (side > 0) {
     double h = fabs(A.b - xmax) / 2;
-    double m = fmax(A.b, xmax), t = wn2 / (h + sqrt(h * h + wn2));
+    double m = fmax(A.b, xmax), t = wn > 0.0 ? wn * (wn / (h + hypot(h, wn))) : 0.0;
     U = (m + t) * grow + 8 * DBL_EPSILON * (fabs(m) + t);
     if (k == 0) {
       /* lambda_1 lies in [d_1 + rho*zeta_1^2, d_1 + rho*||z||^2]. */
@@ -319,7 +333,7 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
     }
   } else {
     double h = fabs(A.b - xmin) / 2;
-    double m = fmin(A.b, xmin), t = wn2 / (h + sqrt(h * h + wn2));
+    double m = fmin(A.b, xmin), t = wn > 0.0 ? wn * (wn / (h + hypot(h, wn))) : 0.0;
     L = (m - t) * grow - 8 * DBL_EPSILON * (fabs(m) + t);
     U = xmin;
   }

@@ -506,3 +506,17 @@ def test_tridiag_dc_wilkinson(orc):
     L = T_truth_eigs(T)
     assert np.max(np.abs(lam - L)) <= 1e-14 * np.max(np.abs(L))
     assert np.max(np.abs(Q.T @ Q - np.eye(2 * m + 1))) <= 1e-13
+
+
+def test_bracket_with_huge_tip(orc):
+    """Both poles around an eigenvalue carry a tiny zeta (1e-100, 1e-120): the eigenvalue (~0.68)
+    sits far from either, so the arrowhead inverse at the chosen pole has |b| ~ 1e200-1e240 and a
+    squared half-width would overflow (the bisection interval must still contain nu).  Against a
+    60-digit dense solver."""
+    d = np.array([2.0, 1.0, 0.5, 0.0, -1.0])
+    z = np.array([1.0, 1e-100, 1e-120, 1.0, 0.7])
+    for rho in (1.0, -1.0):
+        lam, V = orc.eig(d, z, rho)
+        L = np.array([float(x) for x in T.dense_values(d, z, rho, dps=60)])
+        assert np.max(np.abs(lam - L) / np.abs(L)) <= 4e-16, (rho, lam, L)
+        assert np.max(np.abs(V.T @ V - np.eye(5))) <= 1e-15
