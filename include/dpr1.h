@@ -276,6 +276,31 @@ int dpr1_eig_hermitian(const double* d, const double* z, double rho, int64_t n, 
                        double* V, int64_t ldv, int32_t* info, const dpr1_opts* opts, void* work,
                        size_t work_bytes, void* stream);
 
+/* Symmetric tridiagonal eigensolver by divide and conquer whose merges are
+ * DPR1 problems (the application named in Sec. 1).  T has diagonal a [n] and
+ * off-diagonal b [n-1] (device).  A block is split at m = size/2 with
+ * beta = b there: T = diag(T1 - beta e_m e_m^T, T2 - beta e_1 e_1^T)
+ * + beta u u^T, u = e_m + e_{m+1}; the halves are solved recursively down to
+ * 1 x 1, and each merge is the DPR1 problem D = diag(Lambda1, Lambda2),
+ * z = [last row of Q1, first row of Q2], rho = beta, reduced as by
+ * dpr1_eig_general (beta = 0 decouples the halves), solved for all merges
+ * of one depth in one batched launch, and followed by Q = diag(Q1, Q2) V.
+ *   lambda  [n] output, decreasing
+ *   Q       [ldq*n] output (required: the merges need it), column k = q_k
+ *   info    [1] device int32: 0, DPR1_INFO_NONFINITE, or a code of a merge
+ *   opts    options of the merges' DPR1 solves (NULL = defaults; an invalid
+ *           waves_per_simd is argument -8)
+ *   work, work_bytes  >= dpr1_tridiag_workspace_size(n): about 16 n^2 bytes
+ *           (a second Q buffer and the merges' V) plus O(n)
+ * 1 <= n <= 65536.  Synchronises the host with `stream` a few times per
+ * depth of the split tree (the merges are reduced on the host).  Returns 0,
+ * -p for an invalid argument p (-10 also when the workspace is too small),
+ * or DPR1_EHIP.                                                             */
+size_t dpr1_tridiag_workspace_size(int64_t n);
+int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda, double* Q,
+                     int64_t ldq, int32_t* info, const dpr1_opts* opts, void* work,
+                     size_t work_bytes, void* stream);
+
 /* Text for a return code or an info code.                                   */
 const char* dpr1_strerror(int code);
 

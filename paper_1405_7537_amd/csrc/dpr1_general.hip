@@ -30,11 +30,14 @@
 #include <vector>
 
 #include "../../include/dpr1.h"
+#include "reduce.h"
 
 namespace dpr1 {
 namespace gen {
 
-enum : int32_t { COL_REDUCED = 0, COL_UNIT = 1, COL_REFLECT = 2 };
+using fe::COL_REDUCED;
+using fe::COL_REFLECT;
+using fe::COL_UNIT;
 
 // Per original row i: rgrp its group id, rpos its position in the group, ru
 // the reflection vector's component there (0 for groups without reflection).
@@ -157,44 +160,6 @@ __global__ void __launch_bounds__(ASM_T) k_assemble(AsmArgs a) {
   }
 }
 
-// Stable sort of the poles in decreasing order: order[s] = the row with the
-// s-th largest d (equal values keep their row order, -0 and +0 are equal).
-// LSD radix sort on order-preserving 64-bit keys, 11 bits a pass; a pass
-// whose digit is the same for every key is skipped.
-static void sort_decreasing(const std::vector<double>& d, std::vector<int64_t>& order) {
-  const int64_t n = (int64_t)d.size();
-  std::vector<uint64_t> k(n), k2(n);
-  std::vector<int64_t> o2(n);
-  order.resize(n);
-  for (int64_t j = 0; j < n; ++j) {
-    const double x = d[j] == 0.0 ? 0.0 : d[j];
-    uint64_t b;
-    memcpy(&b, &x, 8);
-    b = (b >> 63) ? ~b : (b | (uint64_t(1) << 63));  // increasing with x
-    k[j] = ~b;                                        // decreasing with x
-    order[j] = j;
-  }
-  std::vector<int64_t> cnt(2048);
-  for (int sh = 0; sh < 64; sh += 11) {
-    std::fill(cnt.begin(), cnt.end(), 0);
-    for (int64_t j = 0; j < n; ++j) ++cnt[(k[j] >> sh) & 2047];
-    if (cnt[(k[0] >> sh) & 2047] == n) continue;
-    int64_t acc = 0;
-    for (int b = 0; b < 2048; ++b) {
-      const int64_t c = cnt[b];
-      cnt[b] = acc;
-      acc += c;
-    }
-    for (int64_t j = 0; j < n; ++j) {
-      const int64_t at = cnt[(k[j] >> sh) & 2047]++;
-      k2[at] = k[j];
-      o2[at] = order[j];
-    }
-    k.swap(k2);
-    order.swap(o2);
-  }
-}
-
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct GLayout {
@@ -232,6 +197,7 @@ static GLayout glayout(int64_t n) {
 }  // namespace dpr1
 
 using namespace dpr1::gen;
+namespace fe = dpr1::fe;
 
 #define GCHECK(x)                            \
   do {                                       \
@@ -279,61 +245,12 @@ static int front_end(const double* d, const double* zdev, const std::vector<doub
                      const std::vector<double>& hz, const double* ph, double rho, int64_t n, double* lambda,
                      double* V, int64_t ldv, int32_t* info, const dpr1_opts* opts, char* w, const GLayout& L,
                      hipStream_t st, void* stream) {
-  // sorted position s -> original row order[s]
-  std::vector<int64_t> order;
-  sort_decreasing(hd, order);
   std::vector<double> rd, rz;
-  std::vector<int32_t> rgrp(n, -1), rpos(n, 0);
-  std::vector<double> ru(n, 0.0);
-  struct Col {
-    double val;
-    int32_t kind, idx, t;
-    double ub;
-  };
-  std::vector<Col> cols;
+  std::vector<int32_t> rgrp(n), rpos(n);
+  std::vector<double> ru(n);
+  std::vector<fe::Col> cols;
   cols.reserve(n);
-  std::vector<double> u;
-  int32_t ngrp = 0;
-  for (int64_t s = 0; s < n;) {
-    int64_t e = s + 1;
-    while (e < n && hd[order[e]] == hd[order[s]]) ++e;
-    const double dv = hd[order[s]];
-    // ||w|| scaled by the largest |w_t|, so that no square overflows
-    double big = 0.0, nw = 0.0;
-    for (int64_t t = s; t < e; ++t) big = std::max(big, std::fabs(hz[order[t]]));
-    if (big > 0.0) {
-      double acc = 0.0;
-      for (int64_t t = s; t < e; ++t) {
-        const double q = hz[order[t]] / big;
-        acc += q * q;
-      }
-      nw = big * std::sqrt(acc);
-    }
-    const int32_t g = ngrp++;
-    for (int64_t t = s; t < e; ++t) {
-      rgrp[order[t]] = g;
-      rpos[order[t]] = (int32_t)(t - s);
-    }
-    if (nw == 0.0) {
-      for (int64_t t = s; t < e; ++t) cols.push_back({dv, COL_UNIT, (int32_t)order[t], 0, 0.0});
-    } else if (e - s == 1) {
-      rd.push_back(dv);
-      rz.push_back(hz[order[s]]);
-    } else {
-      rd.push_back(dv);
-      rz.push_back(nw);
-      // u = w/||w|| + sign(u_first) e_first, H = I - beta u u^T, beta = 2/(u^T u)
-      u.resize(e - s);
-      for (int64_t t = s; t < e; ++t) u[t - s] = hz[order[t]] / nw;
-      u[0] += u[0] >= 0.0 ? 1.0 : -1.0;
-      double uu = 0.0;
-      for (double x : u) uu += x * x;
-      const double beta = 2.0 / uu;
-      for (int64_t t = s; t < e; ++t) ru[order[t]] = u[t - s];
-      for (int64_t t = 1; t < e - s; ++t) cols.push_back({dv, COL_REFLECT, g, (int32_t)t, beta * u[t]});
-    }
-    s = e;
-  }
+  fe::reduce(hd.data(), hz.data(), n, false, rd, rz, rgrp.data(), rpos.data(), ru.data(), cols);
   const int64_t m = (int64_t)rd.size();
 
   // the reduced problem on the GPU: eigenvalues and the shifted representation
@@ -364,21 +281,15 @@ static int front_end(const double* d, const double* zdev, const std::vector<doub
     GCHECK(hipStreamSynchronize(st));
     if (hinf != DPR1_INFO_OK) return set_info(info, hinf, st);
   }
-  // both lists are decreasing: merge them (deflated and reflected columns
-  // first among equal values)
   {
-    std::vector<Col> red(m);
-    for (int64_t k = 0; k < m; ++k) red[k] = {lamr[k], COL_REDUCED, (int32_t)k, 0, 0.0};
-    std::vector<Col> all(n);
-    std::merge(cols.begin(), cols.end(), red.begin(), red.end(), all.begin(),
-               [](const Col& a, const Col& b) { return a.val > b.val; });
+    std::vector<fe::Col> all;
+    fe::merge_cols(cols, lamr.data(), m, all);
     cols.swap(all);
   }
-
   std::vector<double> lam(n), csig(n, 0.0), cmu(n, 0.0), cic(n, 0.0), cub(n, 0.0);
   std::vector<int32_t> ckind(n), cidx(n), ct(n);
   for (int64_t c = 0; c < n; ++c) {
-    const Col& q = cols[c];
+    const fe::Col& q = cols[c];
     lam[c] = q.val;
     ckind[c] = q.kind;
     cidx[c] = q.idx;

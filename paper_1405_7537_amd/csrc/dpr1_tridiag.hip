@@ -1,0 +1,600 @@
+// Divide-and-conquer eigensolver for a real symmetric tridiagonal matrix T,
+// the application of DPR1 eigenproblems named in Sec. 1 of the paper: every
+// merge of two halves is a DPR1 problem.
+//
+// Split a block at m = size/2 with beta = its off-diagonal there:
+//   T = diag(T1 - beta e_m e_m^T, T2 - beta e_1 e_1^T) + beta u u^T,
+//   u = e_m + e_{m+1}.
+// With T_h = Q_h Lambda_h Q_h^T the merged block is
+//   Q (diag(Lambda1, Lambda2) + beta z z^T) Q^T, Q = diag(Q1, Q2),
+//   z = Q^T u = [last row of Q1, first row of Q2],
+// and its eigenvectors are Q V for the DPR1 eigenvectors V.  The split tree
+// goes down to 1 x 1 leaves; all merges of one depth are done together:
+//   1. k_gather_z reads z of every merge from the current Q buffer;
+//   2. the host reduces each merge as in Sec. 1 (unsorted poles, equal poles,
+//      zero z_j: reduce.h), a z_j below 2^-500 max|z| counting as zero;
+//   3. one batched launch of the DPR1 solver (dpr1_eig_batched, eigenvalues
+//      and the shifted representation only) solves all reduced problems;
+//   4. k_tri_assemble writes every merge's V (eq. (eigenvecAi) on the merge's
+//      own poles and z, unit and reflection columns);
+//   5. k_dgemm forms diag(Q1, Q2) V for every merge into the other Q buffer
+//      (two products per merge, one batched launch over 64 x 64 tiles).
+// The two Q buffers alternate between depths so that the root's product
+// lands in the caller's Q.  A block is written only by its own merge and read
+// only by its parent's, and a leaf's 1 x 1 block (= 1) is set in both buffers
+// at the start, so no buffer is ever cleared.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "../../include/dpr1.h"
+#include "reduce.h"
+
+namespace dpr1 {
+namespace tri {
+
+using fe::COL_REDUCED;
+using fe::COL_REFLECT;
+using fe::COL_UNIT;
+
+struct Node {
+  int64_t start, size, m;
+  int depth;
+};
+
+static void build_tree(int64_t start, int64_t size, int depth, std::vector<Node>& out, int& maxd) {
+  if (size < 2) return;
+  const int64_t m = size / 2;
+  out.push_back({start, size, m, depth});
+  maxd = std::max(maxd, depth);
+  build_tree(start, m, depth + 1, out, maxd);
+  build_tree(start + m, size - m, depth + 1, out, maxd);
+}
+
+// The diagonal of every leaf after the splits above it: each split subtracts
+// beta from the two diagonal entries beside it, the split nearer the root
+// first (the order of the recursion).
+static void modify_diag(std::vector<double>& a, const std::vector<double>& b, int64_t start, int64_t size) {
+  if (size < 2) return;
+  const int64_t m = size / 2;
+  const double beta = b[start + m - 1];
+  a[start + m - 1] -= beta;
+  a[start + m] -= beta;
+  modify_diag(a, b, start, m);
+  modify_diag(a, b, start + m, size - m);
+}
+
+// --------------------------------------------------------------- kernels
+__global__ void k_diag_one(double* Q, int64_t ld, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Q[i + i * ld] = 1.0;
+}
+
+// z_i = Q[src_i, i] (the last row of the left child's block or the first row
+// of the right child's), 0 for a row not merged at this depth.
+__global__ void k_gather_z(const double* __restrict__ Q, int64_t ld, const int32_t* __restrict__ src, int64_t n,
+                           double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = src[i];
+  z[i] = r >= 0 ? Q[r + i * ld] : 0.0;
+}
+
+struct ANode {
+  int64_t start, size, voff;
+};
+
+// Arrays indexed by the merged block's global row/column start + local index.
+struct TArgs {
+  const double* d;  // the merge's poles (its children's eigenvalues), unsorted
+  const double* z;
+  const int32_t* rgrp;
+  const int32_t* rpos;
+  const double* ru;
+  const int32_t* ckind;
+  const int32_t* cidx;
+  const int32_t* ct;
+  const double* csig;
+  const double* cmu;
+  const double* cic;
+  const double* cub;
+  double* V;  // merge p's size x size V at voff (ld = size)
+};
+
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
+constexpr int TA_T = 256, TA_R = 4, TA_CB = 16;
+
+// One block = (merge, 16 columns, 1024 rows), as the front end's assembly.
+__global__ void __launch_bounds__(TA_T) k_tri_assemble(const ANode* __restrict__ nodes, const int4* __restrict__ tab,
+                                                       TArgs a) {
+  __shared__ int s_kind[TA_CB], s_idx[TA_CB], s_t[TA_CB];
+  __shared__ double s_sig[TA_CB], s_mu[TA_CB], s_ic[TA_CB], s_ub[TA_CB];
+  const int4 e = tab[blockIdx.x];
+  const ANode nd = nodes[e.x];
+  const int64_t n = nd.size, o = nd.start;
+  const int64_t c0 = (int64_t)e.y * TA_CB;
+  const int64_t r0 = (int64_t)e.z * (TA_T * TA_R);
+  const int nc = (int)min((int64_t)TA_CB, n - c0);
+  if (threadIdx.x < nc) {
+    const int64_t c = o + c0 + threadIdx.x;
+    s_kind[threadIdx.x] = a.ckind[c];
+    s_idx[threadIdx.x] = a.cidx[c];
+    s_t[threadIdx.x] = a.ct[c];
+    s_sig[threadIdx.x] = a.csig[c];
+    s_mu[threadIdx.x] = a.cmu[c];
+    s_ic[threadIdx.x] = a.cic[c];
+    s_ub[threadIdx.x] = a.cub[c];
+  }
+  double di[TA_R], zi[TA_R], ui[TA_R];
+  int gi[TA_R], pi[TA_R];
+#pragma unroll
+  for (int j = 0; j < TA_R; ++j) {
+    const int64_t i = r0 + threadIdx.x + j * TA_T;
+    const bool ok = i < n;
+    di[j] = ok ? a.d[o + i] : 0.0;
+    zi[j] = ok ? a.z[o + i] : 0.0;
+    ui[j] = ok ? a.ru[o + i] : 0.0;
+    gi[j] = ok ? a.rgrp[o + i] : -1;
+    pi[j] = ok ? a.rpos[o + i] : -1;
+  }
+  __syncthreads();
+  double* V = a.V + nd.voff;
+  for (int cc = 0; cc < nc; ++cc) {
+    const int kind = s_kind[cc];
+    double v[TA_R];
+    if (kind == COL_REDUCED) {
+      const double m = s_mu[cc], sg = s_sig[cc], ic = s_ic[cc];
+#pragma unroll
+      for (int j = 0; j < TA_R; ++j) {
+        const double den = (di[j] - sg) - m;
+        const double rc = rcp_nr(den);
+        double q = m * rc;
+        q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);
+        v[j] = zi[j] != 0.0 ? (zi[j] * q) * ic : 0.0;
+      }
+    } else if (kind == COL_UNIT) {
+      const int64_t at = s_idx[cc];
+#pragma unroll
+      for (int j = 0; j < TA_R; ++j) v[j] = (r0 + threadIdx.x + j * TA_T == at) ? 1.0 : 0.0;
+    } else {
+      const int g = s_idx[cc], t = s_t[cc];
+      const double ub = s_ub[cc];
+#pragma unroll
+      for (int j = 0; j < TA_R; ++j) v[j] = gi[j] == g ? (pi[j] == t ? 1.0 : 0.0) - ub * ui[j] : 0.0;
+    }
+    double* col = V + (c0 + cc) * n + r0 + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < TA_R; ++j)
+      if (r0 + threadIdx.x + j * TA_T < n) col[j * TA_T] = v[j];
+  }
+}
+
+// C (M x N, ldc) = A (M x K, lda) B (K x N, ldb), column-major, FP64.
+struct GDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t lda, ldb, ldc;
+  int32_t M, N, K, pad;
+};
+
+constexpr int GT = 64, GKS = 16;
+
+// One 256-thread block per 64 x 64 tile of C (tile table entry: descriptor,
+// tile row, tile column); each thread accumulates a 4 x 4 sub-tile over K in
+// steps of 16 staged in LDS.  16 consecutive threads own consecutive 4-row
+// pieces of one column (a 64-row segment), so the stores of C are coalesced.
+__global__ void __launch_bounds__(256) k_dgemm(const GDesc* __restrict__ desc, const int4* __restrict__ tiles) {
+  __shared__ double As[GKS][GT + 1];
+  __shared__ double Bs[GKS][GT + 1];
+  const int4 t = tiles[blockIdx.x];
+  const GDesc g = desc[t.x];
+  const int r0 = t.y * GT, c0 = t.z * GT;
+  const int tid = threadIdx.x;
+  const int tr = (tid % 16) * 4, tc = (tid / 16) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < g.K; k0 += GKS) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = tid % 64, k = tid / 64 + 4 * j;
+      const int gr = r0 + r, gk = k0 + k;
+      As[k][r] = (gr < g.M && gk < g.K) ? g.A[gr + (int64_t)gk * g.lda] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = tid % 16, c = tid / 16 + 16 * j;
+      const int gk = k0 + k, gc = c0 + c;
+      Bs[k][c] = (gk < g.K && gc < g.N) ? g.B[gk + (int64_t)gc * g.ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GKS; ++k) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        av[i] = As[k][tr + i];
+        bv[i] = Bs[k][tc + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int gc = c0 + tc + j;
+    if (gc >= g.N) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gr = r0 + tr + i;
+      if (gr < g.M) g.C[gr + (int64_t)gc * g.ldc] = acc[i][j];
+    }
+  }
+}
+
+// ------------------------------------------------------------ workspace
+static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct TLayout {
+  size_t Qw, Vw, zl, dl, src, rd, rz, lamr, mur, xnr, sidx, infop, rhop, offsp, rgrp, rpos, ru, ckind, cidx, ct,
+      csig, cmu, cic, cub, anodes, atab, gdesc, gtab, solver, total;
+  int64_t maxV, maxAsm, maxTiles, maxNodes;
+  size_t solver_bytes;
+};
+
+static TLayout tlayout(int64_t n, const std::vector<Node>& nodes, int maxd) {
+  TLayout L;
+  L.maxV = 0;
+  L.maxAsm = 0;
+  L.maxTiles = 0;
+  L.maxNodes = 0;
+  L.solver_bytes = 0;
+  std::vector<int64_t> offs;
+  for (int D = maxd; D >= 0; --D) {
+    int64_t v = 0, as = 0, ti = 0, cnt = 0;
+    offs.assign(1, 0);
+    for (const Node& nd : nodes) {
+      if (nd.depth != D) continue;
+      ++cnt;
+      v += nd.size * nd.size;
+      as += cdiv(nd.size, TA_CB) * cdiv(nd.size, TA_T * TA_R);
+      ti += (cdiv(nd.m, GT) + cdiv(nd.size - nd.m, GT)) * cdiv(nd.size, GT);
+      offs.push_back(offs.back() + nd.size);
+    }
+    if (!cnt) continue;
+    L.maxV = std::max(L.maxV, v);
+    L.maxAsm = std::max(L.maxAsm, as);
+    L.maxTiles = std::max(L.maxTiles, ti);
+    L.maxNodes = std::max(L.maxNodes, cnt);
+    // the reduced problems of a depth are no more and no larger than its merges
+    L.solver_bytes = std::max(L.solver_bytes, dpr1_batched_workspace_size(cnt, offs.data()));
+  }
+  const int64_t P = std::max<int64_t>(L.maxNodes, 1);
+  size_t o = 0;
+  L.Qw = o; o = al(o + 8 * (size_t)n * n);
+  L.Vw = o; o = al(o + 8 * (size_t)L.maxV);
+  L.zl = o; o = al(o + 8 * n);
+  L.dl = o; o = al(o + 8 * n);
+  L.src = o; o = al(o + 4 * n);
+  L.rd = o; o = al(o + 8 * n);
+  L.rz = o; o = al(o + 8 * n);
+  L.lamr = o; o = al(o + 8 * n);
+  L.mur = o; o = al(o + 8 * n);
+  L.xnr = o; o = al(o + 8 * n);
+  L.sidx = o; o = al(o + 4 * n);
+  L.infop = o; o = al(o + 4 * P);
+  L.rhop = o; o = al(o + 8 * P);
+  L.offsp = o; o = al(o + 8 * (P + 1));
+  L.rgrp = o; o = al(o + 4 * n);
+  L.rpos = o; o = al(o + 4 * n);
+  L.ru = o; o = al(o + 8 * n);
+  L.ckind = o; o = al(o + 4 * n);
+  L.cidx = o; o = al(o + 4 * n);
+  L.ct = o; o = al(o + 4 * n);
+  L.csig = o; o = al(o + 8 * n);
+  L.cmu = o; o = al(o + 8 * n);
+  L.cic = o; o = al(o + 8 * n);
+  L.cub = o; o = al(o + 8 * n);
+  L.anodes = o; o = al(o + sizeof(ANode) * P);
+  L.atab = o; o = al(o + sizeof(int4) * std::max<int64_t>(L.maxAsm, 1));
+  L.gdesc = o; o = al(o + sizeof(GDesc) * 2 * P);
+  L.gtab = o; o = al(o + sizeof(int4) * std::max<int64_t>(L.maxTiles, 1));
+  L.solver = o; o = al(o + L.solver_bytes);
+  L.total = o;
+  return L;
+}
+
+}  // namespace tri
+}  // namespace dpr1
+
+using namespace dpr1::tri;
+namespace fe = dpr1::fe;
+
+#define TCHECK(x)                            \
+  do {                                       \
+    if ((x) != hipSuccess) return DPR1_EHIP; \
+  } while (0)
+
+template <typename T>
+static hipError_t h2d(void* dst, const std::vector<T>& src, size_t count, hipStream_t st) {
+  return count ? hipMemcpyAsync(dst, src.data(), sizeof(T) * count, hipMemcpyHostToDevice, st) : hipSuccess;
+}
+
+static int tri_set_info(int32_t* info, int32_t code, hipStream_t st) {
+  TCHECK(hipMemcpyAsync(info, &code, 4, hipMemcpyHostToDevice, st));
+  TCHECK(hipStreamSynchronize(st));
+  return DPR1_OK;
+}
+
+extern "C" {
+
+size_t dpr1_tridiag_workspace_size(int64_t n) {
+  if (n < 1 || n > 65536) return 0;
+  std::vector<Node> nodes;
+  int maxd = 0;
+  build_tree(0, n, 0, nodes, maxd);
+  return tlayout(n, nodes, maxd).total;
+}
+
+int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda, double* Q, int64_t ldq,
+                     int32_t* info, const dpr1_opts* opts, void* work, size_t work_bytes, void* stream) {
+  if (!a) return -1;
+  if (!b && n > 1) return -2;
+  if (n < 1 || n > 65536) return -3;
+  if (!lambda) return -4;
+  if (!Q) return -5;
+  if (ldq < n) return -6;
+  if (!info) return -7;
+  if (opts && opts->waves_per_simd != 0 && opts->waves_per_simd != 4 && opts->waves_per_simd != 6 &&
+      opts->waves_per_simd != 8)
+    return -8;
+  if (!work) return -9;
+  std::vector<Node> nodes;
+  int maxd = 0;
+  build_tree(0, n, 0, nodes, maxd);
+  const TLayout L = tlayout(n, nodes, maxd);
+  if (work_bytes < L.total) return -10;
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)work;
+
+  std::vector<double> ha(n), hb(std::max<int64_t>(n - 1, 0));
+  TCHECK(hipMemcpyAsync(ha.data(), a, 8 * n, hipMemcpyDeviceToHost, st));
+  if (n > 1) TCHECK(hipMemcpyAsync(hb.data(), b, 8 * (n - 1), hipMemcpyDeviceToHost, st));
+  TCHECK(hipStreamSynchronize(st));
+  for (double x : ha)
+    if (!std::isfinite(x)) return tri_set_info(info, DPR1_INFO_NONFINITE, st);
+  for (double x : hb)
+    if (!std::isfinite(x)) return tri_set_info(info, DPR1_INFO_NONFINITE, st);
+
+  // leaves: the diagonal after every split's modification, Q = 1 in both buffers
+  std::vector<double> hlam = ha;
+  modify_diag(hlam, hb, 0, n);
+  TCHECK(hipMemcpyAsync(lambda, hlam.data(), 8 * n, hipMemcpyHostToDevice, st));
+  double* Qw = (double*)(w + L.Qw);
+  const unsigned g1 = (unsigned)cdiv(n, 256);
+  hipLaunchKernelGGL(k_diag_one, dim3(g1), dim3(256), 0, st, Q, ldq, n);
+  hipLaunchKernelGGL(k_diag_one, dim3(g1), dim3(256), 0, st, Qw, n, n);
+  TCHECK(hipGetLastError());
+
+  double* zl = (double*)(w + L.zl);
+  double* dl = (double*)(w + L.dl);
+  int32_t* src = (int32_t*)(w + L.src);
+  TArgs ta;
+  ta.d = dl;
+  ta.z = zl;
+  ta.rgrp = (int32_t*)(w + L.rgrp);
+  ta.rpos = (int32_t*)(w + L.rpos);
+  ta.ru = (double*)(w + L.ru);
+  ta.ckind = (int32_t*)(w + L.ckind);
+  ta.cidx = (int32_t*)(w + L.cidx);
+  ta.ct = (int32_t*)(w + L.ct);
+  ta.csig = (double*)(w + L.csig);
+  ta.cmu = (double*)(w + L.cmu);
+  ta.cic = (double*)(w + L.cic);
+  ta.cub = (double*)(w + L.cub);
+  ta.V = (double*)(w + L.Vw);
+
+  // host staging, reused by every depth (each is rewritten only after the
+  // stream has been synchronised at the start of the next depth)
+  std::vector<int32_t> hsrc(n), hgrp(n, 0), hpos(n, 0), hkind(n, 0), hidx(n, 0), hct(n, 0);
+  std::vector<double> hz(n), hru(n, 0.0), hsig(n, 0.0), hmu(n, 0.0), hic(n, 0.0), hub(n, 0.0);
+  std::vector<double> rd, rz, lamr, mur, xnr, rhop;
+  std::vector<int32_t> sidx, infop;
+  std::vector<int64_t> offs;
+  std::vector<ANode> anodes;
+  std::vector<int4> atab, gtab;
+  std::vector<GDesc> gdesc;
+  std::vector<fe::Col> cols, all;
+  std::vector<int64_t> roff, rcnt;  // per merge: offset and size of its reduced problem
+  std::vector<std::vector<fe::Col>> mcols;
+  std::vector<double> hnew(n);
+  dpr1_plan plan;
+
+  for (int D = maxd; D >= 0; --D) {
+    std::vector<const Node*> lv;
+    for (const Node& nd : nodes)
+      if (nd.depth == D) lv.push_back(&nd);
+    if (lv.empty()) continue;
+    // buffers: the root (D = 0) writes the caller's Q
+    double* Qn = (D % 2 == 0) ? Q : Qw;
+    const int64_t ldn = (D % 2 == 0) ? ldq : n;
+    double* Qc = (D % 2 == 0) ? Qw : Q;
+    const int64_t ldc = (D % 2 == 0) ? n : ldq;
+
+    // 1. z of every merge
+    std::fill(hsrc.begin(), hsrc.end(), -1);
+    for (const Node* nd : lv)
+      for (int64_t i = nd->start; i < nd->start + nd->size; ++i)
+        hsrc[i] = (int32_t)(i < nd->start + nd->m ? nd->start + nd->m - 1 : nd->start + nd->m);
+    TCHECK(h2d(src, hsrc, n, st));
+    hipLaunchKernelGGL(k_gather_z, dim3(g1), dim3(256), 0, st, Qc, ldc, src, n, zl);
+    TCHECK(hipGetLastError());
+    TCHECK(hipMemcpyAsync(hz.data(), zl, 8 * n, hipMemcpyDeviceToHost, st));
+    TCHECK(hipStreamSynchronize(st));
+
+    // 2. reduce each merge (hlam holds the current eigenvalues of every block)
+    rd.clear();
+    rz.clear();
+    rhop.clear();
+    offs.assign(1, 0);
+    roff.assign(lv.size(), 0);
+    rcnt.assign(lv.size(), 0);
+    mcols.resize(lv.size());
+    for (size_t p = 0; p < lv.size(); ++p) {
+      const Node& nd = *lv[p];
+      const double beta = hb[nd.start + nd.m - 1];
+      const size_t before = rd.size();
+      // a component below 2^-500 of the largest is taken as 0: its square
+      // (and the eigenvalue's distance to its pole, about beta z_j^2) would
+      // underflow, and it lies far below the absolute accuracy of the
+      // children's eigenvectors it comes from
+      double zmax = 0.0;
+      for (int64_t i = nd.start; i < nd.start + nd.size; ++i) zmax = std::max(zmax, std::fabs(hz[i]));
+      const double ztiny = std::ldexp(zmax, -500);
+      for (int64_t i = nd.start; i < nd.start + nd.size; ++i)
+        if (std::fabs(hz[i]) < ztiny) hz[i] = 0.0;
+      mcols[p].clear();
+      fe::reduce(hlam.data() + nd.start, hz.data() + nd.start, nd.size, beta == 0.0, rd, rz,
+                 hgrp.data() + nd.start, hpos.data() + nd.start, hru.data() + nd.start, mcols[p]);
+      roff[p] = (int64_t)before;
+      rcnt[p] = (int64_t)(rd.size() - before);
+      if (rcnt[p] > 0) {
+        offs.push_back(offs.back() + rcnt[p]);
+        rhop.push_back(beta);
+      }
+    }
+    const int64_t nprob = (int64_t)rhop.size();
+    const int64_t mtot = (int64_t)rd.size();
+
+    // 3. one batched solve of the reduced problems
+    lamr.resize(mtot);
+    mur.resize(mtot);
+    xnr.resize(mtot);
+    sidx.resize(mtot);
+    if (nprob > 0) {
+      infop.assign(nprob, 0);
+      const int prc = dpr1_batched_plan(nprob, offs.data(), opts, &plan, w + L.solver, L.solver_bytes, stream);
+      if (prc != DPR1_OK) return prc == DPR1_EHIP ? DPR1_EHIP : -10;
+      double* drd = (double*)(w + L.rd);
+      double* drz = (double*)(w + L.rz);
+      double* dlr = (double*)(w + L.lamr);
+      double* dmu = (double*)(w + L.mur);
+      double* dxn = (double*)(w + L.xnr);
+      int32_t* dsi = (int32_t*)(w + L.sidx);
+      int32_t* dinf = (int32_t*)(w + L.infop);
+      double* drho = (double*)(w + L.rhop);
+      int64_t* doffs = (int64_t*)(w + L.offsp);
+      TCHECK(h2d(drd, rd, mtot, st));
+      TCHECK(h2d(drz, rz, mtot, st));
+      TCHECK(h2d(drho, rhop, nprob, st));
+      TCHECK(h2d(doffs, offs, nprob + 1, st));
+      const int rc = dpr1_eig_batched(&plan, doffs, drd, drz, drho, dlr, nullptr, nullptr, dsi, dmu, dxn, dinf,
+                                      nullptr, w + L.solver, L.solver_bytes, stream);
+      if (rc != DPR1_OK) return rc;
+      TCHECK(hipMemcpyAsync(lamr.data(), dlr, 8 * mtot, hipMemcpyDeviceToHost, st));
+      TCHECK(hipMemcpyAsync(mur.data(), dmu, 8 * mtot, hipMemcpyDeviceToHost, st));
+      TCHECK(hipMemcpyAsync(xnr.data(), dxn, 8 * mtot, hipMemcpyDeviceToHost, st));
+      TCHECK(hipMemcpyAsync(sidx.data(), dsi, 4 * mtot, hipMemcpyDeviceToHost, st));
+      TCHECK(hipMemcpyAsync(infop.data(), dinf, 4 * nprob, hipMemcpyDeviceToHost, st));
+      TCHECK(hipStreamSynchronize(st));
+      for (int32_t x : infop)
+        if (x != DPR1_INFO_OK) return tri_set_info(info, x, st);
+    }
+
+    // 4. columns of every merge, the new eigenvalues, the assembly and GEMM tables
+    TCHECK(hipMemcpyAsync(dl, hlam.data(), 8 * n, hipMemcpyHostToDevice, st));  // the merges' poles
+    TCHECK(hipMemcpyAsync(zl, hz.data(), 8 * n, hipMemcpyHostToDevice, st));    // z as reduced
+    anodes.clear();
+    atab.clear();
+    gdesc.clear();
+    gtab.clear();
+    int64_t voff = 0;
+    hnew = hlam;
+    for (size_t p = 0; p < lv.size(); ++p) {
+      const Node& nd = *lv[p];
+      const int64_t o = nd.start, s = nd.size;
+      fe::merge_cols(mcols[p], lamr.data() + roff[p], rcnt[p], all);
+      for (int64_t c = 0; c < s; ++c) {
+        const fe::Col& q = all[c];
+        hnew[o + c] = q.val;
+        hkind[o + c] = q.kind;
+        hidx[o + c] = q.idx;
+        hct[o + c] = q.t;
+        hub[o + c] = q.ub;
+        hsig[o + c] = hmu[o + c] = hic[o + c] = 0.0;
+        if (q.kind == COL_REDUCED) {
+          const int64_t k = roff[p] + q.idx;
+          hsig[o + c] = rd[roff[p] + sidx[k]];
+          hmu[o + c] = mur[k];
+          hic[o + c] = 1.0 / (mur[k] * xnr[k]);
+        }
+      }
+      const int32_t q = (int32_t)anodes.size();
+      anodes.push_back({o, s, voff});
+      for (int32_t cg = 0; cg < (int32_t)cdiv(s, TA_CB); ++cg)
+        for (int32_t rc = 0; rc < (int32_t)cdiv(s, TA_T * TA_R); ++rc) atab.push_back({q, cg, rc, 0});
+      const double* Vp = ta.V + voff;
+      // rows of the left child: Q1 (m x m) times V's first m rows
+      GDesc g1d = {Qc + o + o * ldc, Vp, Qn + o + o * ldn, ldc, s, ldn, (int32_t)nd.m, (int32_t)s,
+                   (int32_t)nd.m, 0};
+      // rows of the right child: Q2 ((s-m) x (s-m)) times V's last s - m rows
+      const int64_t o2 = o + nd.m;
+      GDesc g2d = {Qc + o2 + o2 * ldc, Vp + nd.m, Qn + o2 + o * ldn, ldc, s, ldn, (int32_t)(s - nd.m), (int32_t)s,
+                   (int32_t)(s - nd.m), 0};
+      const int32_t d1 = (int32_t)gdesc.size();
+      gdesc.push_back(g1d);
+      gdesc.push_back(g2d);
+      for (int32_t tr = 0; tr < (int32_t)cdiv(nd.m, GT); ++tr)
+        for (int32_t tc = 0; tc < (int32_t)cdiv(s, GT); ++tc) gtab.push_back({d1, tr, tc, 0});
+      for (int32_t tr = 0; tr < (int32_t)cdiv(s - nd.m, GT); ++tr)
+        for (int32_t tc = 0; tc < (int32_t)cdiv(s, GT); ++tc) gtab.push_back({d1 + 1, tr, tc, 0});
+      voff += s * s;
+    }
+    if (voff > L.maxV || (int64_t)atab.size() > L.maxAsm || (int64_t)gtab.size() > L.maxTiles) return -10;
+    hlam.swap(hnew);
+    TCHECK(hipMemcpyAsync(lambda, hlam.data(), 8 * n, hipMemcpyHostToDevice, st));
+    TCHECK(h2d((void*)ta.rgrp, hgrp, n, st));
+    TCHECK(h2d((void*)ta.rpos, hpos, n, st));
+    TCHECK(h2d((void*)ta.ru, hru, n, st));
+    TCHECK(h2d((void*)ta.ckind, hkind, n, st));
+    TCHECK(h2d((void*)ta.cidx, hidx, n, st));
+    TCHECK(h2d((void*)ta.ct, hct, n, st));
+    TCHECK(h2d((void*)ta.csig, hsig, n, st));
+    TCHECK(h2d((void*)ta.cmu, hmu, n, st));
+    TCHECK(h2d((void*)ta.cic, hic, n, st));
+    TCHECK(h2d((void*)ta.cub, hub, n, st));
+    ANode* danodes = (ANode*)(w + L.anodes);
+    int4* datab = (int4*)(w + L.atab);
+    GDesc* dgdesc = (GDesc*)(w + L.gdesc);
+    int4* dgtab = (int4*)(w + L.gtab);
+    TCHECK(h2d(danodes, anodes, anodes.size(), st));
+    TCHECK(h2d(datab, atab, atab.size(), st));
+    TCHECK(h2d(dgdesc, gdesc, gdesc.size(), st));
+    TCHECK(h2d(dgtab, gtab, gtab.size(), st));
+    hipLaunchKernelGGL(k_tri_assemble, dim3((unsigned)atab.size()), dim3(TA_T), 0, st, danodes, datab, ta);
+    TCHECK(hipGetLastError());
+    // 5. Q = diag(Q1, Q2) V for every merge
+    hipLaunchKernelGGL(k_dgemm, dim3((unsigned)gtab.size()), dim3(256), 0, st, dgdesc, dgtab);
+    TCHECK(hipGetLastError());
+  }
+  // tri_set_info waits for the stream: the host staging above must outlive
+  // its copies
+  return tri_set_info(info, DPR1_INFO_OK, st);
+}
+
+}  // extern "C"

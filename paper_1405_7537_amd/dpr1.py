@@ -71,6 +71,9 @@ def lib():
                                        C.c_size_t, vp]
         L.dpr1_eig_hermitian.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, C.POINTER(Opts), vp,
                                          C.c_size_t, vp]
+        L.dpr1_tridiag_workspace_size.argtypes = [i64]
+        L.dpr1_tridiag_workspace_size.restype = C.c_size_t
+        L.dpr1_tridiag_eig.argtypes = [vp, vp, i64, vp, vp, i64, vp, C.POINTER(Opts), vp, C.c_size_t, vp]
         L.dpr1_strerror.argtypes = [C.c_int]
         L.dpr1_strerror.restype = C.c_char_p
         _lib = L
@@ -242,6 +245,35 @@ def eig_hermitian(d, z, rho, vectors=True, opts: Opts | None = None, check=True,
         code = int(info.item())
         if code != 0:
             raise ValueError(f"dpr1_eig_hermitian: info = {code} ({INFO_TEXT.get(code, '?')})")
+    return r
+
+
+def tridiag_eig(a, b, opts: Opts | None = None, check=True, device="cuda", work=None):
+    """All eigenpairs of the symmetric tridiagonal matrix with diagonal a [n] and off-diagonal b [n-1]
+    by divide and conquer over DPR1 merges (dpr1_tridiag_eig).  Synchronises the stream.
+    Returns a Result with lam [n] decreasing, Q [n, n] (Q[:, k] = q_k) and info."""
+    a = _dev(a, device)
+    n = a.numel()
+    b = _dev(b, device) if n > 1 else torch.zeros(1, dtype=torch.float64, device=a.device)
+    if b.numel() < n - 1:
+        raise ValueError("b must have n - 1 entries")
+    dev = a.device
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Qt = torch.empty((n, n), dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    wb = int(lib().dpr1_tridiag_workspace_size(n))
+    if wb == 0:
+        raise ValueError("n must be in [1, 65536]")
+    if work is None or work.numel() < wb:
+        work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    rc = lib().dpr1_tridiag_eig(_ptr(a), _ptr(b), n, _ptr(lam), _ptr(Qt), n, _ptr(info),
+                                C.byref(opts) if opts is not None else None, _ptr(work), wb, _stream())
+    _rc(rc, "dpr1_tridiag_eig")
+    r = Result(lam=lam, Q=Qt.t(), info=info, work=work)
+    if check:
+        code = int(info.item())
+        if code != 0:
+            raise ValueError(f"dpr1_tridiag_eig: info = {code} ({INFO_TEXT.get(code, '?')})")
     return r
 
 

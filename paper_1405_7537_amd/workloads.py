@@ -142,3 +142,15 @@ def reducible(n, seed, groups=None, zeros=None, rho=1.0):
     if zeros:
         z[rng.choice(n, min(zeros, n), replace=False)] = 0.0
     return d, z, rho
+
+
+def tridiagonal(n, seed):
+    """Symmetric tridiagonal T: diagonal and off-diagonal ~ N(0, 1) (seed), the input of the
+    divide-and-conquer driver whose merges are DPR1 problems."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n), rng.standard_normal(max(n - 1, 0))
+
+
+def wilkinson(m):
+    """Wilkinson's W_{2m+1}^+: diagonal |m|, ..., 1, 0, 1, ..., m, off-diagonal ones (close pairs)."""
+    return np.abs(np.arange(-m, m + 1, dtype=np.float64)), np.ones(2 * m)

@@ -1,0 +1,117 @@
+"""GPU parity of the divide-and-conquer tridiagonal driver (merges are DPR1 problems, Sec. 1)
+against the oracle's tridiag_eig on the same inputs, and its properties at larger n.
+
+The two sides run the same reductions and DPR1 solves; they differ in the order of the sums of
+the products diag(Q1, Q2) V, so results agree to rounding propagated through the merges:
+eigenvalues to 1e-13 ||T|| (absolute: Weyl's bound scale), eigenvector columns to 1e-9 where the
+eigenvalue is separated from the others by more than 1e-6 ||T|| (else the projector onto the
+group is compared), Q^T Q = I and T Q = Q Lambda to 1e-13 n ||T||.
+
+Columns are compared up to sign.  A merged column is q = diag(Q1, Q2) v with v_j proportional to
+z_j / (d_j - lambda); when z_j is far below the absolute accuracy of the children's Q (a
+component of 1e-60 from an eigenvector localised away from the split), lambda lies within
+rounding of d_j, v is +-e_j, and its sign is the sign of z_j, which is rounding noise on either
+side.  The eigenvector is unique only up to that sign.
+"""
+import numpy as np
+import pytest
+
+from paper_1405_7537_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1405_7537_amd.dpr1 as D
+    D.lib()
+    return D
+
+
+def dense(a, b):
+    return np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+
+
+def check(D, orc, a, b, tag):
+    n = len(a)
+    print(f"[tridiag] {tag} n={n}", flush=True)
+    r = D.tridiag_eig(a, b)
+    lam = r.lam.cpu().numpy()
+    Q = r.Q.cpu().numpy()
+    lo, Qo = orc.tridiag_eig(a, b)
+    T = dense(a, b)
+    nt = max(np.max(np.abs(lo)), 1e-300)
+    el = np.max(np.abs(lam - lo)) / nt
+    assert el <= 1e-13, (tag, el)
+    sep = np.full(n, np.inf)
+    if n > 1:
+        gaps = np.abs(np.diff(lo))
+        sep[:-1] = np.minimum(sep[:-1], gaps)
+        sep[1:] = np.minimum(sep[1:], gaps)
+    worst_c = worst_p = 0.0
+    k = 0
+    while k < n:
+        e = k + 1
+        while e < n and abs(lo[e] - lo[e - 1]) <= 1e-6 * nt:
+            e += 1
+        if e - k == 1 and sep[k] > 1e-6 * nt:
+            dc = min(np.max(np.abs(Q[:, k] - Qo[:, k])), np.max(np.abs(Q[:, k] + Qo[:, k])))
+            worst_c = max(worst_c, dc)
+            assert dc <= 1e-9, (tag, k, dc)
+        else:
+            dp = np.max(np.abs(Q[:, k:e] @ Q[:, k:e].T - Qo[:, k:e] @ Qo[:, k:e].T))
+            worst_p = max(worst_p, dp)
+            assert dp <= 1e-9, (tag, k, e, dp)
+        k = e
+    orth = np.max(np.abs(Q.T @ Q - np.eye(n)))
+    res = np.max(np.abs(T @ Q - Q * lam)) / nt
+    assert orth <= 1e-13 * n and res <= 1e-13 * n, (tag, orth, res)
+    print(f"[tridiag] {tag}: lam {el:.2e} col {worst_c:.2e} proj {worst_p:.2e} orth {orth:.2e} res {res:.2e}",
+          flush=True)
+    return lam, Q
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (3, 2), (5, 3), (17, 4), (64, 5), (100, 6), (257, 7),
+                                    (600, 8)])
+def test_random_against_oracle(D, orc, n, seed):
+    a, b = W.tridiagonal(n, seed)
+    check(D, orc, a, b, f"random seed {seed}")
+
+
+def test_wilkinson_against_oracle(D, orc):
+    a, b = W.wilkinson(10)
+    check(D, orc, a, b, "W21+")
+    a, b = W.wilkinson(50)
+    check(D, orc, a, b, "W101+")
+
+
+def test_decoupled_and_diagonal(D, orc):
+    a, b = W.tridiagonal(40, 9)
+    b[[3, 19, 20, 33]] = 0.0
+    check(D, orc, a, b, "zero off-diagonals")
+    lam, Q = check(D, orc, [0.3, 2.0, -1.0, 2.0, 5.0], [0.0, 0.0, 0.0, 0.0], "diagonal")
+    assert list(lam) == [5.0, 2.0, 2.0, 0.3, -1.0]
+
+
+def test_large_properties(D):
+    """n = 4096: eigenvalues against LAPACK's symmetric solver on the dense T, orthogonality and the
+    residual (properties that hold at any size)."""
+    a, b = W.tridiagonal(4096, 10)
+    print("[tridiag] n=4096 properties", flush=True)
+    r = D.tridiag_eig(a, b)
+    lam = r.lam.cpu().numpy()
+    T = dense(a, b)
+    L = np.sort(np.linalg.eigvalsh(T))[::-1]
+    nt = np.max(np.abs(L))
+    assert np.max(np.abs(lam - L)) <= 1e-12 * nt
+    Qd = r.Q
+    G = (Qd.T @ Qd).cpu().numpy()
+    orth = np.max(np.abs(G - np.eye(4096)))
+    import torch
+    Td = torch.as_tensor(T, device=Qd.device)
+    res = (Td @ Qd - Qd * r.lam).abs().max().item() / nt
+    print(f"[tridiag] n=4096: lam {np.max(np.abs(lam - L)) / nt:.2e} orth {orth:.2e} res {res:.2e}", flush=True)
+    assert orth <= 1e-11 and res <= 1e-11
