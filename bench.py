@@ -66,7 +66,7 @@ def main():
                     help="fill the tuning cache for every solve this bench times, then exit")
     ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
                     help="copy: a plain device copy of known size, to calibrate HBM byte counters")
-    ap.add_argument("--only", default=None, choices=["batched", "fwd_bwd", "general"],
+    ap.add_argument("--only", default=None, choices=["batched", "fwd_bwd", "general", "tridiag"],
                     help="run only this workload (for profiler runs); prints its JSON")
     args = ap.parse_args()
     if args.mode == "copy":
@@ -76,7 +76,8 @@ def main():
         import paper_1405_7537_amd.dpr1 as D
         from paper_1405_7537_amd import workloads as W
         dev = torch.device("cuda:0")
-        fn = {"batched": bench_batched, "fwd_bwd": bench_fwd_bwd, "general": bench_general}[args.only]
+        fn = {"batched": bench_batched, "fwd_bwd": bench_fwd_bwd, "general": bench_general,
+              "tridiag": bench_tridiag}[args.only]
         print(json.dumps(fn(D, W, torch, dev, args)), flush=True)
         return
 
@@ -220,6 +221,7 @@ def main():
         if fb is not None:
             result["fwd_bwd"] = fb
         result["general"] = bench_general(D, W, torch, dev, args)
+        result["tridiag"] = bench_tridiag(D, W, torch, dev, args)
 
     print(json.dumps(result), flush=True)
 
@@ -374,6 +376,54 @@ def bench_general(D, W, torch, dev, args):
             "value": n / (ms / 1e3), "unit": "eigenpairs/s",
             "hermitian": {"workload": "the same poles and |z|, uniform random phases, complex128 V",
                           "ms_per_step": ms_h, "value": n / (ms_h / 1e3), "unit": "eigenpairs/s"}}
+
+
+def dc_gemm_flops(n):
+    """FP64 flops of the products diag(Q1, Q2) V over the whole split tree (2 m^2 s + 2 (s-m)^2 s
+    per merge of size s split at m = s // 2)."""
+    tot, stack = 0, [n]
+    while stack:
+        s = stack.pop()
+        if s < 2:
+            continue
+        m = s // 2
+        tot += 2 * (m * m + (s - m) * (s - m)) * s
+        stack += [m, s - m]
+    return tot
+
+
+def bench_tridiag(D, W, torch, dev, args, n=8192):
+    """Symmetric tridiagonal T (n = 8192, N(0,1) entries, seed 5) by divide and conquer over DPR1
+    merges; the library dense symmetric eigensolver on the same T is timed beside it for context."""
+    a_h, b_h = W.tridiagonal(n, 5)
+    a = torch.as_tensor(a_h, device=dev)
+    b = torch.as_tensor(b_h, device=dev)
+    r = D.tridiag_eig(a, b)
+    work = r.work
+    del r
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 5))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = D.tridiag_eig(a, b, work=work)
+        del r
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    fl = dc_gemm_flops(n)
+    T = torch.diag(a) + torch.diag(b, 1) + torch.diag(b, -1)
+    torch.linalg.eigh(T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    torch.linalg.eigh(T)
+    torch.cuda.synchronize()
+    ms_ref = (time.perf_counter() - t0) * 1e3
+    del T
+    torch.cuda.empty_cache()
+    log(f"[bench] tridiag n={n}: {ms:.2f} ms per solve ({fl / 1e9:.0f} GFLOP of merge products); "
+        f"dense symmetric library solver on the same T: {ms_ref:.1f} ms")
+    return {"workload": f"symmetric tridiagonal n={n}, diagonal and off-diagonal N(0,1) (seed 5), all eigenpairs",
+            "ms_per_step": ms, "value": n / (ms / 1e3), "unit": "eigenpairs/s", "gemm_flops": fl,
+            "dense_library_eigh_ms": ms_ref}
 
 
 if __name__ == "__main__":

@@ -18,7 +18,7 @@
 //   4. k_tri_assemble writes every merge's V (eq. (eigenvecAi) on the merge's
 //      own poles and z, unit and reflection columns);
 //   5. k_dgemm forms diag(Q1, Q2) V for every merge into the other Q buffer
-//      (two products per merge, one batched launch over 64 x 64 tiles).
+//      (two products per merge, one batched launch over 128 x 128 tiles).
 // The two Q buffers alternate between depths so that the root's product
 // lands in the caller's Q.  A block is written only by its own merge and read
 // only by its parent's, and a leaf's 1 x 1 block (= 1) is set in both buffers
@@ -185,60 +185,73 @@ struct GDesc {
   int32_t M, N, K, pad;
 };
 
-constexpr int GT = 64, GKS = 16;
+constexpr int GT = 128, GKS = 16;
 
-// One 256-thread block per 64 x 64 tile of C (tile table entry: descriptor,
-// tile row, tile column); each thread accumulates a 4 x 4 sub-tile over K in
-// steps of 16 staged in LDS.  16 consecutive threads own consecutive 4-row
-// pieces of one column (a 64-row segment), so the stores of C are coalesced.
+// One 256-thread block per 128 x 128 tile of C (tile table entry: descriptor,
+// tile row, tile column); each thread accumulates an 8 x 8 sub-tile over K in
+// steps of 16 staged in LDS, so that every value read from LDS feeds 8 FMAs.
+// 16 consecutive threads own consecutive 8-row pieces of one column (a
+// 128-row segment), so the stores of C are coalesced.
 __global__ void __launch_bounds__(256) k_dgemm(const GDesc* __restrict__ desc, const int4* __restrict__ tiles) {
-  __shared__ double As[GKS][GT + 1];
-  __shared__ double Bs[GKS][GT + 1];
+  __shared__ double As[GKS][GT + 2];
+  __shared__ double Bs[GKS][GT + 2];
   const int4 t = tiles[blockIdx.x];
   const GDesc g = desc[t.x];
   const int r0 = t.y * GT, c0 = t.z * GT;
   const int tid = threadIdx.x;
-  const int tr = (tid % 16) * 4, tc = (tid / 16) * 4;
-  double acc[4][4];
+  const int tr = (tid % 16) * 8, tc = (tid / 16) * 8;
+  double acc[8][8];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+  // the tile of the next K step is loaded into registers while this one is
+  // multiplied out of LDS
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      // A tile 128 x 16: rows tid % 128 of k = tid / 128 + 2 j
+      const int gr = r0 + tid % GT, gk = k0 + tid / GT + 2 * j;
+      ra[j] = (gr < g.M && gk < g.K) ? g.A[gr + (int64_t)gk * g.lda] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      // B tile 16 x 128: k = tid % 16 of columns tid / 16 + 16 j
+      const int gk = k0 + tid % GKS, gc = c0 + tid / GKS + 16 * j;
+      rb[j] = (gk < g.K && gc < g.N) ? g.B[gk + (int64_t)gc * g.ldb] : 0.0;
+    }
+  };
+  load(0);
   for (int k0 = 0; k0 < g.K; k0 += GKS) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = tid % 64, k = tid / 64 + 4 * j;
-      const int gr = r0 + r, gk = k0 + k;
-      As[k][r] = (gr < g.M && gk < g.K) ? g.A[gr + (int64_t)gk * g.lda] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = tid % 16, c = tid / 16 + 16 * j;
-      const int gk = k0 + k, gc = c0 + c;
-      Bs[k][c] = (gk < g.K && gc < g.N) ? g.B[gk + (int64_t)gc * g.ldb] : 0.0;
+    for (int j = 0; j < 8; ++j) {
+      As[tid / GT + 2 * j][tid % GT] = ra[j];
+      Bs[tid % GKS][tid / GKS + 16 * j] = rb[j];
     }
     __syncthreads();
+    if (k0 + GKS < g.K) load(k0 + GKS);
 #pragma unroll
     for (int k = 0; k < GKS; ++k) {
-      double av[4], bv[4];
+      double av[8], bv[8];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < 8; ++i) {
         av[i] = As[k][tr + i];
         bv[i] = Bs[k][tc + i];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(av[i], bv[j], acc[i][j]);
+        for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_fma(av[i], bv[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < 8; ++j) {
     const int gc = c0 + tc + j;
     if (gc >= g.N) continue;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
       const int gr = r0 + tr + i;
       if (gr < g.M) g.C[gr + (int64_t)gc * g.ldc] = acc[i][j];
     }

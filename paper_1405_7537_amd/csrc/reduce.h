@@ -30,9 +30,23 @@ struct Col {
 
 // Stable sort of the poles in decreasing order: order[s] = the row with the
 // s-th largest d (equal values keep their row order, -0 and +0 are equal).
-// LSD radix sort on order-preserving 64-bit keys, 11 bits a pass; a pass
-// whose digit is the same for every key is skipped.
+// LSD radix sort on order-preserving 64-bit keys, 11 bits a pass (a pass
+// whose digit is the same for every key is skipped); insertion sort up to 256.
 inline void sort_decreasing(const double* d, int64_t n, std::vector<int64_t>& order) {
+  if (n <= 256) {
+    // small problems (the many merges near the leaves of a divide and
+    // conquer): an insertion sort, stable, with -0 = +0 by value comparison
+    order.resize(n);
+    for (int64_t j = 0; j < n; ++j) {
+      int64_t t = j;
+      while (t > 0 && d[order[t - 1]] < d[j]) {
+        order[t] = order[t - 1];
+        --t;
+      }
+      order[t] = j;
+    }
+    return;
+  }
   std::vector<uint64_t> k(n), k2(n);
   std::vector<int64_t> o2(n);
   order.resize(n);
