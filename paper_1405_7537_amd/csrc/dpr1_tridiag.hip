@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "../../include/dpr1.h"
@@ -437,6 +438,16 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
   std::vector<std::vector<fe::Col>> mcols;
   std::vector<double> hnew(n);
   dpr1_plan plan;
+  // host mirrors of contiguous workspace regions, so that each region moves
+  // in one copy per depth: the solver's inputs [rd, offsp], its outputs
+  // [lamr, infop], the merges' poles and z [zl, dl], and the assembly and
+  // GEMM arrays [rgrp, gtab]
+  const int64_t P = std::max<int64_t>(L.maxNodes, 1);
+  std::vector<char> mirA(L.offsp + 8 * (P + 1) - L.rd), mirB(L.infop + 4 * P - L.lamr), mirZ(L.dl + 8 * n - L.zl),
+      mirC(L.solver - L.rgrp);
+  auto put = [](std::vector<char>& mir, size_t base, size_t off, const void* src, size_t bytes) {
+    if (bytes) memcpy(mir.data() + (off - base), src, bytes);
+  };
 
   for (int D = maxd; D >= 0; --D) {
     std::vector<const Node*> lv;
@@ -512,26 +523,29 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
       int32_t* dinf = (int32_t*)(w + L.infop);
       double* drho = (double*)(w + L.rhop);
       int64_t* doffs = (int64_t*)(w + L.offsp);
-      TCHECK(h2d(drd, rd, mtot, st));
-      TCHECK(h2d(drz, rz, mtot, st));
-      TCHECK(h2d(drho, rhop, nprob, st));
-      TCHECK(h2d(doffs, offs, nprob + 1, st));
+      put(mirA, L.rd, L.rd, rd.data(), 8 * mtot);
+      put(mirA, L.rd, L.rz, rz.data(), 8 * mtot);
+      put(mirA, L.rd, L.rhop, rhop.data(), 8 * nprob);
+      put(mirA, L.rd, L.offsp, offs.data(), 8 * (nprob + 1));
+      TCHECK(hipMemcpyAsync(w + L.rd, mirA.data(), L.offsp + 8 * (nprob + 1) - L.rd, hipMemcpyHostToDevice, st));
       const int rc = dpr1_eig_batched(&plan, doffs, drd, drz, drho, dlr, nullptr, nullptr, dsi, dmu, dxn, dinf,
                                       nullptr, w + L.solver, L.solver_bytes, stream);
       if (rc != DPR1_OK) return rc;
-      TCHECK(hipMemcpyAsync(lamr.data(), dlr, 8 * mtot, hipMemcpyDeviceToHost, st));
-      TCHECK(hipMemcpyAsync(mur.data(), dmu, 8 * mtot, hipMemcpyDeviceToHost, st));
-      TCHECK(hipMemcpyAsync(xnr.data(), dxn, 8 * mtot, hipMemcpyDeviceToHost, st));
-      TCHECK(hipMemcpyAsync(sidx.data(), dsi, 4 * mtot, hipMemcpyDeviceToHost, st));
-      TCHECK(hipMemcpyAsync(infop.data(), dinf, 4 * nprob, hipMemcpyDeviceToHost, st));
+      TCHECK(hipMemcpyAsync(mirB.data(), w + L.lamr, mirB.size(), hipMemcpyDeviceToHost, st));
       TCHECK(hipStreamSynchronize(st));
+      memcpy(lamr.data(), mirB.data() + (L.lamr - L.lamr), 8 * mtot);
+      memcpy(mur.data(), mirB.data() + (L.mur - L.lamr), 8 * mtot);
+      memcpy(xnr.data(), mirB.data() + (L.xnr - L.lamr), 8 * mtot);
+      memcpy(sidx.data(), mirB.data() + (L.sidx - L.lamr), 4 * mtot);
+      memcpy(infop.data(), mirB.data() + (L.infop - L.lamr), 4 * nprob);
       for (int32_t x : infop)
         if (x != DPR1_INFO_OK) return tri_set_info(info, x, st);
     }
 
     // 4. columns of every merge, the new eigenvalues, the assembly and GEMM tables
-    TCHECK(hipMemcpyAsync(dl, hlam.data(), 8 * n, hipMemcpyHostToDevice, st));  // the merges' poles
-    TCHECK(hipMemcpyAsync(zl, hz.data(), 8 * n, hipMemcpyHostToDevice, st));    // z as reduced
+    put(mirZ, L.zl, L.zl, hz.data(), 8 * n);     // z as reduced
+    put(mirZ, L.zl, L.dl, hlam.data(), 8 * n);   // the merges' poles
+    TCHECK(hipMemcpyAsync(w + L.zl, mirZ.data(), mirZ.size(), hipMemcpyHostToDevice, st));
     anodes.clear();
     atab.clear();
     gdesc.clear();
@@ -581,24 +595,26 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     if (voff > L.maxV || (int64_t)atab.size() > L.maxAsm || (int64_t)gtab.size() > L.maxTiles) return -10;
     hlam.swap(hnew);
     TCHECK(hipMemcpyAsync(lambda, hlam.data(), 8 * n, hipMemcpyHostToDevice, st));
-    TCHECK(h2d((void*)ta.rgrp, hgrp, n, st));
-    TCHECK(h2d((void*)ta.rpos, hpos, n, st));
-    TCHECK(h2d((void*)ta.ru, hru, n, st));
-    TCHECK(h2d((void*)ta.ckind, hkind, n, st));
-    TCHECK(h2d((void*)ta.cidx, hidx, n, st));
-    TCHECK(h2d((void*)ta.ct, hct, n, st));
-    TCHECK(h2d((void*)ta.csig, hsig, n, st));
-    TCHECK(h2d((void*)ta.cmu, hmu, n, st));
-    TCHECK(h2d((void*)ta.cic, hic, n, st));
-    TCHECK(h2d((void*)ta.cub, hub, n, st));
+    put(mirC, L.rgrp, L.rgrp, hgrp.data(), 4 * n);
+    put(mirC, L.rgrp, L.rpos, hpos.data(), 4 * n);
+    put(mirC, L.rgrp, L.ru, hru.data(), 8 * n);
+    put(mirC, L.rgrp, L.ckind, hkind.data(), 4 * n);
+    put(mirC, L.rgrp, L.cidx, hidx.data(), 4 * n);
+    put(mirC, L.rgrp, L.ct, hct.data(), 4 * n);
+    put(mirC, L.rgrp, L.csig, hsig.data(), 8 * n);
+    put(mirC, L.rgrp, L.cmu, hmu.data(), 8 * n);
+    put(mirC, L.rgrp, L.cic, hic.data(), 8 * n);
+    put(mirC, L.rgrp, L.cub, hub.data(), 8 * n);
+    put(mirC, L.rgrp, L.anodes, anodes.data(), sizeof(ANode) * anodes.size());
+    put(mirC, L.rgrp, L.atab, atab.data(), sizeof(int4) * atab.size());
+    put(mirC, L.rgrp, L.gdesc, gdesc.data(), sizeof(GDesc) * gdesc.size());
+    put(mirC, L.rgrp, L.gtab, gtab.data(), sizeof(int4) * gtab.size());
+    TCHECK(hipMemcpyAsync(w + L.rgrp, mirC.data(), L.gtab + sizeof(int4) * gtab.size() - L.rgrp,
+                          hipMemcpyHostToDevice, st));
     ANode* danodes = (ANode*)(w + L.anodes);
     int4* datab = (int4*)(w + L.atab);
     GDesc* dgdesc = (GDesc*)(w + L.gdesc);
     int4* dgtab = (int4*)(w + L.gtab);
-    TCHECK(h2d(danodes, anodes, anodes.size(), st));
-    TCHECK(h2d(datab, atab, atab.size(), st));
-    TCHECK(h2d(dgdesc, gdesc, gdesc.size(), st));
-    TCHECK(h2d(dgtab, gtab, gtab.size(), st));
     hipLaunchKernelGGL(k_tri_assemble, dim3((unsigned)atab.size()), dim3(TA_T), 0, st, danodes, datab, ta);
     TCHECK(hipGetLastError());
     // 5. Q = diag(Q1, Q2) V for every merge
