@@ -18,7 +18,8 @@
 //   4. k_tri_assemble writes every merge's V (eq. (eigenvecAi) on the merge's
 //      own poles and z, unit and reflection columns);
 //   5. k_dgemm forms diag(Q1, Q2) V for every merge into the other Q buffer
-//      (two products per merge, one batched launch over 128 x 128 tiles).
+//      (two products per merge, one batched launch over 128 x 128 tiles on
+//      FP64 matrix cores).
 // The two Q buffers alternate between depths so that the root's product
 // lands in the caller's Q.  A block is written only by its own merge and read
 // only by its parent's, and a leaf's 1 x 1 block (= 1) is set in both buffers
@@ -186,77 +187,93 @@ struct GDesc {
   int32_t M, N, K, pad;
 };
 
-constexpr int GT = 128, GKS = 16;
+constexpr int GT = 128, GKS = 16, GNT = 512, GPAD = 2;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// One 256-thread block per 128 x 128 tile of C (tile table entry: descriptor,
-// tile row, tile column); each thread accumulates an 8 x 8 sub-tile over K in
-// steps of 16 staged in LDS, so that every value read from LDS feeds 8 FMAs.
-// 16 consecutive threads own consecutive 8-row pieces of one column (a
-// 128-row segment), so the stores of C are coalesced.
-__global__ void __launch_bounds__(256) k_dgemm(const GDesc* __restrict__ desc, const int4* __restrict__ tiles) {
-  __shared__ double As[GKS][GT + 2];
-  __shared__ double Bs[GKS][GT + 2];
+// One 512-thread block (8 waves) per 128 x 128 tile of C (tile table entry:
+// descriptor, tile row, tile column), on FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).  Wave w owns rows 64 (w & 1) .. +63 and columns
+// 32 (w >> 1) .. +31 of the tile: 4 x 2 blocks of 16 x 16.  K advances in
+// steps of 16 through two LDS buffers; the next step's operands are loaded
+// into registers while the current one is multiplied.  Lane layout of the
+// 16x16x4 instruction: A(row = lane % 16, k = lane / 16), B(k = lane / 16,
+// col = lane % 16); accumulator element q of a lane is row lane / 16 + 4 q,
+// column lane % 16 of its block.
+__global__ void __launch_bounds__(GNT, 2) k_dgemm(const GDesc* __restrict__ desc, const int4* __restrict__ tiles) {
+  __shared__ double As[2][GKS][GT + GPAD];
+  __shared__ double Bs[2][GKS][GT + GPAD];
   const int4 t = tiles[blockIdx.x];
   const GDesc g = desc[t.x];
   const int r0 = t.y * GT, c0 = t.z * GT;
   const int tid = threadIdx.x;
-  const int tr = (tid % 16) * 8, tc = (tid / 16) * 8;
-  double acc[8][8];
+  const int wv = tid / 64, lane = tid % 64;
+  const int wm = (wv & 1) * 64, wn = (wv >> 1) * 32;
+  dbl4 acc[4][2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
-  // the tile of the next K step is loaded into registers while this one is
-  // multiplied out of LDS
-  double ra[8], rb[8];
-  auto load = [&](int k0) {
+    for (int y = 0; y < 2; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  constexpr int PER = GT * GKS / GNT;  // 4 elements of each operand per thread
+  double ra[PER], rb[PER];
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      // A tile 128 x 16: rows tid % 128 of k = tid / 128 + 2 j
-      const int gr = r0 + tid % GT, gk = k0 + tid / GT + 2 * j;
-      ra[j] = (gr < g.M && gk < g.K) ? g.A[gr + (int64_t)gk * g.lda] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      // B tile 16 x 128: k = tid % 16 of columns tid / 16 + 16 j
-      const int gk = k0 + tid % GKS, gc = c0 + tid / GKS + 16 * j;
-      rb[j] = (gk < g.K && gc < g.N) ? g.B[gk + (int64_t)gc * g.ldb] : 0.0;
+    for (int e2 = 0; e2 < PER; ++e2) {
+      const int e = tid + e2 * GNT;
+      // A(m, k) = A[m + k lda]: consecutive threads along m
+      const int m = e % GT, ka = e / GT;
+      const int gr = r0 + m, gka = k0 + ka;
+      ra[e2] = (gr < g.M && gka < g.K) ? g.A[gr + (int64_t)gka * g.lda] : 0.0;
+      // B(k, c) = B[k + c ldb]: consecutive threads along k
+      const int kb = e % GKS, c = e / GKS;
+      const int gkb = k0 + kb, gc = c0 + c;
+      rb[e2] = (gkb < g.K && gc < g.N) ? g.B[gkb + (int64_t)gc * g.ldb] : 0.0;
     }
   };
-  load(0);
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e2 = 0; e2 < PER; ++e2) {
+      const int e = tid + e2 * GNT;
+      As[buf][e / GT][e % GT] = ra[e2];
+      Bs[buf][e % GKS][e / GKS] = rb[e2];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < g.K; k0 += GKS) {
+    const bool more = k0 + GKS < g.K;
+    if (more) gload(k0 + GKS);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      As[tid / GT + 2 * j][tid % GT] = ra[j];
-      Bs[tid % GKS][tid / GKS + 16 * j] = rb[j];
+    for (int ks = 0; ks < GKS; ks += 4) {
+      const int r = lane % 16, q = lane / 16;
+      double af[4], bf[2];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) af[x] = As[buf][ks + q][wm + 16 * x + r];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bf[y] = Bs[buf][ks + q][wn + 16 * y + r];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
     }
-    __syncthreads();
-    if (k0 + GKS < g.K) load(k0 + GKS);
+    if (more) {
+      sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
 #pragma unroll
-    for (int k = 0; k < GKS; ++k) {
-      double av[8], bv[8];
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        av[i] = As[k][tr + i];
-        bv[i] = Bs[k][tc + i];
+    for (int y = 0; y < 2; ++y) {
+      const int gc = c0 + wn + 16 * y + lane % 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gr = r0 + wm + 16 * x + lane / 16 + 4 * q;
+        if (gr < g.M && gc < g.N) g.C[gr + (int64_t)gc * g.ldc] = acc[x][y][q];
       }
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_fma(av[i], bv[j], acc[i][j]);
     }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int gc = c0 + tc + j;
-    if (gc >= g.N) continue;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int gr = r0 + tr + i;
-      if (gr < g.M) g.C[gr + (int64_t)gc * g.ldc] = acc[i][j];
-    }
-  }
 }
 
 // ------------------------------------------------------------ workspace
@@ -618,7 +635,7 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     hipLaunchKernelGGL(k_tri_assemble, dim3((unsigned)atab.size()), dim3(TA_T), 0, st, danodes, datab, ta);
     TCHECK(hipGetLastError());
     // 5. Q = diag(Q1, Q2) V for every merge
-    hipLaunchKernelGGL(k_dgemm, dim3((unsigned)gtab.size()), dim3(256), 0, st, dgdesc, dgtab);
+    hipLaunchKernelGGL(k_dgemm, dim3((unsigned)gtab.size()), dim3(GNT), 0, st, dgdesc, dgtab);
     TCHECK(hipGetLastError());
   }
   // tri_set_info waits for the stream: the host staging above must outlive
