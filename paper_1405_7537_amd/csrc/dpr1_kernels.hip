@@ -1328,7 +1328,11 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
     double sg = M.neg ? -1.0 : 1.0;
     lam_out[b] = sg * lam[a];
     // per-column constants of the eigenvector kernel: sigma_k and
-    // 1/(sign(mu) |mu| ||x||), so that v_j = zeta_j (mu/(delta_j - mu)) cinv
+    // 1/(sign(mu) |mu| ||x||), so that v_j = zeta_j ((mu/(delta_j - mu)) cinv);
+    // the quotient is scaled first: (mu/(delta_j - mu)) cinv = 1/((delta_j -
+    // mu) ||x||) is at most 1/|zeta_j|, while zeta_j (mu/(delta_j - mu)) can
+    // underflow when mu is tiny (|mu| = 1e-240, zeta_j = 1e-100) although v_j
+    // is representable
     csig[a] = sd[M.off + ii[a]];
     cinv[a] = 1.0 / copysign(xs[a], mu[a]);
     if (idx_out) idx_out[b] = M.neg ? n - 1 - ii[a] : ii[a];
@@ -1458,7 +1462,7 @@ __device__ void vec_block(unsigned bid, const VArgs& v) {
         const double rc = rcp_1nr(den);
         double qq = m * rc;
         qq = __builtin_fma(__builtin_fma(-qq, den, m), rc, qq);  // corrected quotient
-        __builtin_nontemporal_store((ld_z[pos] * qq) * linv[c], &V[e]);
+        __builtin_nontemporal_store(ld_z[pos] * (qq * linv[c]), &V[e]);
       }
     }
     return;
@@ -1481,7 +1485,7 @@ __device__ void vec_block(unsigned bid, const VArgs& v) {
         const double rc = rcp_1nr(den);
         double q = m * rc;
         q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
-        __builtin_nontemporal_store((ld_z[rel] * q) * iv, vp);
+        __builtin_nontemporal_store(ld_z[rel] * (q * iv), vp);
       }
     }
   }
@@ -1535,7 +1539,7 @@ __global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ la
         const double rc = rcp_1nr(den);
         double q = m * rc;
         q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
-        __builtin_nontemporal_store(((sg * A.sz[M.off + j]) * q) * iv, &col[pos]);
+        __builtin_nontemporal_store((sg * A.sz[M.off + j]) * (q * iv), &col[pos]);
       }
     }
   }

@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(TA_T) k_tri_assemble(const ANode* __restrict__
         const double rc = rcp_nr(den);
         double q = m * rc;
         q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);
-        v[j] = zi[j] != 0.0 ? (zi[j] * q) * ic : 0.0;
+        v[j] = zi[j] != 0.0 ? zi[j] * (q * ic) : 0.0;
       }
     } else if (kind == COL_UNIT) {
       const int64_t at = s_idx[cc];

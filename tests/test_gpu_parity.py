@@ -145,6 +145,25 @@ def test_tiny_zeta_shift(D, orc, case):
     compare(D, orc, np.array(d), np.array(z), rho, tag=f"tinyzeta{case}")
 
 
+def test_huge_tip_between_tiny_zetas(D, orc):
+    """An eigenvalue between two poles with zeta 1e-100 and 1e-120, far from both: the arrowhead
+    inverse at either pole has |b| ~ 1e200-1e240 (the case that once broke the oracle's interval)."""
+    d = np.array([2.0, 1.0, 0.5, 0.0, -1.0])
+    z = np.array([1.0, 1e-100, 1e-120, 1.0, 0.7])
+    compare(D, orc, d, z, 1.0, tag="huge tip rho>0")
+    compare(D, orc, d, z, -1.0, tag="huge tip rho<0")
+
+
+@pytest.mark.parametrize("n,seed,rho", [(300, 50, 1.0), (777, 51, -2.0)])
+def test_zeta_spanning_150_decades(D, orc, n, seed, rho):
+    """|z_j| = 10^U(-150, 0) with random signs, as the merges of a divide and conquer produce:
+    many eigenvalues within 1e-300 of their poles, and shift poles whose zeta is tiny."""
+    rng = np.random.default_rng(seed)
+    d, _, _ = W.uniform(n, seed)
+    z = 10.0 ** rng.uniform(-150, 0, n) * rng.choice([-1.0, 1.0], n)
+    compare(D, orc, d, z, rho, tag=f"zeta 1e-150..1 seed {seed}")
+
+
 def test_config_graded_4096(D, orc):
     """Graded/clustered matrix at its full size (n = 4096, every 64th pair of poles at a
     relative gap of 1e-10): every eigenpair against the oracle, element by element."""
