@@ -115,3 +115,24 @@ def test_large_properties(D):
     res = (Td @ Qd - Qd * r.lam).abs().max().item() / nt
     print(f"[tridiag] n=4096: lam {np.max(np.abs(lam - L)) / nt:.2e} orth {orth:.2e} res {res:.2e}", flush=True)
     assert orth <= 1e-11 and res <= 1e-11
+
+
+@pytest.mark.parametrize("case", ["random10000", "wilkinson3001"])
+def test_large_uneven_and_clustered(D, case):
+    """n = 10000 (an uneven split tree) and Wilkinson's W+ of order 3001 (pairs of eigenvalues equal
+    to many digits): eigenvalues against LAPACK on the dense T, Q^T Q = I and T Q = Q Lambda."""
+    import torch
+    a, b = W.tridiagonal(10000, 12) if case == "random10000" else W.wilkinson(1500)
+    n = len(a)
+    print(f"[tridiag] {case} n={n}", flush=True)
+    r = D.tridiag_eig(a, b)
+    lam = r.lam.cpu().numpy()
+    L = np.sort(np.linalg.eigvalsh(dense(a, b)))[::-1]
+    nt = np.max(np.abs(L))
+    el = np.max(np.abs(lam - L)) / nt
+    Qd = r.Q
+    orth = (Qd.T @ Qd - torch.eye(n, dtype=torch.float64, device=Qd.device)).abs().max().item()
+    Td = torch.as_tensor(dense(a, b), device=Qd.device)
+    res = (Td @ Qd - Qd * r.lam).abs().max().item() / nt
+    print(f"[tridiag] {case}: lam {el:.2e} orth {orth:.2e} res {res:.2e}", flush=True)
+    assert el <= 1e-12 and orth <= 1e-11 and res <= 1e-11
