@@ -806,8 +806,11 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // That sum is taken at m and carried to nu1 = m + h by its Taylor series to
   // second order (derivatives -2 sum zeta^2 delta'/pp^3 and 6 sum zeta^2
   // delta'^2/pp^4; |h|/(m - xi_j) <= 2^-19, so the error is below 2^-55).
+  // The products are formed as h (h S) so that an h near 1e300 (nu = 1/mu
+  // for a mu near 1e-300, beside a zeta_i near 1e-150) meets the underflowed
+  // sums before it is squared: h h would overflow and inf * 0 be NaN.
   const double h = nu1 - m;
-  double Nx[1] = {zi2 + ((Sp[0] - 2.0 * h * Sp[1]) + 3.0 * (h * h) * Sp[2])};
+  double Nx[1] = {zi2 + ((Sp[0] - 2.0 * (h * Sp[1])) + 3.0 * (h * (h * Sp[2])))};
   if (wv == 0 && valid) {
     A.ii[off + k] = i;
     A.vflag[off + k] = (pol || nz || cont) ? 1 : 0;
@@ -1122,7 +1125,7 @@ __device__ void fix_items(const KArgs& A) {
       }
       // ||x|| carried from m to the root to second order, as in k_eig
       const double h = nu1 - m;
-      xsv = sqrt(zi2 + ((sp - 2.0 * h * sp3) + 3.0 * (h * h) * sp4));
+      xsv = sqrt(zi2 + ((sp - 2.0 * (h * sp3)) + 3.0 * (h * (h * sp4))));
       nu0 = m;
       have_xs = true;
     }

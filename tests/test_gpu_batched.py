@@ -153,3 +153,17 @@ def test_more_problems_than_a_grid_row(D, orc):
     for p in list(range(5)) + list(range(65530, 65540)) + [69999]:
         el, ev = check_problem(b, orc, d, z, rho, offs, p)
         assert el <= LAM_TOL and ev <= VEC_TOL, (p, sizes[p], el, ev)
+
+
+def test_zeta_spanning_150_decades(D, orc):
+    """A batch whose z spans 1e-150..1 (as divide-and-conquer merges produce): every problem
+    against the oracle, both signs of rho."""
+    d, _, rho, offs = W.batched(24, 60, nmin=2, nmax=400)
+    rng = np.random.default_rng(60)
+    z = 10.0 ** rng.uniform(-150, 0, d.size) * rng.choice([-1.0, 1.0], d.size)
+    rho[::3] *= -1.0
+    print(f"[batched] tiny-zeta mix total {offs[-1]}", flush=True)
+    b = D.eig_batched(d, z, rho, offs)
+    for p in range(24):
+        el, ev = check_problem(b, orc, d, z, rho, offs, p)
+        assert el <= LAM_TOL and ev <= VEC_TOL, (p, el, ev)

@@ -207,3 +207,14 @@ def test_hermitian_large_properties(D):
     scale = max(np.max(np.abs(d)), abs(rho) * np.sum(np.abs(zc) ** 2))
     assert np.max(np.abs(res)) <= 1e-13 * scale, np.max(np.abs(res))
     print(f"[general] hermitian n=4096: orth {orth:.2e} residual {np.max(np.abs(res)) / scale:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_zeta_spanning_150_decades(D, orc, hermitian):
+    """Front end (and Hermitian case) with repeated poles, zero z_j and |z_j| spanning 1e-150..1."""
+    d, z, _ = W.reducible(500, 61, rho=-1.3)
+    rng = np.random.default_rng(61)
+    z = np.where(z == 0, 0.0, 10.0 ** rng.uniform(-150, 0, 500) * np.sign(z))
+    if hermitian:
+        z = _complex_z(z, 61)
+    check(D, orc, d, z, -1.3, f"tiny zeta hermitian={hermitian}", hermitian=hermitian)
