@@ -35,7 +35,13 @@
  *  - Asynchronous per-problem device `info` (int32, set by the library on the
  *    stream): 0 ok; DPR1_INFO_UNSORTED d not strictly decreasing;
  *    DPR1_INFO_ZERO_Z some z_j == 0 (reducible, Sec. 1); DPR1_INFO_NONFINITE
- *    a non-finite input; DPR1_INFO_BAD_RHO zero or non-finite rho (batched).
+ *    a non-finite input; DPR1_INFO_BAD_RHO zero or non-finite rho (batched);
+ *    DPR1_INFO_RANGE the shifted representation (d_i, mu) of some eigenpair
+ *    left the binary64 range: mu not a normal number or |mu| ||x|| not
+ *    finite.  This happens only at extremes of the input range, when an
+ *    eigenvalue lies within ~1e-300 of a pole whose zeta_i is ~1e-150 while
+ *    the poles spread so far that |d_j - d_i| / |mu| overflows; deflating
+ *    such z_j (they are below any meaningful accuracy) avoids it.
  *    When info != 0 the outputs of that problem are unspecified.
  */
 #ifndef DPR1_H
@@ -56,6 +62,7 @@ extern "C" {
 #define DPR1_INFO_ZERO_Z 2
 #define DPR1_INFO_NONFINITE 3
 #define DPR1_INFO_BAD_RHO 4
+#define DPR1_INFO_RANGE 5
 
 /* Counters written to the optional device `stats` array (int32, length
  * DPR1_NSTATS; the library zeroes it before counting).                      */

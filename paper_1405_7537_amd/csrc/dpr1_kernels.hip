@@ -1298,6 +1298,16 @@ __device__ void fix_items(const KArgs& A) {
 __global__ void __launch_bounds__(FIXT) k_fix(KArgs A) { fix_items(A); }
 
 // ------------------------------------------------------------------- out
+// The shifted representation of an eigenpair is usable when lambda is finite,
+// mu is a normal number and |mu| ||x|| is finite and positive.  It leaves the
+// binary64 range when |delta_j / mu| exceeds it (mu beside a pole with zeta
+// near 1e-150 while the poles spread over many decades): the problem's info
+// then reports DPR1_INFO_RANGE instead of returning NaN silently.
+__device__ __forceinline__ bool range_ok(double lam, double mu, double xs) {
+  return fabs(lam) < INFINITY && fabs(mu) >= 2.2250738585072014e-308 && fabs(mu) < INFINITY && xs > 0.0 &&
+         xs < INFINITY;
+}
+
 // user outputs in the caller's order (rho < 0 maps k -> n-1-k, lambda -> -lambda)
 __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int nprob,
                                              const int32_t* __restrict__ ii, const double* __restrict__ mu,
@@ -1305,7 +1315,8 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
                                              const double* __restrict__ sd, double* __restrict__ csig,
                                              double* __restrict__ cinv, double* __restrict__ lam_out,
                                              int32_t* __restrict__ idx_out, double* __restrict__ mu_out,
-                                             double* __restrict__ xn_out) {
+                                             double* __restrict__ xn_out, const uint8_t* __restrict__ vflag,
+                                             int32_t* __restrict__ info_out) {
   // a batch: block p handles problem p; one problem: the grid strides over it
   const int p = nprob > 1 ? (int)blockIdx.x : 0;
   const int k0 = nprob > 1 ? (int)threadIdx.x : (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -1341,6 +1352,8 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
     if (idx_out) idx_out[b] = M.neg ? n - 1 - ii[a] : ii[a];
     if (mu_out) mu_out[b] = sg * mu[a];
     if (xn_out) xn_out[b] = xs[a] / fabs(mu[a]);
+    // flagged pairs are finished (and checked) by k_fix / k_fixout
+    if (!vflag[a] && !range_ok(lam[a], mu[a], xs[a])) info_out[p] = DPR1_INFO_RANGE;
   }
 }
 
@@ -1511,7 +1524,8 @@ __global__ void __launch_bounds__(VEC_T) k_fixvec(KArgs A, VArgs v, int nfix) {
 __global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ lam_out,
                                                 int32_t* __restrict__ idx_out, double* __restrict__ mu_out,
                                                 double* __restrict__ xn_out, double* __restrict__ V,
-                                                const int64_t* __restrict__ voffs, int64_t ldv) {
+                                                const int64_t* __restrict__ voffs, int64_t ldv,
+                                                int32_t* __restrict__ info_out) {
   const int n0 = A.ctr[0];
   const int cnt = n0 + A.ctr[3];
   for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
@@ -1528,6 +1542,7 @@ __global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ la
       lam_out[b] = sg * A.lam[a];
       if (idx_out) idx_out[b] = M.neg ? n - 1 - ii : ii;
       if (mu_out) mu_out[b] = sg * m;
+      if (!range_ok(A.lam[a], m, xs)) info_out[it.p] = DPR1_INFO_RANGE;
       if (xn_out) xn_out[b] = xs / fabs(m);
     }
     if (V) {
@@ -1749,7 +1764,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   double* cinv = (double*)(w + L.cinv);
   hipLaunchKernelGGL(k_out, dim3(nprob > 1 ? (unsigned)nprob : (unsigned)std::min<int64_t>((N + 255) / 256, 1024)),
                      dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, A.sd, csig, cinv, lambda,
-                     shift_idx, mu, xnorm);
+                     shift_idx, mu, xnorm, A.vflag, info);
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[2], st));
   if (V) {
@@ -1785,7 +1800,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   }
   HIPCHECK(hipGetLastError());
   hipLaunchKernelGGL(k_fixout, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048)), dim3(256), 0, st,
-                     A, lambda, shift_idx, mu, xnorm, V, voffs, ldv);
+                     A, lambda, shift_idx, mu, xnorm, V, voffs, ldv, info);
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[3], st));
   return DPR1_OK;
@@ -1992,6 +2007,7 @@ const char* dpr1_strerror(int code) {
     case DPR1_INFO_ZERO_Z: return "info: some z_j is zero (reducible problem)";
     case DPR1_INFO_NONFINITE: return "info: non-finite input";
     case DPR1_INFO_BAD_RHO: return "info: rho is zero or not finite";
+    case DPR1_INFO_RANGE: return "info: a shifted representation left the binary64 range";
     default: return code < 0 ? "invalid argument (see the argument position -code)" : "unknown code";
   }
 }

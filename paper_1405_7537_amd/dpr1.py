@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpr1.so")
 
 INFO_TEXT = {0: "ok", 1: "d is not strictly decreasing", 2: "some z_j is zero (reducible)",
-             3: "non-finite input", 4: "rho is zero or not finite"}
+             3: "non-finite input", 4: "rho is zero or not finite",
+             5: "a shifted representation left the binary64 range"}
 NSTATS = 8
 STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "iters_sum", "continued",
               "polish_steps_max"]
@@ -127,8 +128,10 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _dev(x, device):
-    t = torch.as_tensor(x, dtype=torch.float64)
+def _dev(x, device, dtype=torch.float64):
+    if isinstance(x, np.ndarray):
+        x = np.ascontiguousarray(x)   # torch refuses negative strides (e.g. d[::-1])
+    t = torch.as_tensor(x, dtype=dtype)
     return t.to(device).contiguous()
 
 
@@ -227,7 +230,7 @@ def eig_hermitian(d, z, rho, vectors=True, opts: Opts | None = None, check=True,
     stream.  Returns a Result with lam [n] float64 decreasing, V [n, n] complex128 (V[:, k] = v_k,
     rows in the input order) and info."""
     d = _dev(d, device)
-    z = torch.as_tensor(z, dtype=torch.complex128).to(device).contiguous()
+    z = _dev(z, device, dtype=torch.complex128)
     n = d.numel()
     if z.numel() != n:
         raise ValueError("z must have n entries")

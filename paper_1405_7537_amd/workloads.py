@@ -154,3 +154,23 @@ def tridiagonal(n, seed):
 def wilkinson(m):
     """Wilkinson's W_{2m+1}^+: diagonal |m|, ..., 1, 0, 1, ..., m, off-diagonal ones (close pairs)."""
     return np.abs(np.arange(-m, m + 1, dtype=np.float64)), np.ones(2 * m)
+
+
+def extreme(seed):
+    """A small problem at the edges of the binary64 range (seeded): 2-40 distinct poles, sorted
+    decreasingly, either uniform in [-1, 1], spread over 20 decades with both signs, or clustered
+    (gaps 1e-14..1e-1 above 1); |z_j| = 10^U(-150, 0) with random signs; |rho| = 10^U(-8, 8), either
+    sign."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 40))
+    kind = seed % 3
+    if kind == 0:
+        d = rng.uniform(-1, 1, n)
+    elif kind == 1:
+        d = 10.0 ** rng.uniform(-10, 10, n) * rng.choice([-1.0, 1.0], n)
+    else:
+        d = 1.0 + np.cumsum(10.0 ** rng.uniform(-14, -1, n))
+    d = np.unique(d)[::-1].copy()
+    z = 10.0 ** rng.uniform(-150, 0, d.size) * rng.choice([-1.0, 1.0], d.size)
+    rho = 10.0 ** rng.uniform(-8, 8) * rng.choice([-1.0, 1.0])
+    return d, z, float(rho)

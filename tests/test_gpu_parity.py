@@ -270,3 +270,34 @@ def test_single_solve_graph_capture(D):
         for a, b in zip(out, ref):
             assert torch.equal(a, b), rep
         assert int(out[5].item()) == 0
+
+
+def test_extreme_range_is_exact_or_reported(D, orc):
+    """300 problems at the edges of the range (workloads.extreme): each is within the parity bar of
+    the oracle, or reported with DPR1_INFO_RANGE; never NaN with info 0.  One corner stays open:
+    poles clustered to gaps near 1e-13 with a zeta near 1e-149 at one of them, where the oracle
+    itself returns NaN (5-6 of the 100 clustered cases); the GPU's eigenvalue there can sit at the
+    midpoint of the tiny interval.  Those cases are counted, not asserted."""
+    ok = reported = open_corner = 0
+    for seed in range(300):
+        d, z, rho = W.extreme(seed)
+        r = D.eig(d, z, rho, check=False)
+        info = int(r.info.item())
+        lam = r.lam.cpu().numpy()
+        V = r.V.cpu().numpy()
+        if info == 5:
+            reported += 1
+            continue
+        assert info == 0, (seed, info)
+        assert np.all(np.isfinite(lam)) and np.all(np.isfinite(V)), seed
+        lo, Vo = orc.eig(d, z, rho)
+        if not (np.all(np.isfinite(lo)) and np.all(np.isfinite(Vo))):
+            assert seed % 3 == 2, seed          # only the clustered kind
+            open_corner += 1
+            continue
+        assert np.max(rel(lam, lo)) <= LAM_TOL, seed
+        assert np.max(rel(V, Vo)) <= VEC_TOL, seed
+        ok += 1
+    print(f"[parity] extreme range: {ok} within the bar, {reported} reported, {open_corner} in the open corner",
+          flush=True)
+    assert ok >= 240 and open_corner <= 10
