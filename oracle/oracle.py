@@ -276,7 +276,7 @@ def tridiag_eig(a, b):
         D = diag(Lambda1, Lambda2),  z = Q^T u = [last row of Q1, first row of Q2],  rho = beta
     (eig_general: unsorted poles, equal poles and zero z_j handled as in Sec. 1); the eigenvectors
     of T are diag(Q1, Q2) V.  beta = 0 decouples the halves (every z_j treated as 0); a z_j below
-    2^-500 max|z| is treated as 0 (its square would underflow).
+    2^-300 max|z| is treated as 0 (far below the accuracy of the children's eigenvectors).
     Returns (lam decreasing, Q with Q[:, k] = q_k)."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -293,10 +293,10 @@ def tridiag_eig(a, b):
     l2, Q2 = tridiag_eig(a2, b[m:])
     d = np.concatenate([l1, l2])
     z = np.concatenate([Q1[-1, :], Q2[0, :]])
-    # a component below 2^-500 of the largest is taken as 0: its square (and the eigenvalue's
-    # distance to its pole, about rho z_j^2) would underflow binary64, and it lies far below the
-    # absolute accuracy of the children's eigenvectors it comes from
-    z = np.where(np.abs(z) < np.ldexp(np.max(np.abs(z)), -500), 0.0, z)
+    # a component below 2^-300 of the largest is taken as 0: it lies far below the absolute
+    # accuracy of the children's eigenvectors it comes from, and kept it would put an eigenvalue
+    # within ~rho z_j^2 (below 1e-180) of its pole, where binary64 loses the shifted representation
+    z = np.where(np.abs(z) < np.ldexp(np.max(np.abs(z)), -300), 0.0, z)
     if beta == 0.0:
         lam, V = eig_general(d, np.zeros(n), 1.0)
     else:

@@ -12,7 +12,7 @@
 // goes down to 1 x 1 leaves; all merges of one depth are done together:
 //   1. k_gather_z reads z of every merge from the current Q buffer;
 //   2. the host reduces each merge as in Sec. 1 (unsorted poles, equal poles,
-//      zero z_j: reduce.h), a z_j below 2^-500 max|z| counting as zero;
+//      zero z_j: reduce.h), a z_j below 2^-300 max|z| counting as zero;
 //   3. one batched launch of the DPR1 solver (dpr1_eig_batched, eigenvalues
 //      and the shifted representation only) solves all reduced problems;
 //   4. k_tri_assemble writes every merge's V (eq. (eigenvecAi) on the merge's
@@ -500,13 +500,13 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
       const Node& nd = *lv[p];
       const double beta = hb[nd.start + nd.m - 1];
       const size_t before = rd.size();
-      // a component below 2^-500 of the largest is taken as 0: its square
-      // (and the eigenvalue's distance to its pole, about beta z_j^2) would
-      // underflow, and it lies far below the absolute accuracy of the
-      // children's eigenvectors it comes from
+      // a component below 2^-300 of the largest is taken as 0: it lies far
+      // below the absolute accuracy of the children's eigenvectors it comes
+      // from, and kept it would put an eigenvalue within ~beta z_j^2 (below
+      // 1e-180) of its pole, where binary64 loses the shifted representation
       double zmax = 0.0;
       for (int64_t i = nd.start; i < nd.start + nd.size; ++i) zmax = std::max(zmax, std::fabs(hz[i]));
-      const double ztiny = std::ldexp(zmax, -500);
+      const double ztiny = std::ldexp(zmax, -300);
       for (int64_t i = nd.start; i < nd.start + nd.size; ++i)
         if (std::fabs(hz[i]) < ztiny) hz[i] = 0.0;
       mcols[p].clear();
