@@ -450,7 +450,7 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
   std::vector<ANode> anodes;
   std::vector<int4> atab, gtab;
   std::vector<GDesc> gdesc;
-  std::vector<fe::Col> cols, all;
+  std::vector<fe::Col> all;
   std::vector<int64_t> roff, rcnt;  // per merge: offset and size of its reduced problem
   std::vector<std::vector<fe::Col>> mcols;
   std::vector<double> hnew(n);
