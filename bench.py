@@ -64,6 +64,8 @@ def main():
                     help="default launch shape instead of the autotuned one (tuning cache or a fresh tuning run)")
     ap.add_argument("--tune-only", action="store_true",
                     help="fill the tuning cache for every solve this bench times, then exit")
+    ap.add_argument("--launch", default=None,
+                    help="SPLIT,WAVES_PER_SIMD,MAIN_PASSES: time this launch shape instead of the tuned one")
     ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
                     help="copy: a plain device copy of known size, to calibrate HBM byte counters")
     ap.add_argument("--only", default=None, choices=["batched", "fwd_bwd", "general", "tridiag"],
@@ -145,13 +147,16 @@ def main():
     # HBM bytes of one k_eig launch from the FETCH_SIZE / WRITE_SIZE counters,
     # scaled by the copy-kernel calibration; used only while the kernel
     # sources are the ones the counters were taken on
+    # per launch shape (split, waves per SIMD, pass budget): the register
+    # budget changes what stays in registers and so the bytes moved
     traffic = None
+    shape = f"{int(base.split)},{int(base.waves_per_simd) or 4},{int(base.main_passes) or 2}"
     tf = os.path.join(ROOT, "profiles", f"k_eig_n{n}_traffic.txt")
     if os.path.exists(tf):
         try:
             tj = json.load(open(tf))
             if tj.get("source_sha") == source_sha() and tj.get("n") == n:
-                traffic = tj.get("k_eig_bytes")
+                traffic = tj.get("shapes", {}).get(shape, {}).get("k_eig_bytes")
         except Exception:
             traffic = None
 
@@ -255,6 +260,11 @@ def tuned(D, args, d, z, rho, vectors):
     """Options of the timed solves: the autotuned split and pass budget (tuning cache, else a tuning
     run before any timing), or the defaults with --no-tune.  Returns (opts, description)."""
     o = D.opts(root=args.root)
+    if args.launch and vectors:
+        sp, wps, mp = (int(x) for x in args.launch.split(","))
+        o = D.opts(root=args.root, split=sp, waves_per_simd=wps, main_passes=mp)
+        log(f"[bench] launch shape given: split {sp}, waves/SIMD {wps}, main_passes {mp}")
+        return o, {"split": sp, "waves_per_simd": wps, "main_passes": mp, "from_cache": False, "given": True}
     if args.no_tune:
         return o, {"split": "default", "main_passes": "default"}
     from paper_1405_7537_amd import tuning
