@@ -370,12 +370,18 @@ __device__ __forceinline__ double model_root(double m, double Sz, double Spz, do
     A = Rp * x * x;
     B = Rs - Rp * x;
   }
+  // A model whose fitted weight or offset is not finite (R' x^2 overflows
+  // when zeta_i is near 1e-149: R' ~ 1e291, x ~ 1e13) says nothing: NaN
+  // makes the caller take a bisection step instead of reading a zero step
+  // as convergence.
+  if (!(fabs(A) < INFINITY) || !(fabs(B) < INFINITY)) return NAN;
   double lo = fmax(L, fmax(xm, p)), hi = U;
   double t = m;
   for (int q = 0; q < 40; ++q) {
     const double e1 = 1.0 / (t - xm), e2 = 1.0 / (t - p);
     const double a1 = wm * e1, a2 = A * e2;
     const double h = ((bp - t) + B) + (a1 + a2);
+    if (!(h == h)) return NAN;
     if (h == 0.0) break;  // t is a root of the model
     const double hp = -1.0 - (a1 * e1 + a2 * e2);
     if (h > 0.0) lo = t; else hi = t;
