@@ -36,12 +36,13 @@
  *    stream): 0 ok; DPR1_INFO_UNSORTED d not strictly decreasing;
  *    DPR1_INFO_ZERO_Z some z_j == 0 (reducible, Sec. 1); DPR1_INFO_NONFINITE
  *    a non-finite input; DPR1_INFO_BAD_RHO zero or non-finite rho (batched);
- *    DPR1_INFO_RANGE the shifted representation (d_i, mu) of some eigenpair
- *    left the binary64 range: mu not a normal number or |mu| ||x|| not
- *    finite.  This happens only at extremes of the input range, when an
- *    eigenvalue lies within ~1e-300 of a pole whose zeta_i is ~1e-150 while
- *    the poles spread so far that |d_j - d_i| / |mu| overflows; deflating
- *    such z_j (they are below any meaningful accuracy) avoids it.
+ *    DPR1_INFO_RANGE the problem leaves the binary64 range of the method:
+ *    some 0 < |z_j| < 2^-511 (its square is not a normal number), two poles
+ *    closer than 2^-1000, or the shifted representation (d_i, mu) of some
+ *    eigenpair not representable (mu not a normal number, |mu| ||x|| not
+ *    finite: an eigenvalue within ~1e-300 of a pole whose zeta_i is ~1e-150
+ *    while the poles spread over many decades).  Deflating such z_j avoids
+ *    it; dpr1_eig_general does so for |z_j| < 2^-511.
  *    When info != 0 the outputs of that problem are unspecified.
  */
 #ifndef DPR1_H

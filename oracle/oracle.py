@@ -189,10 +189,13 @@ def eig_general(d, z, rho, vectors=True):
     w of z onto ||w|| e_first (a Householder reflection): the pole then appears once in the reduced
     problem, with z = ||w||, and the other vectors of the reflection give ||w||-orthogonal
     eigenvectors for the same eigenvalue.  The reduced problem (strictly decreasing poles, no zero
-    z) is solved by Algorithm 1 (``eig``).  Returns (lam decreasing, V with V[:, k] = v_k).
+    z) is solved by Algorithm 1 (``eig``).  A z_j with |z_j| < 2^-511, whose square is not a normal
+    binary64 number, is deflated like a zero.  Returns (lam decreasing, V with V[:, k] = v_k).
     Ties between equal eigenvalues are in no particular order."""
     d = np.asarray(d, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
+    # |z_j| < 2^-511 counts as zero: its square is not a normal binary64 number
+    z = np.where(np.abs(z) < 2.0 ** -511, 0.0, z)
     n = d.size
     order = np.argsort(-d, kind="stable")            # sorted position s -> original row order[s]
     ds, zs = d[order], z[order]

@@ -245,12 +245,21 @@ static int front_end(const double* d, const double* zdev, const std::vector<doub
                      const std::vector<double>& hz, const double* ph, double rho, int64_t n, double* lambda,
                      double* V, int64_t ldv, int32_t* info, const dpr1_opts* opts, char* w, const GLayout& L,
                      hipStream_t st, void* stream) {
+  // |z_j| < 2^-511 counts as zero: its square is not a normal number, and
+  // the eigenvalue beside d_j would lie within rho z_j^2 of it; the assembly
+  // then reads this deflated z from the workspace
+  std::vector<double> hz0(hz);
+  for (double& x : hz0)
+    if (std::fabs(x) < 0x1p-511) x = 0.0;
+  double* zdef = (double*)(w + L.zabs);
+  GCHECK(hipMemcpyAsync(zdef, hz0.data(), 8 * n, hipMemcpyHostToDevice, st));
+  zdev = zdef;
   std::vector<double> rd, rz;
   std::vector<int32_t> rgrp(n), rpos(n);
   std::vector<double> ru(n);
   std::vector<fe::Col> cols;
   cols.reserve(n);
-  fe::reduce(hd.data(), hz.data(), n, false, rd, rz, rgrp.data(), rpos.data(), ru.data(), cols);
+  fe::reduce(hd.data(), hz0.data(), n, false, rd, rz, rgrp.data(), rpos.data(), ru.data(), cols);
   const int64_t m = (int64_t)rd.size();
 
   // the reduced problem on the GPU: eigenvalues and the shifted representation

@@ -275,10 +275,15 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, int nsplit, const int64
     double dj = d[off + src], zj = z[off + src];
     if (!isfinite(dj) || !isfinite(zj)) f |= 4;
     if (zj == 0.0) f |= 2;
+    // zeta_j^2 must be a normal number (the sums are taken in squares), and
+    // two poles closer than 2^-1000 would put 1/(d_j - d_i) and nu beyond the
+    // binary64 range
+    if (zj != 0.0 && fabs(zj) < 0x1p-511) f |= 8;
     if (j + 1 < n) {
       double dn = d[off + src + (neg ? -1 : 1)];
       // staged order must be strictly decreasing: d_j > d_{j+1} (or -d reversed)
       if (!(neg ? (-dj > -dn) : (dj > dn))) f |= 1;
+      else if (fabs(dj - dn) < 0x1p-1000) f |= 8;
     }
     double ds = neg ? -dj : dj;
     double z2 = zj * zj;
@@ -323,6 +328,7 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, int nsplit, const int64
     else if (fl & 4) code = DPR1_INFO_NONFINITE;
     else if (fl & 1) code = DPR1_INFO_UNSORTED;
     else if (fl & 2) code = DPR1_INFO_ZERO_Z;
+    else if (fl & 8) code = DPR1_INFO_RANGE;
     Meta m;
     m.off = off;
     m.n = (int32_t)n;

@@ -174,3 +174,27 @@ def extreme(seed):
     z = 10.0 ** rng.uniform(-150, 0, d.size) * rng.choice([-1.0, 1.0], d.size)
     rho = 10.0 ** rng.uniform(-8, 8) * rng.choice([-1.0, 1.0])
     return d, z, float(rho)
+
+
+def extreme_wide(seed):
+    """A wider edge problem (seeded): 1-59 distinct poles, uniform in [-1, 1] with |z_j| down to 1e-20,
+    or (other kinds) spread over 60 decades, clustered to gaps of 1e-15, half near 1e-300, or normal
+    times 10^(-5..5), each with |z_j| down to 1e-300; |rho| = 10^U(-12, 12), either sign."""
+    rng = np.random.default_rng(10_000 + seed)
+    n = int(rng.integers(1, 60))
+    kind = seed % 5
+    if kind == 0:
+        d = rng.uniform(-1, 1, n)
+    elif kind == 1:
+        d = 10.0 ** rng.uniform(-30, 30, n) * rng.choice([-1.0, 1.0], n)
+    elif kind == 2:
+        d = 1.0 + np.cumsum(10.0 ** rng.uniform(-15, -1, n))
+    elif kind == 3:
+        d = np.concatenate([rng.uniform(-1, 1, n // 2), 1e-300 * rng.uniform(-1, 1, n - n // 2)])
+    else:
+        d = rng.standard_normal(n) * 10.0 ** rng.integers(-5, 6)
+    d = np.unique(d)[::-1].copy()
+    zl = rng.uniform(-300, 0, d.size) if kind != 0 else rng.uniform(-20, 0, d.size)
+    z = 10.0 ** zl * rng.choice([-1.0, 1.0], d.size)
+    rho = 10.0 ** rng.uniform(-12, 12) * rng.choice([-1.0, 1.0])
+    return d, z, float(rho)

@@ -167,3 +167,41 @@ def test_zeta_spanning_150_decades(D, orc):
     for p in range(24):
         el, ev = check_problem(b, orc, d, z, rho, offs, p)
         assert el <= LAM_TOL and ev <= VEC_TOL, (p, el, ev)
+
+
+def test_wide_edge_batch_is_exact_or_reported(D, orc):
+    """1500 edge problems in one batch (workloads.extreme_wide: poles over 60 decades or 1e-15
+    apart or near 1e-300, |z_j| down to 1e-300, |rho| 1e-12..1e12): every problem is within the
+    parity bar of the oracle or reported with DPR1_INFO_RANGE (never a silent failure), and the
+    uniform kind is always within the bar."""
+    cases = [W.extreme_wide(s) for s in range(1500)]
+    sizes = np.array([c[0].size for c in cases])
+    offs = np.zeros(1501, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    d = np.concatenate([c[0] for c in cases])
+    z = np.concatenate([c[1] for c in cases])
+    rho = np.array([c[2] for c in cases])
+    print(f"[batched] wide edge batch total {offs[-1]}", flush=True)
+    b = D.eig_batched(d, z, rho, offs, check=False)
+    info = b.info.cpu().numpy()
+    ok = reported = 0
+    for p in range(1500):
+        if info[p] == 5:
+            assert p % 5 != 0, p
+            reported += 1
+            continue
+        assert info[p] == 0, (p, info[p])
+        el, ev = check_problem(b, orc, d, z, rho, offs, p)
+        assert el <= LAM_TOL and ev <= VEC_TOL, (p, el, ev)
+        ok += 1
+    print(f"[batched] wide edge batch: {ok} within the bar, {reported} reported", flush=True)
+
+
+def test_range_reports(D):
+    """A z_j whose square is not a normal number, and two poles closer than 2^-1000, are reported."""
+    r = D.eig([1.0, 0.5, 0.0], [1.0, 1e-160, 1.0], 1.0, check=False)
+    assert int(r.info.item()) == 5
+    r = D.eig([1.0, 2e-302, 1e-302, -1.0], [1.0, 1.0, 1.0, 1.0], 1.0, check=False)
+    assert int(r.info.item()) == 5
+    r = D.eig([1.0, 0.5, 0.0], [1.0, 1e-150, 1.0], 1.0, check=False)
+    assert int(r.info.item()) == 0

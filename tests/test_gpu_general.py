@@ -218,3 +218,11 @@ def test_zeta_spanning_150_decades(D, orc, hermitian):
     if hermitian:
         z = _complex_z(z, 61)
     check(D, orc, d, z, -1.3, f"tiny zeta hermitian={hermitian}", hermitian=hermitian)
+
+
+def test_subnormal_square_is_deflated(D, orc):
+    """The front end deflates |z_j| < 2^-511 (its square is not a normal number), as the oracle does."""
+    d = np.array([0.9, 0.3, -0.2, -0.8, 0.1])
+    z = np.array([1.0, 1e-160, 0.7, -3e-200, 0.4])
+    lam, V = check(D, orc, d, z, 1.1, "subnormal squares")
+    assert 0.3 in lam and -0.8 in lam
