@@ -181,7 +181,7 @@ def tip(d, z, rho, i, mode=0):
     return b.value, kb.value
 
 
-def eig_general(d, z, rho, vectors=True):
+def eig_general(d, z, rho, vectors=True, tol=0.0):
     """All eigenpairs of D + rho z z^T for any finite d (any order, repeated values) and any finite
     z (zeros allowed), by the reduction of Sec. 1 of the paper: sort the poles decreasingly (the
     same permutation applied to z), deflate a pole whose z_j is zero (eigenpair (d_j, e_j)), and
@@ -190,7 +190,9 @@ def eig_general(d, z, rho, vectors=True):
     problem, with z = ||w||, and the other vectors of the reflection give ||w||-orthogonal
     eigenvectors for the same eigenvalue.  The reduced problem (strictly decreasing poles, no zero
     z) is solved by Algorithm 1 (``eig``).  A z_j with |z_j| < 2^-511, whose square is not a normal
-    binary64 number, is deflated like a zero.  Returns (lam decreasing, V with V[:, k] = v_k).
+    binary64 number, is deflated like a zero.  With tol > 0 (the divide-and-conquer driver), poles
+    within tol of a group's largest join that group and take its value.  Returns (lam decreasing,
+    V with V[:, k] = v_k).
     Ties between equal eigenvalues are in no particular order."""
     d = np.asarray(d, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
@@ -205,7 +207,7 @@ def eig_general(d, z, rho, vectors=True):
     s = 0
     while s < n:
         e = s + 1
-        while e < n and ds[e] == ds[s]:
+        while e < n and ds[s] - ds[e] <= tol:     # tol = 0: equal poles (Sec. 1)
             e += 1
         w = zs[s:e]
         nw = float(np.sqrt(np.sum(w * w)))
@@ -278,8 +280,9 @@ def tridiag_eig(a, b):
     solve the halves, and with T_h = Q_h Lambda_h Q_h^T merge through the DPR1 problem
         D = diag(Lambda1, Lambda2),  z = Q^T u = [last row of Q1, first row of Q2],  rho = beta
     (eig_general: unsorted poles, equal poles and zero z_j handled as in Sec. 1); the eigenvectors
-    of T are diag(Q1, Q2) V.  beta = 0 decouples the halves (every z_j treated as 0); a z_j below
-    2^-300 max|z| is treated as 0 (far below the accuracy of the children's eigenvectors).
+    of T are diag(Q1, Q2) V.  |beta| <= 8 eps max|d| decouples the halves (every z_j treated as 0);
+    a z_j below 2^-300 max|z| is treated as 0 (far below the accuracy of the children's
+    eigenvectors); poles within 8 eps max|d| are merged like equal ones.
     Returns (lam decreasing, Q with Q[:, k] = q_k)."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -300,10 +303,13 @@ def tridiag_eig(a, b):
     # accuracy of the children's eigenvectors it comes from, and kept it would put an eigenvalue
     # within ~rho z_j^2 (below 1e-180) of its pole, where binary64 loses the shifted representation
     z = np.where(np.abs(z) < np.ldexp(np.max(np.abs(z)), -300), 0.0, z)
-    if beta == 0.0:
-        lam, V = eig_general(d, np.zeros(n), 1.0)
+    # poles within 8 eps max|d| are merged like equal ones: the perturbation is within the
+    # accuracy of the children's eigenvalues (divide and conquer deflation)
+    tol = 8.0 * np.finfo(float).eps * np.max(np.abs(d))
+    if abs(beta) <= tol:          # a negligible coupling decouples the halves
+        lam, V = eig_general(d, np.zeros(n), 1.0, tol=tol)
     else:
-        lam, V = eig_general(d, z, beta)
+        lam, V = eig_general(d, z, beta, tol=tol)
     Q = np.zeros((n, n))
     Q[:m, :] = Q1 @ V[:m, :]
     Q[m:, :] = Q2 @ V[m:, :]

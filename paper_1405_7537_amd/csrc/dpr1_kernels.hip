@@ -1152,7 +1152,12 @@ __device__ void fix_items(const KArgs& A) {
       double cur = nu1;
       if (!(cur > lo && cur < hi)) cur = nu0;
       if (!(cur > lo && cur < hi)) cur = fmid(lo, hi);
-      for (pit = 0; pit < 48; ++pit) {
+      // progress guard: when |g| has not halved over two steps away from the
+      // final Newton phase, the model is not describing g (a pole one ulp
+      // from the shift pole dominates it), and the step is a bisection
+      double gprev = INFINITY;
+      int slow = 0;
+      for (pit = 0; pit < 100; ++pit) {
         dd acc = {0.0, 0.0};
         double sp = 0.0;
         #pragma unroll 4
@@ -1181,6 +1186,9 @@ __device__ void fix_items(const KArgs& A) {
         double gpv = -1.0 - Spz;
         if (gd.hi == 0.0) break;
         if (gd.hi > 0) lo = cur; else hi = cur;
+        const double ag = fabs(gd.hi);
+        slow = ag > 0.5 * gprev ? slow + 1 : 0;
+        gprev = ag;
         double newton = -(gd.hi + gd.lo) / gpv;
         double t;
         if (fabs(newton) <= 0x1p-30 * cur) {
@@ -1194,7 +1202,11 @@ __device__ void fix_items(const KArgs& A) {
           t = xm + u;
         }
         // stay inside the sign bracket and off the pole / rigorous lower end
-        if (!(t >= lo && t <= hi) || !(t > it.lo) || !(t < INFINITY)) t = fmid(lo, hi);
+        if (!(t >= lo && t <= hi) || !(t > it.lo) || !(t < INFINITY) ||
+            (slow >= 2 && fabs(newton) > 0x1p-30 * cur)) {
+          t = fmid(lo, hi);
+          slow = 0;
+        }
         if (t == cur) break;
         cur = t;
       }
@@ -1296,7 +1308,7 @@ __device__ void fix_items(const KArgs& A) {
       if (A.stats) {
         if (polished) {
           atomicAdd(&A.stats[DPR1_STAT_POLISHED], 1);
-          atomicMax(&A.stats[DPR1_STAT_POLISH_STEPS_MAX], min(pit + 1, 48));
+          atomicMax(&A.stats[DPR1_STAT_POLISH_STEPS_MAX], min(pit + 1, 100));
         }
         if (it.flags & FIX_CONTINUE) atomicAdd(&A.stats[DPR1_STAT_CONTINUED], 1);
         if (nz) atomicAdd(&A.stats[DPR1_STAT_NEARZERO], 1);

@@ -12,7 +12,8 @@
 // goes down to 1 x 1 leaves; all merges of one depth are done together:
 //   1. k_gather_z reads z of every merge from the current Q buffer;
 //   2. the host reduces each merge as in Sec. 1 (unsorted poles, equal poles,
-//      zero z_j: reduce.h), a z_j below 2^-300 max|z| counting as zero;
+//      zero z_j: reduce.h), a z_j below 2^-300 max|z| counting as zero and
+//      poles within 8 eps max|d| merged like equal ones;
 //   3. one batched launch of the DPR1 solver (dpr1_eig_batched, eigenvalues
 //      and the shifted representation only) solves all reduced problems;
 //   4. k_tri_assemble writes every merge's V (eq. (eigenvecAi) on the merge's
@@ -453,7 +454,7 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
   std::vector<fe::Col> all;
   std::vector<int64_t> roff, rcnt;  // per merge: offset and size of its reduced problem
   std::vector<std::vector<fe::Col>> mcols;
-  std::vector<double> hnew(n);
+  std::vector<double> hnew(n), hpole(n);
   dpr1_plan plan;
   // host mirrors of contiguous workspace regions, so that each region moves
   // in one copy per depth: the solver's inputs [rd, offsp], its outputs
@@ -510,8 +511,27 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
       for (int64_t i = nd.start; i < nd.start + nd.size; ++i)
         if (std::fabs(hz[i]) < ztiny) hz[i] = 0.0;
       mcols[p].clear();
-      fe::reduce(hlam.data() + nd.start, hz.data() + nd.start, nd.size, beta == 0.0, rd, rz,
-                 hgrp.data() + nd.start, hpos.data() + nd.start, hru.data() + nd.start, mcols[p]);
+      // poles within 8 eps max|d| of each other are merged like equal ones (the
+      // perturbation is within the accuracy of the children's eigenvalues);
+      // each member then takes its group's pole, in hpole for the assembly
+      double dmax = 0.0;
+      for (int64_t i = nd.start; i < nd.start + nd.size; ++i) dmax = std::max(dmax, std::fabs(hlam[i]));
+      const double ptol = 8.0 * 0x1p-52 * dmax;
+      // a coupling |beta| <= 8 eps max|d| decouples the halves (the matrix
+      // changes by less than the children's accuracy)
+      const bool decoupled = std::fabs(beta) <= ptol;
+      fe::reduce(hlam.data() + nd.start, hz.data() + nd.start, nd.size, decoupled, rd, rz,
+                 hgrp.data() + nd.start, hpos.data() + nd.start, hru.data() + nd.start, mcols[p], ptol);
+      {
+        std::vector<double> gval(nd.size, 0.0);
+        std::vector<char> seen(nd.size, 0);
+        for (int64_t i = 0; i < nd.size; ++i) {
+          const int g = hgrp[nd.start + i];
+          if (!seen[g] || hlam[nd.start + i] > gval[g]) gval[g] = hlam[nd.start + i];
+          seen[g] = 1;
+        }
+        for (int64_t i = 0; i < nd.size; ++i) hpole[nd.start + i] = gval[hgrp[nd.start + i]];
+      }
       roff[p] = (int64_t)before;
       rcnt[p] = (int64_t)(rd.size() - before);
       if (rcnt[p] > 0) {
@@ -561,7 +581,7 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
 
     // 4. columns of every merge, the new eigenvalues, the assembly and GEMM tables
     put(mirZ, L.zl, L.zl, hz.data(), 8 * n);     // z as reduced
-    put(mirZ, L.zl, L.dl, hlam.data(), 8 * n);   // the merges' poles
+    put(mirZ, L.zl, L.dl, hpole.data(), 8 * n);  // the merges' poles (grouped)
     TCHECK(hipMemcpyAsync(w + L.zl, mirZ.data(), mirZ.size(), hipMemcpyHostToDevice, st));
     anodes.clear();
     atab.clear();

@@ -80,20 +80,24 @@ inline void sort_decreasing(const double* d, int64_t n, std::vector<int64_t>& or
   }
 }
 
-// Reduce one problem (host d, z of length n; zero_all treats every z_j as 0).
+// Reduce one problem (host d, z of length n; zero_all treats every z_j as 0;
+// poles within tol of a group's largest are merged into that group).
 // Appends the reduced poles and z to rd, rz (decreasing poles, no zero z);
 // writes per row i: rgrp[i] group id (local), rpos[i] position in the group,
 // ru[i] reflection component (0 for groups without one); appends the
 // deflated and reflected columns to cols in decreasing pole order.
 inline void reduce(const double* hd, const double* hz, int64_t n, bool zero_all, std::vector<double>& rd,
-                   std::vector<double>& rz, int32_t* rgrp, int32_t* rpos, double* ru, std::vector<Col>& cols) {
+                   std::vector<double>& rz, int32_t* rgrp, int32_t* rpos, double* ru, std::vector<Col>& cols,
+                   double tol = 0.0) {
   std::vector<int64_t> order;
   sort_decreasing(hd, n, order);
   std::vector<double> u;
   int32_t ngrp = 0;
   for (int64_t s = 0; s < n;) {
     int64_t e = s + 1;
-    while (e < n && hd[order[e]] == hd[order[s]]) ++e;
+    // tol = 0: equal poles only (Sec. 1); tol > 0 (divide and conquer): poles
+    // within tol of the group's first join it and take its value
+    while (e < n && hd[order[s]] - hd[order[e]] <= tol) ++e;
     const double dv = hd[order[s]];
     // ||w|| scaled by the largest |w_t|, so that no square overflows
     double big = 0.0, nw = 0.0;

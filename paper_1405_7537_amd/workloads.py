@@ -198,3 +198,33 @@ def extreme_wide(seed):
     z = 10.0 ** zl * rng.choice([-1.0, 1.0], d.size)
     rho = 10.0 ** rng.uniform(-12, 12) * rng.choice([-1.0, 1.0])
     return d, z, float(rho)
+
+
+def tridiagonal_family(seed):
+    """Structured symmetric tridiagonal matrices that stress divide-and-conquer merges (seeded):
+    kind = seed % 7: 0 random, 1 graded off-diagonal (1 .. 1e-20), 2 glued Wilkinson W21+ blocks
+    (couplings 1e-8), 3 couplings 10^U(-300, 0) with 10 % zeros, 4 diagonal over 20 decades,
+    5 constant diagonal with 1e-6 couplings, 6 the 1-2-1 matrix.  Returns (a, b)."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(2, 700))
+    k = seed % 7
+    if k == 0:
+        a, b = rng.standard_normal(n), rng.standard_normal(n - 1)
+    elif k == 1:
+        a, b = rng.standard_normal(n), 10.0 ** (-np.linspace(0, 20, n - 1))
+    elif k == 2:
+        m = 10
+        blk = np.abs(np.arange(-m, m + 1, dtype=np.float64))
+        a = np.tile(blk, max(1, n // 21))
+        b = np.ones(a.size - 1)
+        b[20::21] = 1e-8
+    elif k == 3:
+        a, b = rng.standard_normal(n), rng.standard_normal(n - 1) * 10.0 ** rng.uniform(-300, 0, n - 1)
+        b[rng.random(n - 1) < 0.1] = 0.0
+    elif k == 4:
+        a, b = 10.0 ** rng.uniform(-10, 10, n) * rng.choice([-1.0, 1.0], n), rng.standard_normal(n - 1)
+    elif k == 5:
+        a, b = np.ones(n), 1e-6 * rng.standard_normal(n - 1)
+    else:
+        a, b = 2.0 * np.ones(n), -np.ones(n - 1)
+    return a, b

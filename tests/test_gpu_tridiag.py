@@ -136,3 +136,22 @@ def test_large_uneven_and_clustered(D, case):
     res = (Td @ Qd - Qd * r.lam).abs().max().item() / nt
     print(f"[tridiag] {case}: lam {el:.2e} orth {orth:.2e} res {res:.2e}", flush=True)
     assert el <= 1e-12 and orth <= 1e-11 and res <= 1e-11
+
+
+def test_structured_families(D):
+    """35 structured matrices (workloads.tridiagonal_family, 5 of each of 7 kinds: graded, glued
+    Wilkinson, tiny and zero couplings, wide diagonal, constant diagonal, 1-2-1): eigenvalues against
+    LAPACK on the dense T, Q^T Q = I and T Q = Q Lambda."""
+    worst = np.zeros(3)
+    for s in range(35):
+        a, b = W.tridiagonal_family(s)
+        n = a.size
+        r = D.tridiag_eig(a, b)
+        lam, Q = r.lam.cpu().numpy(), r.Q.cpu().numpy()
+        T = dense(a, b)
+        L = np.sort(np.linalg.eigvalsh(T))[::-1]
+        nt = np.max(np.abs(L))
+        m = (np.max(np.abs(lam - L)) / nt, np.max(np.abs(Q.T @ Q - np.eye(n))), np.max(np.abs(T @ Q - Q * lam)) / nt)
+        worst = np.maximum(worst, m)
+        assert m[0] <= 1e-12 and m[1] <= 1e-12 and m[2] <= 1e-12, (s, n, m)
+    print(f"[tridiag] families: lam {worst[0]:.1e} orth {worst[1]:.1e} res {worst[2]:.1e}", flush=True)

@@ -520,3 +520,13 @@ def test_bracket_with_huge_tip(orc):
         L = np.array([float(x) for x in T.dense_values(d, z, rho, dps=60)])
         assert np.max(np.abs(lam - L) / np.abs(L)) <= 4e-16, (rho, lam, L)
         assert np.max(np.abs(V.T @ V - np.eye(5))) <= 1e-15
+
+
+def test_tridiag_dc_one_two_one_closed_form(orc):
+    """The 1-2-1 matrix (identical halves: merges with equal and nearly equal poles) has the
+    eigenvalues 2 - 2 cos(k pi / (n + 1))."""
+    for n in (8, 37, 64):
+        lam, Q = orc.tridiag_eig(2.0 * np.ones(n), -np.ones(n - 1))
+        exact = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1]
+        assert np.max(np.abs(lam - exact)) <= 1e-14
+        assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-14
