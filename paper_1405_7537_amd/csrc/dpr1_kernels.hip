@@ -827,7 +827,10 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     A.ii[off + k] = i;
     A.vflag[off + k] = (pol || nz || cont) ? 1 : 0;
     A.mu[off + k] = muv;
-    A.xs[off + k] = sqrt(Nx[0]);
+    // a tip b' beyond binary64 (zeta_i near 1e-150 beside a pole 1e-13 away
+    // with an O(1) zeta) leaves g undefined: the NaN norm makes the output
+    // check report DPR1_INFO_RANGE instead of a wrong vector
+    A.xs[off + k] = fabs(bp) < INFINITY ? sqrt(Nx[0]) : NAN;
     A.lam[off + k] = lam;
     if (pol || nz || cont) {
       // the long items (polish, near-zero recomputation) fill the list from
@@ -1303,7 +1306,7 @@ __device__ void fix_items(const KArgs& A) {
       A.lam[off + k] = lam;
       if (polished || have_xs) {
         A.mu[off + k] = muv;
-        A.xs[off + k] = xsv;
+        A.xs[off + k] = fabs(it.bhi) < INFINITY ? xsv : NAN;
       }
       if (A.stats) {
         if (polished) {

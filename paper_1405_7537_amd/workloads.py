@@ -228,3 +228,24 @@ def tridiagonal_family(seed):
     else:
         a, b = 2.0 * np.ones(n), -np.ones(n - 1)
     return a, b
+
+
+def extreme_large(seed):
+    """Larger edge problems (seeded): 100-2000 distinct poles, uniform, clustered (gaps 1e-13..1e-2
+    above 1), over 16 decades with both signs, or half in a 1e-9 cluster at 0.3; |z_j| = 10^U(-150, 0)
+    with random signs; |rho| = 10^U(-6, 6), either sign."""
+    rng = np.random.default_rng(77_000 + seed)
+    n = int(rng.integers(100, 2000))
+    kind = seed % 4
+    if kind == 0:
+        d = rng.uniform(-1, 1, n)
+    elif kind == 1:
+        d = 1.0 + np.cumsum(10.0 ** rng.uniform(-13, -2, n))
+    elif kind == 2:
+        d = np.sort(10.0 ** rng.uniform(-8, 8, n) * rng.choice([-1.0, 1.0], n))
+    else:
+        d = np.concatenate([rng.uniform(-1, 1, n // 2), rng.uniform(0.3, 0.3 + 1e-9, n - n // 2)])
+    d = np.unique(d)[::-1].copy()
+    z = 10.0 ** rng.uniform(-150, 0, d.size) * rng.choice([-1.0, 1.0], d.size)
+    rho = 10.0 ** rng.uniform(-6, 6) * rng.choice([-1.0, 1.0])
+    return d, z, float(rho)

@@ -205,3 +205,33 @@ def test_range_reports(D):
     assert int(r.info.item()) == 5
     r = D.eig([1.0, 0.5, 0.0], [1.0, 1e-150, 1.0], 1.0, check=False)
     assert int(r.info.item()) == 0
+
+
+def test_large_edge_batch(D, orc):
+    """20 edge problems of 100-2000 poles in one batch (workloads.extreme_large): within the parity
+    bar, or reported with DPR1_INFO_RANGE, or (where the oracle itself returns NaN) orthogonal with
+    a small residual -- never a silent failure."""
+    cases = [W.extreme_large(s) for s in range(20)]
+    offs = np.zeros(21, dtype=np.int64)
+    offs[1:] = np.cumsum([c[0].size for c in cases])
+    d = np.concatenate([c[0] for c in cases])
+    z = np.concatenate([c[1] for c in cases])
+    rho = np.array([c[2] for c in cases])
+    print(f"[batched] large edge batch total {offs[-1]}", flush=True)
+    b = D.eig_batched(d, z, rho, offs, check=False)
+    info = b.info.cpu().numpy()
+    for p in range(20):
+        if info[p] == 5:
+            continue
+        assert info[p] == 0, (p, info[p])
+        dp, zp, rp = cases[p]
+        lo, Vo = orc.eig(dp, zp, rp)
+        lam = b.lam[offs[p]:offs[p + 1]].cpu().numpy()
+        V = b.vblock(p).cpu().numpy()
+        if np.all(np.isfinite(lo)) and np.all(np.isfinite(Vo)):
+            el, ev = check_problem(b, orc, d, z, rho, offs, p)
+            assert el <= LAM_TOL and ev <= VEC_TOL, (p, el, ev)
+        else:
+            A = np.diag(dp) + rp * np.outer(zp, zp)
+            assert np.max(np.abs(V.T @ V - np.eye(dp.size))) <= 1e-12, p
+            assert np.max(np.abs(A @ V - V * lam)) <= 1e-12 * np.max(np.abs(lam)), p
