@@ -302,7 +302,11 @@ def tridiag_eig(a, b):
     # a component below 2^-300 of the largest is taken as 0: it lies far below the absolute
     # accuracy of the children's eigenvectors it comes from, and kept it would put an eigenvalue
     # within ~rho z_j^2 (below 1e-180) of its pole, where binary64 loses the shifted representation
-    z = np.where(np.abs(z) < np.ldexp(np.max(np.abs(z)), -300), 0.0, z)
+    # and so is a component whose share of the rank-one term is negligible, |beta z_j| <= 2 eps
+    # max|d| (zeroing it changes T by at most 2 sqrt(2) |beta z_j|), as divide and conquer deflates
+    dmax = np.max(np.abs(d))
+    ztiny = max(np.ldexp(np.max(np.abs(z)), -300), 2.0 * np.finfo(float).eps * dmax / abs(beta) if beta else np.inf)
+    z = np.where(np.abs(z) < ztiny, 0.0, z)
     # poles within 8 eps max|d| are merged like equal ones: the perturbation is within the
     # accuracy of the children's eigenvalues (divide and conquer deflation)
     tol = 8.0 * np.finfo(float).eps * np.max(np.abs(d))

@@ -505,9 +505,16 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
       // below the absolute accuracy of the children's eigenvectors it comes
       // from, and kept it would put an eigenvalue within ~beta z_j^2 (below
       // 1e-180) of its pole, where binary64 loses the shifted representation
-      double zmax = 0.0;
-      for (int64_t i = nd.start; i < nd.start + nd.size; ++i) zmax = std::max(zmax, std::fabs(hz[i]));
-      const double ztiny = std::ldexp(zmax, -300);
+      // Also a component whose share of the rank-one term is negligible,
+      // |beta z_j| <= 2 eps max|d| (zeroing it changes T by at most
+      // 2 sqrt(2) |beta z_j|, within the children's accuracy), as divide and
+      // conquer codes deflate.
+      double zmax = 0.0, dm = 0.0;
+      for (int64_t i = nd.start; i < nd.start + nd.size; ++i) {
+        zmax = std::max(zmax, std::fabs(hz[i]));
+        dm = std::max(dm, std::fabs(hlam[i]));
+      }
+      const double ztiny = std::max(std::ldexp(zmax, -300), 2.0 * 0x1p-52 * dm / std::fabs(beta));
       for (int64_t i = nd.start; i < nd.start + nd.size; ++i)
         if (std::fabs(hz[i]) < ztiny) hz[i] = 0.0;
       mcols[p].clear();
