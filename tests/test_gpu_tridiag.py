@@ -155,3 +155,27 @@ def test_structured_families(D):
         worst = np.maximum(worst, m)
         assert m[0] <= 1e-12 and m[1] <= 1e-12 and m[2] <= 1e-12, (s, n, m)
     print(f"[tridiag] families: lam {worst[0]:.1e} orth {worst[1]:.1e} res {worst[2]:.1e}", flush=True)
+
+
+@pytest.mark.parametrize("kind", ["one_two_one", "graded"])
+def test_structured_large(D, kind):
+    """n = 3000: the 1-2-1 matrix (closed-form spectrum 2 - 2 cos(k pi/(n+1))) and a graded
+    off-diagonal (1 .. 1e-20): eigenvalues, Q^T Q = I and T Q = Q Lambda."""
+    import torch
+    n = 3000
+    if kind == "one_two_one":
+        a, b = 2.0 * np.ones(n), -np.ones(n - 1)
+        L = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1]
+    else:
+        rng = np.random.default_rng(3000)
+        a, b = rng.standard_normal(n), 10.0 ** (-np.linspace(0, 20, n - 1))
+        L = np.sort(np.linalg.eigvalsh(dense(a, b)))[::-1]
+    print(f"[tridiag] {kind} n={n}", flush=True)
+    r = D.tridiag_eig(a, b)
+    nt = np.max(np.abs(L))
+    el = np.max(np.abs(r.lam.cpu().numpy() - L)) / nt
+    Q = r.Q
+    orth = (Q.T @ Q - torch.eye(n, dtype=torch.float64, device=Q.device)).abs().max().item()
+    res = (torch.as_tensor(dense(a, b), device=Q.device) @ Q - Q * r.lam).abs().max().item() / nt
+    print(f"[tridiag] {kind}: lam {el:.1e} orth {orth:.1e} res {res:.1e}", flush=True)
+    assert el <= 1e-13 and orth <= 1e-12 and res <= 1e-12
