@@ -16,7 +16,8 @@
  *  - All array arguments are DEVICE pointers unless the name ends in _host.
  *    The caller owns every buffer.  The library allocates no device memory:
  *    it uses the caller's workspace, whose size the *_workspace_size queries
- *    return.  Workspace contents need not be initialised.
+ *    return (dpr1_eig_noalloc: a static device array of the library).
+ *    Workspace contents need not be initialised.
  *  - All work is enqueued asynchronously on `stream` (a hipStream_t passed as
  *    void*; NULL = the default stream).  No call synchronises the host, so the
  *    launches may be captured into a hipGraph, except dpr1_batched_plan (it
@@ -57,6 +58,7 @@ extern "C" {
 
 #define DPR1_OK 0
 #define DPR1_EHIP (-1000)
+#define DPR1_ETOOBIG (-1001) /* n above DPR1_NOALLOC_MAX_N (dpr1_eig_noalloc) */
 
 #define DPR1_INFO_OK 0
 #define DPR1_INFO_UNSORTED 1
@@ -143,6 +145,29 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
              double* V, int64_t ldv, int32_t* shift_idx, double* mu, double* xnorm,
              int32_t* info, int32_t* stats, const dpr1_opts* opts, void* work,
              size_t work_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dpr1_eig
+ * without the workspace argument.  Its workspace is a static device array of
+ * the library, dpr1_noalloc_scratch_bytes() bytes (about 6.2 MB, sized for
+ * n = DPR1_NOALLOC_MAX_N), of which every GPU the library runs on holds its
+ * own copy until the process ends.  The call allocates nothing (no hipMalloc,
+ * no allocating library routine); on its first use on a device it looks up
+ * that device's copy of the array (hipGetSymbolAddress) and keeps the
+ * address.  Arguments, outputs, info codes and results are those of
+ * dpr1_eig with the same options (the same kernels run on the same data).
+ * Returns DPR1_ETOOBIG when n > DPR1_NOALLOC_MAX_N, the other codes as
+ * dpr1_eig (-4 for n < 1, -13 for an invalid waves_per_simd), DPR1_EHIP when
+ * the array cannot be reached.  All calls on one GPU share its array and the
+ * array keeps the last call's contents (the solve clears its own counters):
+ * calls that overlap on one GPU (different streams, or host threads, without
+ * ordering between them) race and give undefined results; calls ordered on
+ * one stream are safe.                                                      */
+#define DPR1_NOALLOC_MAX_N 32768
+size_t dpr1_noalloc_scratch_bytes(void);
+int dpr1_eig_noalloc(const double* d, const double* z, double rho, int64_t n, double* lambda,
+                     double* V, int64_t ldv, int32_t* shift_idx, double* mu, double* xnorm,
+                     int32_t* info, int32_t* stats, const dpr1_opts* opts, void* stream);
 
 /* Batched: nprob independent problems of sizes n_p packed back to back
  * (problem p occupies [offs[p], offs[p+1]) of d, z, lambda, shift_idx, mu,

@@ -32,6 +32,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/dpr1.h"
@@ -1595,10 +1596,10 @@ struct Layout {
   size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, csig, cinv, fix, vflag, items, groups, part, ctr, total;
 };
 
-static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+static constexpr size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-static Layout layout(int64_t nprob, int64_t N, int64_t nitems, int64_t ngroups = 0) {
-  Layout L;
+static constexpr Layout layout(int64_t nprob, int64_t N, int64_t nitems, int64_t ngroups = 0) {
+  Layout L{};
   size_t o = 0;
   L.meta = o; o = al(o + sizeof(Meta) * nprob);
   L.sd = o; o = al(o + 8 * N);
@@ -1703,6 +1704,32 @@ static int64_t count_groups(int64_t nprob, const int64_t* offs) {
 // RED_NV values per lane and wave.
 constexpr int RED_NV = 4;
 static size_t red_bytes(int W) { return W > 1 ? sizeof(double) * RED_NV * W * WAVE : 0; }
+
+// Workspace of dpr1_eig_noalloc: a device array of the library, sized for the
+// largest problem it accepts.  Every GPU holds its own copy for the life of
+// the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the name itself is a host-side
+// stand-in, not a device address).
+constexpr size_t NOALLOC_BYTES = layout(1, DPR1_NOALLOC_MAX_N, 0).total;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex scratch_mutex;
+static void* scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of `scratch` on the current device, resolved once per device
+// (nullptr on a HIP error or an out-of-range device index).
+static void* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    scratch_ptr[dev] = p;
+  }
+  return scratch_ptr[dev];
+}
 
 }  // namespace dpr1
 
@@ -1849,6 +1876,33 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
   dpr1_opts o;
   fill_opts(opts, &o);
   if (!occ_valid(o.waves_per_simd)) return -13;
+  int64_t nblocks = (n + WAVE - 1) / WAVE;
+  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
+  return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
+                      mu, xnorm, info, stats, o, W, nblocks, 0, 0, (hipStream_t)stream);
+}
+
+size_t dpr1_noalloc_scratch_bytes(void) { return NOALLOC_BYTES; }
+
+// dpr1_eig on the library's static device scratch instead of a workspace
+// argument: the same checks, kernels and results; no allocation of any kind.
+int dpr1_eig_noalloc(const double* d, const double* z, double rho, int64_t n, double* lambda, double* V,
+                     int64_t ldv, int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, int32_t* stats,
+                     const dpr1_opts* opts, void* stream) {
+  if (!d) return -1;
+  if (!z) return -2;
+  if (!(rho == rho) || rho == 0.0 || rho == INFINITY || rho == -INFINITY) return -3;
+  if (n < 1) return -4;
+  if (n > DPR1_NOALLOC_MAX_N) return DPR1_ETOOBIG;
+  if (!lambda) return -5;
+  if (V && ldv < n) return -7;
+  if (!info) return -11;
+  dpr1_opts o;
+  fill_opts(opts, &o);
+  if (!occ_valid(o.waves_per_simd)) return -13;
+  void* work = scratch_on_current_device();
+  if (!work) return DPR1_EHIP;
+  const Layout L = layout(1, n, 0);
   int64_t nblocks = (n + WAVE - 1) / WAVE;
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
   return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
@@ -2030,6 +2084,7 @@ const char* dpr1_strerror(int code) {
   switch (code) {
     case DPR1_OK: return "ok";
     case DPR1_EHIP: return "a HIP runtime call or kernel launch failed";
+    case DPR1_ETOOBIG: return "n exceeds DPR1_NOALLOC_MAX_N, the size of the static scratch of dpr1_eig_noalloc";
     case DPR1_INFO_UNSORTED: return "info: d is not strictly decreasing";
     case DPR1_INFO_ZERO_Z: return "info: some z_j is zero (reducible problem)";
     case DPR1_INFO_NONFINITE: return "info: non-finite input";

@@ -52,6 +52,10 @@ def lib():
         L.dpr1_workspace_size.restype = C.c_size_t
         L.dpr1_eig.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, vp, vp, vp, vp,
                                C.POINTER(Opts), vp, C.c_size_t, vp]
+        L.dpr1_noalloc_scratch_bytes.argtypes = []
+        L.dpr1_noalloc_scratch_bytes.restype = C.c_size_t
+        L.dpr1_eig_noalloc.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, vp, vp, vp, vp,
+                                       C.POINTER(Opts), vp]
         L.dpr1_batched_workspace_size.argtypes = [i64, C.POINTER(C.c_int64)]
         L.dpr1_batched_workspace_size.restype = C.c_size_t
         L.dpr1_batched_plan.argtypes = [i64, C.POINTER(C.c_int64), C.POINTER(Opts), C.POINTER(Plan),
@@ -195,6 +199,39 @@ def eig(d, z, rho, vectors=True, opts: Opts | None = None, check=True, want_stat
         code = int(info.item())
         if code != 0:
             raise ValueError(f"dpr1_eig: info = {code} ({INFO_TEXT.get(code, '?')})")
+    return r
+
+
+NOALLOC_MAX_N = 32768
+
+
+def eig_noalloc(d, z, rho, vectors=True, opts: Opts | None = None, check=True, out=None, device="cuda"):
+    """dpr1_eig_noalloc: as eig(), with the library's static device scratch as workspace (n <=
+    NOALLOC_MAX_N).  With `out` = (lam, Vt, shift_idx, mu, xnorm, info) preallocated, the call
+    itself allocates nothing."""
+    d = _dev(d, device)
+    z = _dev(z, device)
+    n = d.numel()
+    dev = d.device
+    if out is None:
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        Vt = torch.empty((n, n), dtype=torch.float64, device=dev) if vectors else None
+        idx = torch.empty(n, dtype=torch.int32, device=dev)
+        mu = torch.empty(n, dtype=torch.float64, device=dev)
+        xn = torch.empty(n, dtype=torch.float64, device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+    else:
+        lam, Vt, idx, mu, xn, info = out
+    ld = max(n, 1) if Vt is None or n <= 1 else Vt.stride(0)
+    rc = lib().dpr1_eig_noalloc(_ptr(d), _ptr(z), float(rho), n, _ptr(lam), _ptr(Vt), ld, _ptr(idx), _ptr(mu),
+                                _ptr(xn), _ptr(info), None, C.byref(opts) if opts is not None else None,
+                                _stream())
+    _rc(rc, "dpr1_eig_noalloc")
+    r = Result(lam=lam, V=Vt.t() if Vt is not None else None, shift_idx=idx, mu=mu, xnorm=xn, info=info)
+    if check:
+        code = int(info.item())
+        if code != 0:
+            raise ValueError(f"dpr1_eig_noalloc: info = {code} ({INFO_TEXT.get(code, '?')})")
     return r
 
 

@@ -123,3 +123,25 @@ def test_general_front_end_argument_errors_need_no_gpu(lib):
     assert lib.dpr1_eig_hermitian(None, fake, 1.0, 4, fake, None, 4, fake, None, fake, big, None) == -1
     assert lib.dpr1_eig_hermitian(fake, fake, float("nan"), 4, fake, None, 4, fake, None, fake, big, None) == -3
     assert lib.dpr1_eig_hermitian(fake, fake, 1.0, 4, fake, None, 4, fake, None, fake, 16, None) == -11
+
+
+def test_noalloc_limits_need_no_gpu(lib):
+    """dpr1_eig_noalloc: its scratch holds the workspace of the largest accepted n, and larger
+    problems are refused (DPR1_ETOOBIG) before any device work."""
+    lib.dpr1_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    lib.dpr1_workspace_size.argtypes = [ctypes.c_int64]
+    lib.dpr1_workspace_size.restype = ctypes.c_size_t
+    src = open(HDR).read()
+    nmax = int(re.search(r"#define DPR1_NOALLOC_MAX_N (\d+)", src).group(1))
+    assert lib.dpr1_noalloc_scratch_bytes() == lib.dpr1_workspace_size(nmax)
+    assert lib.dpr1_noalloc_scratch_bytes() < 16 << 20
+    vp = ctypes.c_void_p
+    lib.dpr1_eig_noalloc.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64,
+                                     vp, vp, vp, vp, vp, vp, vp]
+    fake = vp(16)
+    assert lib.dpr1_eig_noalloc(fake, fake, 1.0, nmax + 1, fake, None, 0, None, None, None, fake,
+                                None, None, None) == -1001
+    assert lib.dpr1_eig_noalloc(fake, fake, 1.0, 0, fake, None, 0, None, None, None, fake,
+                                None, None, None) == -4
+    assert lib.dpr1_eig_noalloc(None, fake, 1.0, 5, fake, None, 0, None, None, None, fake,
+                                None, None, None) == -1
