@@ -41,6 +41,15 @@
  *    where (R1) is impossible (there is no pole on the other side).
  *  - The near-zero rule (Alg. 1, last test) fires when
  *    10*|lambda| < min |lambda - neighbouring pole|.
+ *  - Range of the arrowhead inverse (eq. invAi, secAi): with a tiny zeta_i
+ *    beside a close pole the arrow w_j = -zeta_j/(zeta_i delta_j) can exceed
+ *    2^511 (zeta_i near 1e-150 beside a pole 1e-13 away gives 1e162), so its
+ *    square, and the terms of g, leave binary64 although the eigenpair does
+ *    not.  For such an eigenpair the whole secular function -- its bracket,
+ *    every evaluation of g for the bisection and the Newton step -- is carried
+ *    in binary128 (exponent range 1e+-4932) from the exact shifted
+ *    differences, with the binary128 tip (there is no binary64 b to gate).
+ *    Every other eigenpair is computed in binary64 exactly as above.
  */
 #include <float.h>
 #include <math.h>
@@ -169,27 +178,31 @@ static void g_comp(const arrow_t* A, double nu, double* g, double* gp, double* k
   double S = s + c;
   *g = (A->b - nu) - S;
   *gp = -1.0 - sp;
-  *kap = (fabs(A->b) + fabs(nu) + sabs) / (fabs(nu) * fabs(*gp));
+  /* in two divisions: |nu| |g'| alone can overflow when nu nears 1e304 */
+  *kap = ((fabs(A->b) + fabs(nu) + sabs) / fabs(nu)) / fabs(*gp);
 }
 
 /* g evaluated entirely in binary128 at a binary64 point nu, with the entries
  * of A_i^{-1} formed in binary128 from the binary64 data (double the
  * working precision, Sec. 2.3). */
 static void g_quad(const double* d, const double* z, const arrow_t* A, double nu,
-                   quad* g, quad* gp) {
+                   quad* g, quad* gp, quad* sabs) {
   quad zi = (quad)z[A->i];
-  quad s = 0, sp = 0, nq = (quad)nu;
+  quad s = 0, sp = 0, sa = 0, nq = (quad)nu;
   for (int64_t j = 0; j < A->n; ++j) {
     if (j == A->i) continue;
     quad dl = (quad)d[j] - (quad)A->sigma;
     quad xi = 1 / dl;
     quad w = -(quad)z[j] / (zi * dl);
     quad den = xi - nq;
-    s += w * w / den;
+    quad t = w * w / den;
+    s += t;
+    sa += t < 0 ? -t : t;
     sp += w * w / (den * den);
   }
   *g = (A->bq - nq) - s;
   *gp = -1 - sp;
+  if (sabs) *sabs = sa;
 }
 
 /* b from eq. (b_ob) in binary128: (1/zeta_i^2)(1/rho + sum_{j!=i} zeta_j^2/(d_j - sigma)). */
@@ -276,6 +289,16 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
   else use_ext = 0;
   A.b = use_ext ? (double)A.bq : b64;
   if (!use_ext) A.bq = (quad)b64;   /* the polish then sees the b in use */
+  /* An arrow entry whose square leaves binary64 (|w_j| >= 2^511), or a tip
+   * beyond binary64: the secular function is carried in binary128. */
+  int wide = !(fabs(A.b) < INFINITY);
+  for (int64_t j = 0; j < n && !wide; ++j)
+    if (j != i && !(fabs(A.w[j]) < 0x1p+511)) wide = 1;
+  if (wide) {
+    A.bq = b_quad(d, z, n, i, sigma, rho);
+    A.b = (double)A.bq;
+    use_ext = 1;
+  }
   dg.used_ext_b = use_ext;
   dg.Kb = use_ext ? Kb_acc : Kb64;
   {
@@ -316,11 +339,35 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
     wn = wmax * sqrt(acc);
   }
   const double grow = 1.0 + 0x1p-40;
+  /* Far end of the bracket: the same 2x2 bound.  On the binary128 path it is
+   * formed in binary128 from the exact shifted differences (||w|| can exceed
+   * binary64 there) and rounded outwards; beyond binary64 it is the largest
+   * finite number. */
+  double far = 0.0;
+  if (wide) {
+    quad zq = (quad)zi, w2 = 0, xe = (side > 0) ? -(quad)INFINITY : (quad)INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      quad dl = (quad)d[j] - (quad)sigma;
+      quad wq = (quad)z[j] / (zq * dl);
+      w2 += wq * wq;
+      quad xq = 1 / dl;
+      if (side > 0 ? xq > xe : xq < xe) xe = xq;
+    }
+    quad wnq = sqrtq(w2);
+    quad hq = fabsq(A.bq - xe) / 2;
+    quad mq = (side > 0) ? (A.bq > xe ? A.bq : xe) : (A.bq < xe ? A.bq : xe);
+    quad tq = wnq > 0 ? wnq * (wnq / (hq + sqrtq(hq * hq + wnq * wnq))) : 0;
+    quad fq = (side > 0) ? (mq + tq) * (1 + (quad)0x1p-100) : (mq - tq) * (1 + (quad)0x1p-100);
+    if (fq > (quad)DBL_MAX) far = DBL_MAX;
+    else if (fq < -(quad)DBL_MAX) far = -DBL_MAX;
+    else far = (double)fq * (side > 0 ? (fq > 0 ? grow : 1 / grow) : (fq < 0 ? grow : 1 / grow));
+  }
   double L, U;
   if (side > 0) {
     double h = fabs(A.b - xmax) / 2;
     double m = fmax(A.b, xmax), t = wn > 0.0 ? wn * (wn / (h + hypot(h, wn))) : 0.0;
-    U = (m + t) * grow + 8 * DBL_EPSILON * (fabs(m) + t);
+    U = wide ? far : (m + t) * grow + 8 * DBL_EPSILON * (fabs(m) + t);
     if (k == 0) {
       /* lambda_1 lies in [d_1 + rho*zeta_1^2, d_1 + rho*||z||^2]. */
       double zz = 0.0;
@@ -334,7 +381,7 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
   } else {
     double h = fabs(A.b - xmin) / 2;
     double m = fmin(A.b, xmin), t = wn > 0.0 ? wn * (wn / (h + hypot(h, wn))) : 0.0;
-    L = (m - t) * grow - 8 * DBL_EPSILON * (fabs(m) + t);
+    L = wide ? far : (m - t) * grow - 8 * DBL_EPSILON * (fabs(m) + t);
     U = xmin;
   }
   const double L0 = L, U0 = U;
@@ -343,16 +390,32 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
   int it = 0;
   while (!adjacent(L, U) && it < 200) {
     double m = fmid(L, U);
-    if (g_plain(&A, m) > 0) L = m; else U = m;
+    int up;
+    if (wide) {
+      quad gq, gpq;
+      g_quad(d, z, &A, m, &gq, &gpq, NULL);
+      up = gq > 0;
+    } else {
+      up = g_plain(&A, m) > 0;
+    }
+    if (up) L = m; else U = m;
     ++it;
   }
   dg.bisect_iters = it;
   double nu0 = (side > 0) ? U : L;   /* the end that is not a pole */
 
-  /* One Newton step with a compensated sum. */
-  double g, gp, kap;
-  g_comp(&A, nu0, &g, &gp, &kap);
-  double nu = nu0 - g / gp;
+  /* One Newton step with a compensated sum (binary128 on the wide path). */
+  double g, gp, kap, nu;
+  if (wide) {
+    quad gq, gpq, sa;
+    g_quad(d, z, &A, nu0, &gq, &gpq, &sa);
+    quad nq0 = (quad)nu0, anu = nq0 < 0 ? -nq0 : nq0, agp = gpq < 0 ? -gpq : gpq;
+    nu = (double)(nq0 - gq / gpq);
+    kap = (double)((fabsq(A.bq) + anu + sa) / (anu * agp));
+  } else {
+    g_comp(&A, nu0, &g, &gp, &kap);
+    nu = nu0 - g / gp;
+  }
   dg.kappa_g = kap;
   double mu = 1.0 / nu;
   double lam = sigma + mu;
@@ -368,7 +431,7 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
     int pit = 0;
     for (; pit < 100; ++pit) {
       quad gq, gpq;
-      g_quad(d, z, &A, cur, &gq, &gpq);
+      g_quad(d, z, &A, cur, &gq, &gpq, NULL);
       if (gq == 0) break;
       if (gq > 0) lo = cur; else hi = cur;
       double t = (double)((quad)cur - gq / gpq);

@@ -231,6 +231,51 @@ def test_truth_graded_4096_tiny_zeta(orc):
         assert max(T.rel(V[j, m], tr[m]["v"][j]) for j in range(0, 4096, 7)) <= 5e-14
 
 
+# Edge problems whose arrow w_j = -zeta_j/(zeta_i delta_j) leaves the square range of binary64
+# (zeta_i near 1e-150 beside a pole 1e-13 away: |w_j| up to 1e162): the oracle carries eq. (secAi)
+# in binary128 for those eigenpairs.  Pinned to the 256-bit solution of the plain definition,
+# eigenvalue, shifted representation (i, mu) and every eigenvector component.
+def _wide(d, z, i):
+    dl = d - d[i]
+    dl[i] = np.inf
+    with np.errstate(all="ignore"):
+        w = np.abs(z / (z[i] * dl))
+    w[i] = 0.0
+    return not (w.max() < 2.0 ** 511)
+
+
+def _pin_pairs(orc, d, z, rho, ks=None):
+    if rho < 0:                                   # Sec. 1: solve the reversed problem with -rho
+        d, z, rho = -d[::-1].copy(), z[::-1].copy(), -rho
+    ks = list(range(d.size)) if ks is None else ks
+    lam, V, dg = orc.eig_some(d, z, rho, ks, vectors=True)
+    tr = T.eig(d, z, rho, ks=ks)
+    nwide = 0
+    for m, k in enumerate(ks):
+        assert dg[m]["i"] == tr[m]["i"], (k, dg[m]["i"], tr[m]["i"])
+        nwide += _wide(d, z, dg[m]["i"])
+        assert T.rel(lam[m], tr[m]["lam"]) <= 2e-14, k
+        assert T.rel(dg[m]["mu"], tr[m]["mu"]) <= 2e-14, k
+        assert max(T.rel(V[j, m], tr[m]["v"][j]) for j in range(d.size)) <= 5e-14, k
+    return nwide
+
+
+@pytest.mark.parametrize("seed", [92, 128, 137, 167, 182, 203])
+def test_truth_arrow_beyond_binary64_small(orc, seed):
+    """Every eigenpair of the clustered edge problems whose binary64 evaluation of eq. (secAi)
+    overflowed (workloads.extreme)."""
+    d, z, rho = W.extreme(seed)
+    assert _pin_pairs(orc, d, z, rho) >= 1
+
+
+@pytest.mark.parametrize("seed,ks", [(6, [322, 323, 324]), (11, [122, 139, 167, 179, 181, 190]),
+                                     (13, [82, 99])])
+def test_truth_arrow_beyond_binary64_large(orc, seed, ks):
+    """The same regime inside larger edge problems (workloads.extreme_large, 353-629 poles)."""
+    d, z, rho = W.extreme_large(seed)
+    assert _pin_pairs(orc, d, z, rho, ks) >= 1
+
+
 def test_negative_rho_reduction(orc):
     d, z, _ = W.uniform(24, 5)
     lam, V = orc.eig(d, z, -0.7)
