@@ -1,5 +1,6 @@
-// Double-double arithmetic for the device ("double the working precision",
-// Sec. 2.3 of the paper).  A value is hi + lo with |lo| <= ulp(hi)/2.  The
+// Double-double arithmetic for the device: the extended precision that the
+// paper asks for in the tip of the arrowhead inverse (Sec. 2.1, 2.3).  A
+// value is hi + lo with |lo| <= ulp(hi)/2.  The
 // error-free transformations are Knuth's TwoSum, Dekker's FastTwoSum and the
 // FMA-based TwoProd; the library is compiled with -ffp-contract=off so that
 // none of these sequences is re-associated or fused behind our back.
@@ -74,6 +75,17 @@ __device__ __forceinline__ dd dd_div(dd a, dd b) {
   r.lo += a.lo - p.lo;
   double q2 = (r.hi + r.lo) / b.hi;
   return fast_two_sum(q1, q2);
+}
+
+// a / zeta^2 with zeta^2 formed exactly as a double-double.  zeta is first
+// scaled by a power of two into [1, 2) (and a by its square): for |zeta|
+// below about 2^-484 the low part of the unscaled square would be a
+// subnormal number and lose bits.
+__device__ __forceinline__ dd dd_div_sq(dd a, double zeta) {
+  const int e = ilogb(zeta);
+  const double zs = ldexp(zeta, -e);
+  const dd as = {ldexp(a.hi, -2 * e), ldexp(a.lo, -2 * e)};
+  return dd_div(as, two_prod(zs, zs));
 }
 
 }  // namespace dpr1

@@ -43,7 +43,7 @@ using fe::COL_UNIT;
 // the reflection vector's component there (0 for groups without reflection).
 // Per final column c:
 //   COL_REDUCED  csig = sigma_k (the shift pole), cmu = mu_k,
-//                cic = 1 / (mu_k ||x_k||)
+//                cic = 1 / ||x_k||
 //   COL_UNIT     cidx = original row of the unit vector
 //   COL_REFLECT  cidx = group id, ct = column t of the reflection,
 //                cub = beta u_t
@@ -131,9 +131,9 @@ __global__ void __launch_bounds__(ASM_T) k_assemble(AsmArgs a) {
           // is exactly 0 whatever den is
           const double den = (di[j] - sg) - m;
           const double rc = rcp_nr(den);
-          double q = m * rc;
-          q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);
-          v[j] = zi[j] != 0.0 ? zi[j] * (q * ic) : 0.0;
+          double q = ic * rc;
+          q = __builtin_fma(__builtin_fma(-q, den, ic), rc, q);
+          v[j] = zi[j] != 0.0 ? zi[j] * q : 0.0;
         }
       } else if (kind == COL_UNIT) {
         const int64_t at = s_idx[cc];
@@ -307,7 +307,7 @@ static int front_end(const double* d, const double* zdev, const std::vector<doub
     if (V && q.kind == COL_REDUCED) {
       csig[c] = rd[sir[q.idx]];
       cmu[c] = mur[q.idx];
-      cic[c] = 1.0 / (mur[q.idx] * xnr[q.idx]);
+      cic[c] = 1.0 / xnr[q.idx];
     }
   }
   GCHECK(hipMemcpyAsync(lambda, lam.data(), 8 * n, hipMemcpyHostToDevice, st));

@@ -27,6 +27,7 @@
 //              in windows aligned to whole cache lines; flagged columns are
 //              left to k_fixout.
 //   k_fixout -- outputs and V columns of the flagged eigenpairs.
+#include <float.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -352,45 +353,46 @@ __global__ void k_zero(int32_t* __restrict__ a, int n) {
 // Root of the model of g at the current iterate m.  Written in poles,
 // g(t) = b' - t + sum_j w_j/(t - xi_j) with xi_j = 1/delta'_j and
 // w_j = zeta_j^2/(delta'_j^2 zeta_i^2); the wanted root lies right of every
-// pole.  The model keeps the nearest pole xm with its exact weight wm and
-// replaces the rest of the sum, R(t), by A/(t - p) + B fitted to R's value,
-// slope and curvature at m (Sz, Spz, Sppz are the moments of the whole sum:
-// S/zeta_i^2, sum w/(m - xi)^2, sum w/(m - xi)^3).  Every other pole lies
-// left of xm, so the fitted pole does too; the model is then convex and
+// pole.  The model keeps the nearest pole xm with its exact weight sw^2 and
+// replaces the rest of the sum, R(t), by sa^2/(t - p) + B fitted to R's
+// value, slope and curvature at m (Sz, Spz, Sppz are the moments of the whole
+// sum: S/zeta_i^2, sum w/(m - xi)^2, sum w/(m - xi)^3).  Every other pole
+// lies left of xm, so the fitted pole does too; the model is then convex and
 // decreasing right of its poles and its root is found by Newton's method
 // inside the bracket (L, U).  The model matches g to second order at m, so
-// the outer iteration converges cubically.
+// the outer iteration converges cubically.  Both weights are carried as
+// square roots: with zeta_i near 1e-148 beside a pole 1e-13 away a weight
+// reaches 1e322 while every term weight/(t - pole) of the model is finite.
 __device__ __forceinline__ double model_root(double m, double Sz, double Spz, double Sppz, double bp, double xm,
-                                             double wm, double L, double U) {
+                                             double sw, double L, double U) {
   double Rs = Sz, Rp = Spz, Rpp = Sppz;
-  if (wm > 0.0) {
+  if (sw > 0.0) {
     const double ie = 1.0 / (m - xm);
-    const double tm = wm * ie;
-    Rs -= tm;
-    Rp -= tm * ie;
-    Rpp -= (tm * ie) * ie;
+    const double a = sw * ie;
+    Rs -= sw * a;
+    Rp -= a * a;
+    Rpp -= (a * a) * ie;
   }
-  double p = xm, A = 0.0, B = Rs;
+  double p = xm, sa = 0.0, B = Rs;
   if (Rp > 0.0 && Rpp > 0.0) {
     p = fmin(m - Rp / Rpp, xm);
     const double x = m - p;
-    A = Rp * x * x;
+    sa = sqrt(Rp) * x;
     B = Rs - Rp * x;
   }
-  // A model whose fitted weight or offset is not finite (R' x^2 overflows
-  // when zeta_i is near 1e-149: R' ~ 1e291, x ~ 1e13) says nothing: NaN
-  // makes the caller take a bisection step instead of reading a zero step
-  // as convergence.
-  if (!(fabs(A) < INFINITY) || !(fabs(B) < INFINITY)) return NAN;
+  // a model whose parameters are not finite says nothing: NaN makes the
+  // caller take a bisection step instead of reading a zero step as
+  // convergence
+  if (!(sa < INFINITY) || !(fabs(B) < INFINITY) || !(sw < INFINITY)) return NAN;
   double lo = fmax(L, fmax(xm, p)), hi = U;
   double t = m;
   for (int q = 0; q < 40; ++q) {
     const double e1 = 1.0 / (t - xm), e2 = 1.0 / (t - p);
-    const double a1 = wm * e1, a2 = A * e2;
-    const double h = ((bp - t) + B) + (a1 + a2);
+    const double s1 = sw * e1, s2 = sa * e2;
+    const double h = ((bp - t) + B) + (sw * s1 + sa * s2);
     if (!(h == h)) return NAN;
     if (h == 0.0) break;  // t is a root of the model
-    const double hp = -1.0 - (a1 * e1 + a2 * e2);
+    const double hp = -1.0 - (s1 * s1 + s2 * s2);
     if (h > 0.0) lo = t; else hi = t;
     double tn = t - h / hp;
     // a step below the resolution of t ends the iteration (t may sit on the
@@ -412,7 +414,7 @@ __device__ __forceinline__ double model_root(double m, double Sz, double Spz, do
 // while |g| fell by less than a factor 10 on the same side (g1, g2 keep the
 // two previous values of g).
 __device__ __forceinline__ void model_step(double m, double g, double Sz, double Spz, double Sppz, double bp,
-                                           double xm, double wm, int iters, double L, double U, double& nu,
+                                           double xm, double sw, int iters, double L, double U, double& nu,
                                            double& nu0, double& prevstep, double& g1, double& g2, bool& done,
                                            double tol = 0x1p-20) {
   if (g == 0.0) {
@@ -423,7 +425,7 @@ __device__ __forceinline__ void model_step(double m, double g, double Sz, double
   const bool cycle = (g * g1 < 0.0) && (g1 * g2 < 0.0) && (fabs(g) > 0.1 * fabs(g2));
   g2 = g1;
   g1 = g;
-  const double nn0 = model_root(m, Sz, Spz, Sppz, bp, xm, wm, L, U);
+  const double nn0 = model_root(m, Sz, Spz, Sppz, bp, xm, sw, L, U);
   double nn = nn0;
   const double step = fabs(nn - m);
   // Cubic convergence: a step e leaves a model error of about 8 e^3 (the
@@ -528,7 +530,27 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     Fs[3] = __builtin_fma(tr, r, Fs[3]);
   });
   wg_sum<4>(Fs, W, wv, lane, red);
-  const double F = 1.0 + rho * Fs[0];
+  double F = 1.0 + rho * Fs[0];
+  // The estimated reciprocals leave the sign of F open when |F| is within
+  // their error (2^-23 of the sum of |terms|, taken with a margin of 8): such
+  // lanes repeat the test with corrected quotients, so that the shift pole
+  // differs from a serial IEEE evaluation only where F is zero to rounding
+  // (the eigenvalue at the midpoint of its gap: either pole is then nearest).
+  // Every wave of the block holds the same per-lane state, so all take the
+  // branch together.
+  const bool open = valid && kk > 0 && fabs(F) <= 0x1p-20 * (1.0 + rho * Fs[1]);
+  if (wave_any(open)) {
+    double Fr[1] = {0.0};
+    sweep(P, j0, j1, wlo, whi, [&](int, int, double dj, double z2, double, int) {
+      const double den = (dj - dk) - tau;
+      const double r = rcp_1nr(den);
+      double t = z2 * r;
+      t = __builtin_fma(__builtin_fma(-t, den, z2), r, t);
+      Fr[0] += t;
+    });
+    wg_sum<1>(Fr, W, wv, lane, red);
+    if (open) F = 1.0 + rho * Fr[0];
+  }
   const bool right = (kk == 0) || (F > 0);
   const int i = right ? kk : kk - 1;
   const double s = right ? 1.0 : -1.0;
@@ -576,7 +598,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   wg_sum_dd(Nd, W, wv, lane, red);
   const dd rr = dd_div(dd{1.0, 0.0}, dd{rho, 0.0});
   const dd num = dd_add(dd_add_same(rr, Pd), Nd);
-  const dd bdd = dd_div(num, two_prod(zi, zi));
+  const dd bdd = dd_div_sq(num, zi);
   const double Pr = rho * Pd.hi, Nr = rho * Nd.hi;
   const double Kb64 = (1.0 + Pr - Nr) / fabs(1.0 + Pr + Nr);
   bool use_ext = A.mode_b == 0 || (A.mode_b == 1 && Kb64 > 100.0);
@@ -591,9 +613,10 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   const double nss = -s * sigma;
   const bool interior = kk > 0;
   const double xm = interior ? 1.0 / (dkm1 - dk) : 0.0;  // pole nearest to the root
-  // its weight zeta_jm^2/(delta'_jm^2 zeta_i^2), jm the other end of the gap
+  // the square root of its weight zeta_jm^2/(delta'_jm^2 zeta_i^2), jm the
+  // other end of the gap
   const double zjm = interior ? Zv[right ? kk - 1 : kk] : 0.0;
-  const double wm = interior ? ((zjm * xm) * (zjm * xm)) / zi2 : 0.0;
+  const double sw = interior ? fabs(zjm * xm) / fabs(zi) : 0.0;
   double L, U, nu;
   if (interior) {
     L = xm;
@@ -726,7 +749,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
           const double gtol = 0x1p-20 * Sz + 0x1p-50 * fabs(bp);
           if (g > gtol) L = m; else if (g < -gtol) U = m;
         }
-        model_step(m, g, Sz, Spz, Sppz, bp, xm, wm, iters, L, U, nu, nu0, prevstep, g1, g2, done);
+        model_step(m, g, Sz, Spz, Sppz, bp, xm, sw, iters, L, U, nu, nu0, prevstep, g1, g2, done);
       }
     }
   }
@@ -754,7 +777,10 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, double, int ub) {
     double dl = __builtin_fma(s, dj, nss);
     double pp = __builtin_fma(m, dl, -1.0);
-    double q = dl * pp;
+    // q > 0; beyond binary64 (a far pole with nu near 1e300) it is held at the
+    // largest finite number, where the quotient is 0 to working precision and
+    // the correction below stays finite (0 * inf would be NaN)
+    double q = fmin(dl * pp, DBL_MAX);
     double r = rcp_1nr(q);
     double t = z2 * r;
     t = __builtin_fma(__builtin_fma(-t, q, z2), r, t);  // corrected quotient
@@ -788,7 +814,8 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   const double Sz = (cs + cc) / zi2;
   const double g = (bp - m) + Sz;
   const double gp = -1.0 - Sp[0] / zi2;
-  const double kap = (fabs(bp) + m + Sz) / (m * fabs(gp));
+  // divided in two steps: m |g'| overflows when nu nears 1e304
+  const double kap = ((fabs(bp) + m + Sz) / m) / fabs(gp);
   double nu1 = m;
   bool fin = true;
   if (A.root == 0) {
@@ -797,7 +824,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     fin = false;
     if (g > 0) L = m; else if (g < 0) U = m;
     double nn = m;
-    model_step(m, g, Sz, Sp[0] / zi2, Sp[1] / zi2, bp, xm, wm, iters, L, U, nu, nn, prevstep, g1, g2, fin);
+    model_step(m, g, Sz, Sp[0] / zi2, Sp[1] / zi2, bp, xm, sw, iters, L, U, nu, nn, prevstep, g1, g2, fin);
     if (fin) nu1 = nn;
   }
   const bool cont = valid && !fin;  // unfinished: continued in k_fix
@@ -1068,7 +1095,6 @@ __device__ void fix_items(const KArgs& A) {
     const double sigma = Dv[i];
     const double zi = Zv[i];
     const double zi2 = zi * zi;
-    const dd zi2d = two_prod(zi, zi);
     double muv = A.mu[off + k];
     double lam = A.lam[off + k];
     bool nz = (it.flags & FIX_NEARZERO) != 0;
@@ -1087,7 +1113,7 @@ __device__ void fix_items(const KArgs& A) {
       // step is accepted also gives kappa_g and ||x||
       const double xm = (k > 0) ? 1.0 / (Dv[k - 1] - Dv[k]) : 0.0;
       const double zjm = (k > 0) ? Zv[i == k ? k - 1 : k] : 0.0;
-      const double wm = (k > 0) ? ((zjm * xm) * (zjm * xm)) / zi2 : 0.0;
+      const double sw = (k > 0) ? fabs(zjm * xm) / fabs(zi) : 0.0;
       const double bp = it.bhi;
       double nu = it.cnu, L = it.cL, U = it.cU, prevstep = it.cprev, g1 = 0.0, g2 = 0.0;
       int iters = it.iters;
@@ -1105,7 +1131,7 @@ __device__ void fix_items(const KArgs& A) {
           const double2 pj = Z2v[j];
           const double dl = __builtin_fma(s, pj.x, -s * sigma);
           const double pp = __builtin_fma(m, dl, -1.0);
-          const double q = dl * pp;
+          const double q = fmin(dl * pp, DBL_MAX);  // as in k_eig's accurate pass
           const double r = rcp_1nr(q);
           double t = pj.y * r;
           t = __builtin_fma(__builtin_fma(-t, q, pj.y), r, t);  // corrected quotient
@@ -1124,11 +1150,11 @@ __device__ void fix_items(const KArgs& A) {
         ++iters;
         const double g = (bp - m) + Sz;
         if (g > 0) L = m; else if (g < 0) U = m;
-        model_step(m, g, Sz, sp / zi2, sp3 / zi2, bp, xm, wm, iters, L, U, nu, nu0, prevstep, g1, g2, done);
+        model_step(m, g, Sz, sp / zi2, sp3 / zi2, bp, xm, sw, iters, L, U, nu, nu0, prevstep, g1, g2, done);
       }
       nu1 = nu0;
       const double gp = -1.0 - sp / zi2;
-      const double kap = (fabs(bp) + m + Sz) / (m * fabs(gp));
+      const double kap = ((fabs(bp) + m + Sz) / m) / fabs(gp);  // as in k_eig
       muv = s / nu1;
       lam = sigma + muv;
       double amp = fabs(muv / lam);
@@ -1172,6 +1198,7 @@ __device__ void fix_items(const KArgs& A) {
           dd dl = two_sum(s * dj, -s * sigma);                   // delta'_j exactly
           dd pp = dd_add(dd_mul_d(dl, cur), dd{-1.0, 0.0});       // nu delta' - 1
           dd q = dd_mul(dl, pp);
+          if (!(q.hi < DBL_MAX)) q = {DBL_MAX, 0.0};  // beyond binary64: the term is 0
           // (zeta_j^2 hi + lo)/q: leading quotient from the refined
           // reciprocal (2^-48.7) and one residual correction, about 2^-97
           const double r = rcp_1nr(q.hi);
@@ -1184,7 +1211,7 @@ __device__ void fix_items(const KArgs& A) {
         }
         acc = block_sum_same(acc, sm);
         sp = block_sum(sp, sm);
-        dd Sdd = dd_div(acc, zi2d);
+        dd Sdd = dd_div_sq(acc, zi);
         dd gd = dd_add(dd_add(bdd, dd{-cur, 0.0}), Sdd);
         double Spz = sp / zi2;
         double gpv = -1.0 - Spz;
@@ -1370,13 +1397,13 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
     double sg = M.neg ? -1.0 : 1.0;
     lam_out[b] = sg * lam[a];
     // per-column constants of the eigenvector kernel: sigma_k and
-    // 1/(sign(mu) |mu| ||x||), so that v_j = zeta_j ((mu/(delta_j - mu)) cinv);
-    // the quotient is scaled first: (mu/(delta_j - mu)) cinv = 1/((delta_j -
-    // mu) ||x||) is at most 1/|zeta_j|, while zeta_j (mu/(delta_j - mu)) can
-    // underflow when mu is tiny (|mu| = 1e-240, zeta_j = 1e-100) although v_j
-    // is representable
+    // w_k = 1/||x_k|| = |mu|/(|mu| ||x||), so that v_j = zeta_j (w_k/(delta_j -
+    // mu)).  The quotient w/(delta_j - mu) = v_j/zeta_j is at most 1/|zeta_j|
+    // and underflows only where v_j/zeta_j does; mu/(delta_j - mu) alone would
+    // be subnormal beside a distant pole when mu is tiny (1e-304 against
+    // delta_j = 1e10) and lose bits although v_j is a normal number
     csig[a] = sd[M.off + ii[a]];
-    cinv[a] = 1.0 / copysign(xs[a], mu[a]);
+    cinv[a] = fabs(mu[a]) / xs[a];
     if (idx_out) idx_out[b] = M.neg ? n - 1 - ii[a] : ii[a];
     if (mu_out) mu_out[b] = sg * mu[a];
     if (xn_out) xn_out[b] = xs[a] / fabs(mu[a]);
@@ -1501,12 +1528,12 @@ __device__ void vec_block(unsigned bid, const VArgs& v) {
         const int ko = (int)kolo + q;
         const int c = (M.neg ? n - 1 - ko : ko) - c0;
         if (lskip[c]) continue;
-        const double m = lmu[c];
-        const double den = (ld_d[pos] - lsig[c]) - m;
+        const double w = linv[c];
+        const double den = (ld_d[pos] - lsig[c]) - lmu[c];
         const double rc = rcp_1nr(den);
-        double qq = m * rc;
-        qq = __builtin_fma(__builtin_fma(-qq, den, m), rc, qq);  // corrected quotient
-        __builtin_nontemporal_store(ld_z[pos] * (qq * linv[c]), &V[e]);
+        double qq = w * rc;
+        qq = __builtin_fma(__builtin_fma(-qq, den, w), rc, qq);  // corrected quotient
+        __builtin_nontemporal_store(ld_z[pos] * qq, &V[e]);
       }
     }
     return;
@@ -1527,9 +1554,9 @@ __device__ void vec_block(unsigned bid, const VArgs& v) {
       if (rel >= 0 && rel < nr) {
         const double den = (ld_d[rel] - sc) - m;
         const double rc = rcp_1nr(den);
-        double q = m * rc;
-        q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
-        __builtin_nontemporal_store(ld_z[rel] * (q * iv), vp);
+        double q = iv * rc;
+        q = __builtin_fma(__builtin_fma(-q, den, iv), rc, q);  // corrected quotient
+        __builtin_nontemporal_store(ld_z[rel] * q, vp);
       }
     }
   }
@@ -1575,7 +1602,7 @@ __global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ la
     }
     if (V) {
       const double sc = A.sd[M.off + ii];
-      const double iv = 1.0 / copysign(xs, m);
+      const double iv = fabs(m) / xs;  // 1/||x||, as in k_out
       const int64_t ld = voffs ? (int64_t)n : ldv;
       double* col = V + (voffs ? voffs[it.p] : 0) + (int64_t)ko * ld;
 #pragma unroll 8
@@ -1583,9 +1610,9 @@ __global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ la
         const int j = M.neg ? n - 1 - pos : pos;
         const double den = (A.sd[M.off + j] - sc) - m;
         const double rc = rcp_1nr(den);
-        double q = m * rc;
-        q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);  // corrected quotient
-        __builtin_nontemporal_store((sg * A.sz[M.off + j]) * (q * iv), &col[pos]);
+        double q = iv * rc;
+        q = __builtin_fma(__builtin_fma(-q, den, iv), rc, q);  // corrected quotient
+        __builtin_nontemporal_store((sg * A.sz[M.off + j]) * q, &col[pos]);
       }
     }
   }

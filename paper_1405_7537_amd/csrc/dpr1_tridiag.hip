@@ -158,9 +158,9 @@ __global__ void __launch_bounds__(TA_T) k_tri_assemble(const ANode* __restrict__
       for (int j = 0; j < TA_R; ++j) {
         const double den = (di[j] - sg) - m;
         const double rc = rcp_nr(den);
-        double q = m * rc;
-        q = __builtin_fma(__builtin_fma(-q, den, m), rc, q);
-        v[j] = zi[j] != 0.0 ? zi[j] * (q * ic) : 0.0;
+        double q = ic * rc;
+        q = __builtin_fma(__builtin_fma(-q, den, ic), rc, q);
+        v[j] = zi[j] != 0.0 ? zi[j] * q : 0.0;
       }
     } else if (kind == COL_UNIT) {
       const int64_t at = s_idx[cc];
@@ -612,7 +612,7 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
           const int64_t k = roff[p] + q.idx;
           hsig[o + c] = rd[roff[p] + sidx[k]];
           hmu[o + c] = mur[k];
-          hic[o + c] = 1.0 / (mur[k] * xnr[k]);
+          hic[o + c] = 1.0 / xnr[k];
         }
       }
       const int32_t q = (int32_t)anodes.size();

@@ -20,14 +20,16 @@ def D():
 
 
 def scales(V, lam, lb, Vb, z, rho):
-    """Magnitudes |V||X||V|^T (diag), rho |V|(|X|+|X|^T)|y|, |y|^T|X||y| for the tolerances."""
+    """Magnitudes |V||X||V|^T (diag), rho |V|(|X|+|X|^T)|y|, |y|^T|X||y| for the tolerances, with
+    |X| = |F| o (|V|^T |V_bar|) off the diagonal: the rounding error of the product V^T V_bar is
+    bounded by n eps times the product of the magnitudes, which can exceed |V^T V_bar| where the
+    sum cancels (standard error analysis of inner products)."""
     n = lam.size
     gap = lam[None, :] - lam[:, None]
     np.fill_diagonal(gap, 1.0)
-    P = V.T @ Vb
-    X = P / gap
-    np.fill_diagonal(X, lb)
-    Xa = np.abs(X)
+    Pa = np.abs(V).T @ np.abs(Vb) if Vb is not None else np.zeros((n, n))
+    Xa = Pa / np.abs(gap)
+    np.fill_diagonal(Xa, np.abs(lb) if lb is not None else 0.0)
     Va = np.abs(V)
     y = np.abs(V.T @ z)
     Md = np.sum((Va @ Xa) * Va, axis=1)
@@ -142,7 +144,8 @@ def test_autograd_single_and_batched(D):
 
 
 def test_config_fwd_bwd_sampled(D, orc):
-    """256 problems of n = 512 (seed 4): batched forward + backward; 3 problems checked in full."""
+    """256 problems of n = 512 (seed 4): batched forward + backward; 33 problems (every 8th and the
+    last) checked in full against the oracle's dense backward."""
     import torch
     nb, n = 256, 512
     dB, zB, rB = W.uniform_batch(nb, n, 4)
@@ -156,7 +159,7 @@ def test_config_fwd_bwd_sampled(D, orc):
     db, zb, rb = D.backward_batched(dt, zt, rt, b.shift_idx.view(nb, n), b.mu.view(nb, n), b.xnorm.view(nb, n),
                                     b.V, torch.as_tensor(w, device="cuda"), torch.as_tensor(Wcm, device="cuda"))
     db, zb, rb = db.cpu().numpy(), zb.cpu().numpy(), rb.cpu().numpy()
-    for p in (0, 77, 255):
+    for p in list(range(0, nb, 8)) + [nb - 1]:
         lo, Vo, dg = orc.eig(dB[p], zB[p], rB[p], diags=True)
         Vb = Wcm[p].T
         db_o, zb_o, rb_o = orc.backward(dB[p], zB[p], rB[p], [x["sigma"] for x in dg], [x["mu"] for x in dg], Vo,
