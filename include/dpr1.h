@@ -19,9 +19,12 @@
  *    return (dpr1_eig_noalloc: a static device array of the library).
  *    Workspace contents need not be initialised.
  *  - All work is enqueued asynchronously on `stream` (a hipStream_t passed as
- *    void*; NULL = the default stream).  No call synchronises the host, so the
- *    launches may be captured into a hipGraph, except dpr1_batched_plan (it
- *    copies from host memory), the autotuners and dpr1_eig_general.
+ *    void*; NULL = the default stream); dpr1_eig with eigenvectors forks part
+ *    of its work to a second stream of the library and joins it back into
+ *    `stream` through events before it returns (opts.vwrite).  No call
+ *    synchronises the host, so the launches may be captured into a hipGraph,
+ *    except dpr1_batched_plan (it copies from host memory), the autotuners
+ *    and dpr1_eig_general.
  *  - Inputs (Sec. 1 of the paper): n >= 1, d strictly decreasing, every
  *    z_j != 0, rho != 0 and finite.  rho < 0 is reduced to rho > 0 as in
  *    Sec. 1 by solving with (-d reversed, z reversed, -rho) and mapping back.
@@ -118,6 +121,13 @@ typedef struct dpr1_opts {
                           ([0], [1]) and around the second phase ([2], [3]):
                           the flagged eigenpairs overlapped with the
                           eigenvector write                                 */
+  int32_t vwrite;      /* eigenvectors of a single problem: 0 (default) the
+                          eigenvalue kernel runs in two halves and the first
+                          half's columns are written on a second stream (a
+                          library stream per device, created on first use,
+                          default priority) while the second half is solved;
+                          1 every column after the eigenvalue kernel, on
+                          `stream` only.  dpr1_eig_noalloc always uses 1.    */
 } dpr1_opts;
 
 void dpr1_default_opts(dpr1_opts* opts);

@@ -95,6 +95,8 @@ struct KArgs {
   int32_t mode_b, root, polish;
   int32_t main_passes;
   double kappa_polish, nearzero;
+  int32_t g0;           // single problem: first group of 64 eigenvalues of this launch
+  int32_t pad2;
 };
 
 // ------------------------------------------------------------ bit helpers
@@ -910,7 +912,7 @@ template <int OCC>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) k_eig(KArgs A) {
   extern __shared__ double red[];
   if (A.items == nullptr) {
-    eig_block(A, 0, blockIdx.x * WAVE, red);
+    eig_block(A, 0, (A.g0 + (int)blockIdx.x) * WAVE, red);
     return;
   }
   // persistent: take (problem, first eigenvalue) items from the queue
@@ -1371,8 +1373,9 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
                                              double* __restrict__ cinv, double* __restrict__ lam_out,
                                              int32_t* __restrict__ idx_out, double* __restrict__ mu_out,
                                              double* __restrict__ xn_out, const uint8_t* __restrict__ vflag,
-                                             int32_t* __restrict__ info_out) {
-  // a batch: block p handles problem p; one problem: the grid strides over it
+                                             int32_t* __restrict__ info_out, int kb, int ke) {
+  // a batch: block p handles problem p; one problem: the grid strides over
+  // its eigenvalues kb .. ke-1
   const int p = nprob > 1 ? (int)blockIdx.x : 0;
   const int k0 = nprob > 1 ? (int)threadIdx.x : (int)(blockIdx.x * blockDim.x + threadIdx.x);
   const int kstep = nprob > 1 ? (int)blockDim.x : (int)(gridDim.x * blockDim.x);
@@ -1391,7 +1394,7 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
     }
     return;
   }
-  for (int k = k0; k < n; k += kstep) {
+  for (int k = kb + k0; k < min(n, ke); k += kstep) {
     int ko = M.neg ? n - 1 - k : k;
     int64_t a = M.off + k, b = M.off + ko;
     double sg = M.neg ? -1.0 : 1.0;
@@ -1413,7 +1416,7 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
 }
 
 // ------------------------------------------------------------------- vec
-// v_j = zeta_j r_j / (|mu| ||x||), r_j = mu/(delta_j - mu).  A block owns up
+// v_j = zeta_j w/(delta_j - mu), w = 1/||x|| (eq. eigenvecAi).  A block owns up
 // to CB columns of one problem over up to ROWS consecutive positions of each
 // column.  The (d_j, zeta_j) of those positions are staged in LDS once; each
 // wave then writes 64-element windows aligned to 512 bytes of V, so every
@@ -1444,6 +1447,7 @@ struct VArgs {
   double* V;
   const int64_t* voffs;
   int64_t ldv;
+  int32_t cbase, cend;  // single problem: columns cbase .. cend-1
 };
 
 template <int CB>
@@ -1469,14 +1473,14 @@ __device__ void vec_block(unsigned bid, const VArgs& v) {
     r0 = g.w;
   } else {
     p = 0;
-    c0 = (int)(bid % ncolgroups) * CB;
+    c0 = v.cbase + (int)(bid % ncolgroups) * CB;
     r0 = (int64_t)(bid / ncolgroups) * VEC_ROWS;
     nc = 0;
   }
   const Meta M = meta[p];
   if (M.info != 0) return;
   const int n = M.n;
-  if (!groups) nc = min(CB, n - c0);
+  if (!groups) nc = min(CB, min(n, v.cend) - c0);
   const int nr = (int)min((int64_t)VEC_ROWS, (int64_t)n - r0);
   if (nc <= 0 || nr <= 0) return;
   const double sg = M.neg ? -1.0 : 1.0;
@@ -1562,6 +1566,12 @@ __device__ void vec_block(unsigned bid, const VArgs& v) {
   }
 }
 
+
+// The eigenvector writer alone (single problem, a range of columns).
+template <int CB>
+__global__ void __launch_bounds__(VEC_T) k_vec(VArgs v) {
+  vec_block<CB>(blockIdx.x, v);
+}
 
 // k_fix and the eigenvector writer in one launch: the first nfix blocks take
 // flagged eigenpairs from the queue (latency-bound work), the others write V
@@ -1774,6 +1784,7 @@ void dpr1_default_opts(dpr1_opts* o) {
   o->main_passes = 0;
   o->waves_per_simd = 0;
   o->events = nullptr;
+  o->vwrite = 0;
 }
 
 size_t dpr1_workspace_size(int64_t n) {
@@ -1786,12 +1797,30 @@ size_t dpr1_workspace_size(int64_t n) {
     if ((x) != hipSuccess) return DPR1_EHIP;  \
   } while (0)
 
+// Second stream of the current device for the overlapped eigenvector write:
+// created once per device (default priority, non-blocking) and kept until the
+// process ends; nullptr if it cannot be created.
+constexpr int AUX_MAX_DEVICES = 64;
+static std::mutex aux_mutex;
+static hipStream_t aux_streams[AUX_MAX_DEVICES];
+static hipStream_t aux_stream() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= AUX_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(aux_mutex);
+  if (!aux_streams[dev]) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    aux_streams[dev] = s;
+  }
+  return aux_streams[dev];
+}
+
 static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, const int64_t* offs,
                         int64_t n_single, const double* d, const double* z, const double* rho_dev,
                         double rho_host, double* lambda, double* V, const int64_t* voffs, int64_t ldv,
                         int32_t* shift_idx, double* mu, double* xnorm, int32_t* info, int32_t* stats,
                         const dpr1_opts& o, int W, int64_t nitems, int persistent_grid, int64_t ngroups,
-                        hipStream_t st) {
+                        hipStream_t st, bool aux_ok = true) {
   Meta* meta = (Meta*)(w + L.meta);
   KArgs A;
   A.meta = meta;
@@ -1830,38 +1859,118 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
                      (double*)A.pairs, (double*)A.z2lo, info, (double2*)(w + L.part), A.ctr + 8);
   HIPCHECK(hipGetLastError());
   hipEvent_t* ev = (hipEvent_t*)o.events;
-  unsigned grid = persistent_grid ? (unsigned)persistent_grid : (unsigned)nitems;
-  if (ev) HIPCHECK(hipEventRecord(ev[0], st));
-  switch (occ_of(o)) {
-    case 6: hipLaunchKernelGGL(k_eig<6>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
-    case 8: hipLaunchKernelGGL(k_eig<8>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
-    default: hipLaunchKernelGGL(k_eig<4>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
-  }
-  HIPCHECK(hipGetLastError());
-  if (ev) HIPCHECK(hipEventRecord(ev[1], st));
-  // user outputs of every eigenpair (those of flagged ones are rewritten by
-  // k_fixout once k_fix has finished them)
   double* csig = (double*)(w + L.csig);
   double* cinv = (double*)(w + L.cinv);
-  hipLaunchKernelGGL(k_out, dim3(nprob > 1 ? (unsigned)nprob : (unsigned)std::min<int64_t>((N + 255) / 256, 1024)),
-                     dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, A.sd, csig, cinv, lambda,
-                     shift_idx, mu, xnorm, A.vflag, info);
+  VArgs va;
+  va.meta = meta;
+  va.sd = A.sd;
+  va.sz = A.sz;
+  va.mu = A.mu;
+  va.csig = csig;
+  va.cinv = cinv;
+  va.vflag = A.vflag;
+  va.V = V;
+  va.voffs = voffs;
+  va.ldv = ldv;
+  va.cbase = 0;
+  va.cend = (int32_t)N;
+  auto launch_eig = [&](unsigned grid, int g0) {
+    A.g0 = g0;
+    A.pad2 = 0;
+    switch (occ_of(o)) {
+      case 6: hipLaunchKernelGGL(k_eig<6>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
+      case 8: hipLaunchKernelGGL(k_eig<8>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
+      default: hipLaunchKernelGGL(k_eig<4>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
+    }
+  };
+  // user outputs of eigenvalues kb .. ke-1 (those of flagged ones are
+  // rewritten by k_fixout once k_fix has finished them) and the per-column
+  // constants of the eigenvector writer
+  auto launch_out = [&](int64_t kb, int64_t ke) {
+    const int64_t cnt = nprob > 1 ? N : ke - kb;
+    hipLaunchKernelGGL(k_out,
+                       dim3(nprob > 1 ? (unsigned)nprob : (unsigned)std::min<int64_t>((cnt + 255) / 256, 1024)),
+                       dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, A.sd, csig, cinv, lambda,
+                       shift_idx, mu, xnorm, A.vflag, info, (int)kb, (int)ke);
+  };
+  auto launch_vec = [&](int64_t cb, int64_t ce, hipStream_t s2) {
+    const int64_t cg = (ce - cb + VEC_C_SINGLE - 1) / VEC_C_SINGLE;
+    const int64_t rt = (N + VEC_ROWS - 1) / VEC_ROWS;
+    VArgs vb = va;
+    vb.groups = nullptr;
+    vb.ncolgroups = cg;
+    vb.cbase = (int32_t)cb;
+    vb.cend = (int32_t)ce;
+    hipLaunchKernelGGL((k_vec<VEC_C_SINGLE>), dim3((unsigned)(cg * rt)), dim3(VEC_T), 0, s2, vb);
+  };
+
+  // A single problem with eigenvectors: the eigenvalue kernel runs in two
+  // launches over the two halves of its groups of 64 eigenvalues, and the
+  // eigenvector writer of the first half runs on a second stream while the
+  // second half is solved, so that the HBM-bound stores overlap the
+  // ALU-bound sweeps; the second half's columns are written after it, beside
+  // k_fix.  Flagged columns are left to k_fixout, as in the sequential path.
+  hipStream_t st2 = nullptr;
+  hipEvent_t ea = nullptr, eb = nullptr, ec = nullptr;
+  bool overlap = V && !persistent_grid && o.vwrite == 0 && aux_ok && nitems >= 2;
+  if (overlap) {
+    st2 = aux_stream();
+    if (!st2 || hipEventCreateWithFlags(&ea, hipEventDisableTiming) != hipSuccess) overlap = false;
+    else if (hipEventCreateWithFlags(&eb, hipEventDisableTiming) != hipSuccess) overlap = false;
+    else if (hipEventCreateWithFlags(&ec, hipEventDisableTiming) != hipSuccess) overlap = false;
+  }
+  if (overlap) {
+    const int64_t g1 = nitems / 2;
+    const int64_t kmid = g1 * WAVE;
+    int rc = DPR1_OK;
+    if (ev && hipEventRecord(ev[0], st) != hipSuccess) rc = DPR1_EHIP;
+    if (rc == DPR1_OK) {
+      launch_eig((unsigned)g1, 0);
+      launch_out(0, kmid);
+      if (hipGetLastError() != hipSuccess || hipEventRecord(ea, st) != hipSuccess ||
+          hipStreamWaitEvent(st2, ea, 0) != hipSuccess)
+        rc = DPR1_EHIP;
+    }
+    if (rc == DPR1_OK) {
+      launch_vec(0, kmid, st2);
+      launch_eig((unsigned)(nitems - g1), (int)g1);
+      if (hipGetLastError() != hipSuccess || (ev && hipEventRecord(ev[1], st) != hipSuccess)) rc = DPR1_EHIP;
+    }
+    if (rc == DPR1_OK) {
+      launch_out(kmid, N);
+      if (hipGetLastError() != hipSuccess || (ev && hipEventRecord(ev[2], st) != hipSuccess) ||
+          hipEventRecord(eb, st) != hipSuccess || hipStreamWaitEvent(st2, eb, 0) != hipSuccess)
+        rc = DPR1_EHIP;
+    }
+    if (rc == DPR1_OK) {
+      launch_vec(kmid, N, st2);
+      unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048);
+      hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(FIXT), 0, st, A);
+      hipLaunchKernelGGL(k_fixout, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048)), dim3(256), 0,
+                         st, A, lambda, shift_idx, mu, xnorm, V, voffs, ldv, info);
+      if (hipGetLastError() != hipSuccess || hipEventRecord(ec, st2) != hipSuccess ||
+          hipStreamWaitEvent(st, ec, 0) != hipSuccess || (ev && hipEventRecord(ev[3], st) != hipSuccess))
+        rc = DPR1_EHIP;
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    (void)hipEventDestroy(ec);
+    return rc;
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+
+  unsigned grid = persistent_grid ? (unsigned)persistent_grid : (unsigned)nitems;
+  if (ev) HIPCHECK(hipEventRecord(ev[0], st));
+  launch_eig(grid, 0);
+  HIPCHECK(hipGetLastError());
+  if (ev) HIPCHECK(hipEventRecord(ev[1], st));
+  launch_out(0, N);
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[2], st));
   if (V) {
     // k_fix overlapped with the eigenvector writer: a few blocks take the
     // flagged eigenpairs, the rest write every other column
-    VArgs va;
-    va.meta = meta;
-    va.sd = A.sd;
-    va.sz = A.sz;
-    va.mu = A.mu;
-    va.csig = csig;
-    va.cinv = cinv;
-    va.vflag = A.vflag;
-    va.V = V;
-    va.voffs = voffs;
-    va.ldv = ldv;
     const int nfix = persistent_grid ? 512 : 256;
     if (persistent_grid) {
       va.groups = (const int4*)(w + L.groups);
@@ -1933,7 +2042,8 @@ int dpr1_eig_noalloc(const double* d, const double* z, double rho, int64_t n, do
   int64_t nblocks = (n + WAVE - 1) / WAVE;
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
   return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
-                      mu, xnorm, info, stats, o, W, nblocks, 0, 0, (hipStream_t)stream);
+                      mu, xnorm, info, stats, o, W, nblocks, 0, 0, (hipStream_t)stream,
+                      /*aux_ok=*/false);
 }
 
 // ------------------------------------------------------------ batched

@@ -27,7 +27,8 @@ STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "ite
 class Opts(C.Structure):
     _fields_ = [("mode_b", C.c_int32), ("root", C.c_int32), ("polish", C.c_int32),
                 ("split", C.c_int32), ("kappa_polish", C.c_double), ("nearzero", C.c_double),
-                ("main_passes", C.c_int32), ("waves_per_simd", C.c_int32), ("events", C.c_void_p)]
+                ("main_passes", C.c_int32), ("waves_per_simd", C.c_int32), ("events", C.c_void_p),
+                ("vwrite", C.c_int32)]
 
 
 class Plan(C.Structure):
@@ -86,8 +87,8 @@ def lib():
 
 
 def opts(mode_b=0, root=1, polish=1, split=0, kappa_polish=16.0, nearzero=10.0, main_passes=0,
-         events=None, waves_per_simd=0) -> Opts:
-    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, main_passes, waves_per_simd, events)
+         events=None, waves_per_simd=0, vwrite=0) -> Opts:
+    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, main_passes, waves_per_simd, events, vwrite)
 
 
 class HipEvents:
