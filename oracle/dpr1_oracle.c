@@ -69,6 +69,9 @@ typedef struct {
   int32_t polish;        /* 1: extended-precision polish when flagged        */
   double kappa_polish;   /* threshold on kappa_g*max(1,|mu/lambda|)          */
   double nearzero;       /* factor of the near-zero test                     */
+  int32_t remedy;        /* 1: remedies (R1)/(R2) where K_nu > knu_thr       */
+  int32_t pad;
+  double knu_thr;        /* threshold on K_nu of eq. (K0)                    */
 } oracle_opts;
 
 typedef struct {
@@ -83,6 +86,10 @@ typedef struct {
   double sigma, mu, nu, lambda, b;
   double Kb, Kz, kappa_nu_bound, kappa_g;
   double xnorm;          /* ||x||_2 of the unnormalised eigenvector          */
+  double Knu;            /* K_nu of eq. (K0) at the shift pole (all-pairs
+                            driver only; 0 where not computed)              */
+  int32_t remedied;      /* 0 none, 1 remedy (R1), 2 remedy (R2)             */
+  int32_t pad2;
 } oracle_eigdiag;
 
 #define ORC_OK 0
@@ -97,6 +104,9 @@ void oracle_default_opts(oracle_opts* o) {
   o->polish = 1;
   o->kappa_polish = 16.0;
   o->nearzero = 10.0;
+  o->remedy = 0;
+  o->pad = 0;
+  o->knu_thr = 32.0;
 }
 
 /* ---------------------------------------------------------------- helpers */
@@ -219,9 +229,12 @@ static quad b_quad(const double* d, const double* z, int64_t n, int64_t i, doubl
 
 /* ----------------------------------------------------- one eigenpair */
 
-int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int64_t k,
-                   const oracle_opts* opts_in, double* lambda_out, double* v_out,
-                   oracle_eigdiag* dg_out) {
+/* One eigenpair; force_i >= 0 takes the shift pole d_{force_i} (k or k-1)
+ * instead of Algorithm 1's test (remedy (R1)); nuq_out (nullable) receives
+ * nu after one more Newton step with g in binary128, carried in binary128. */
+static int dpr1eig_at(const double* d, const double* z, double rho, int64_t n, int64_t k,
+                      const oracle_opts* opts_in, double* lambda_out, double* v_out,
+                      oracle_eigdiag* dg_out, int64_t force_i, quad* nuq_out) {
   oracle_opts opts;
   if (opts_in) opts = *opts_in; else oracle_default_opts(&opts);
   oracle_eigdiag dg;
@@ -245,7 +258,9 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
    * the nearest pole; otherwise (including F == 0) d_{k-1}. */
   int64_t i;
   int side;
-  if (k == 0) {
+  if (force_i >= 0) {
+    i = force_i; side = (i == k) ? 1 : -1;
+  } else if (k == 0) {
     i = 0; side = 1;
   } else {
     double tau = (d[k - 1] - d[k]) / 2;
@@ -445,6 +460,11 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
     mu = 1.0 / nu;
     lam = sigma + mu;
   }
+  if (nuq_out) {
+    quad gq, gpq;
+    g_quad(d, z, &A, nu, &gq, &gpq, NULL);
+    *nuq_out = (quad)nu - gq / gpq;
+  }
 
   /* Near-zero eigenvalue (eq. gamma): lambda much closer to zero than to its
    * neighbouring poles.  Then all poles are non-zero and lambda = 1/eta with
@@ -535,6 +555,114 @@ int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int6
   return ORC_OK;
 }
 
+int oracle_dpr1eig(const double* d, const double* z, double rho, int64_t n, int64_t k,
+                   const oracle_opts* opts_in, double* lambda_out, double* v_out,
+                   oracle_eigdiag* dg_out) {
+  return dpr1eig_at(d, z, rho, n, k, opts_in, lambda_out, v_out, dg_out, -1, NULL);
+}
+
+/* ------------------------------------------------- K_nu and the remedies */
+/* ||A_i^{-1}||_2 = 1/min_j |lambda_j - d_i|, and by the interlacing
+ * (eq. interlace) the minimum is taken at one of the two eigenvalues beside
+ * the pole d_i: lambda_k itself or lambda_o, o = k+1 when i = k, o = k-1 when
+ * i = k-1.  So K_nu of eq. (K0) for eigenpair k shifted to d_i is
+ * |lambda_k - d_i| / min(|lambda_k - d_i|, |lambda_o - d_i|), the distances
+ * taken from the shifted representations (sigma_j, mu_j) in binary128.  For
+ * a pole p other than the shift, the same with |lambda_k - d_p|. */
+static double knu_at(const double* d, int64_t n, const oracle_eigdiag* dg, int64_t k, int64_t p) {
+  quad lk = fabsq(((quad)dg[k].sigma - (quad)d[p]) + (quad)dg[k].mu);
+  int64_t o = (p == k) ? k + 1 : k - 1;   /* the other eigenvalue beside d_p */
+  if (o < 0 || o >= n || lk == 0) return 1.0;
+  quad lo = fabsq(((quad)dg[o].sigma - (quad)d[p]) + (quad)dg[o].mu);
+  if (lo >= lk) return 1.0;
+  return lo > 0 ? (double)(lk / lo) : INFINITY;
+}
+
+/* v = x/||x||, x_j = zeta_j/((d_j - d_i) - mu) (eq. eigenvecAi) for the
+ * shifted representation (i, mu); ||x|| accumulated in binary128. */
+static double vector_from(const double* d, const double* z, int64_t n, int64_t i, double mu, double* v) {
+  quad nq = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    double xj = (j == i) ? -z[i] / mu : z[j] / ((d[j] - d[i]) - mu);
+    nq += (quad)xj * (quad)xj;
+  }
+  double xn = (double)sqrtq(nq);
+  if (v)
+    for (int64_t j = 0; j < n; ++j) {
+      double xj = (j == i) ? -z[i] / mu : z[j] / ((d[j] - d[i]) - mu);
+      v[j] = xj / xn;
+    }
+  return xn;
+}
+
+/* Remedy (R2): invert A - sigma I with sigma between d_i and lambda, near
+ * lambda (sigma = d_i + mu (1 - t), in binary128), so that lambda - sigma is the
+ * eigenvalue of A - sigma I closest to zero.  Its inverse is the DPR1 matrix
+ * E + gamma u u^T with e_j = 1/(d_j - sigma), u_j = zeta_j e_j,
+ * gamma = -rho/f(sigma), f(sigma) = 1 + rho sum zeta_j^2/(d_j - sigma) (the
+ * same form as eq. gamma, shifted), everything in binary128 ("the DPR1 matrix
+ * must be computed in double the working precision").  eta = 1/(lambda -
+ * sigma) is its exterior eigenvalue: the root of h(eta) = 1 + gamma sum
+ * u_j^2/(e_j - eta) right of every e_j when mu > 0 (then f(sigma) < 0), left of
+ * every e_j when mu < 0.  Returns mu_new = lambda - d_i = (sigma - d_i) + 1/eta,
+ * or NaN when no sigma on the right side of lambda is found. */
+static double remedy_r2(const double* d, const double* z, double rho, int64_t n, int64_t i, double mu) {
+  const int pos = mu > 0;
+  for (int e = 20; e >= 2; e -= 6) {
+    const quad ms = (quad)mu * (1 - ldexpq(1, -e));   /* sigma - d_i */
+    const quad sg = (quad)d[i] + ms;
+    quad f = 1, uu = 0, emax = -(quad)INFINITY, emin = (quad)INFINITY, emag = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      quad dl = (quad)d[j] - sg;
+      quad zj = (quad)z[j];
+      f += (quad)rho * zj * zj / dl;
+      quad ej = 1 / dl, uj = zj / dl;
+      uu += uj * uj;
+      if (ej > emax) emax = ej;
+      if (ej < emin) emin = ej;
+      if (fabsq(ej) > emag) emag = fabsq(ej);
+    }
+    if (pos ? !(f < 0) : !(f > 0)) continue;      /* sigma is not between d_i and lambda */
+    const quad gam = -(quad)rho / f;
+    const quad ub = (emag + fabsq(gam) * uu) * (1 + ldexpq(1, -40));
+    /* bisection on the binary64 numbers of eta, h in binary128 */
+    /* eta has the sign of mu: the bracket stays on that side of 0 */
+    double lo, hi;
+    if (pos) {
+      lo = nextafter(emax > 0 ? (double)emax : 0.0, INFINITY);
+      hi = nextafter((double)ub, INFINITY);
+    } else {
+      lo = nextafter(-(double)ub, -INFINITY);
+      hi = nextafter(emin < 0 ? (double)emin : -0.0, -INFINITY);
+    }
+    for (int it = 0; it < 200 && !adjacent(lo, hi); ++it) {
+      double m = fmid(lo, hi);
+      quad hsum = 0;
+      for (int64_t j = 0; j < n; ++j) {
+        quad dl = (quad)d[j] - sg;
+        quad ej = 1 / dl, uj = (quad)z[j] / dl;
+        hsum += uj * uj / (ej - (quad)m);
+      }
+      quad h = 1 + gam * hsum;
+      /* right branch (gamma > 0): h rises from -inf to 1, the root is above m
+       * where h < 0; left branch (gamma < 0): h falls from 1 to -inf, the root
+       * is above m where h > 0 */
+      if (pos ? (h < 0) : (h > 0)) lo = m; else hi = m;
+    }
+    /* one Newton step in binary128 from the bracket end away from the poles */
+    quad et = pos ? (quad)hi : (quad)lo, hs = 0, hp = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      quad dl = (quad)d[j] - sg;
+      quad ej = 1 / dl, uj = (quad)z[j] / dl, den = ej - et;
+      hs += uj * uj / den;
+      hp += uj * uj / (den * den);
+    }
+    et = et - (1 + gam * hs) / (gam * hp);
+    return (double)(ms + 1 / et);
+  }
+  return NAN;
+}
+
 /* ------------------------------------------------------- all eigenpairs */
 /* rho < 0 is reduced to rho > 0 as in Sec. 1: the eigenpairs of
  * D + rho z z^T are those of -((-D) + (-rho) z z^T); -D is put back in
@@ -546,6 +674,8 @@ int oracle_dpr1eig_all(const double* d, const double* z, double rho, int64_t n,
   int rc = oracle_check(d, z, rho, n);
   if (rc != ORC_OK) return rc;
   if (V && ldv < n) return ORC_EARG;
+  oracle_opts op;
+  if (opts) op = *opts; else oracle_default_opts(&op);
   const double* dd = d;
   const double* zz = z;
   double r = rho;
@@ -557,6 +687,8 @@ int oracle_dpr1eig_all(const double* d, const double* z, double rho, int64_t n,
     for (int64_t j = 0; j < n; ++j) { dn[j] = -d[n - 1 - j]; zn[j] = z[n - 1 - j]; }
     dd = dn; zz = zn; r = -rho;
   }
+  /* diagnostics in the order of the solved problem (rho > 0) */
+  oracle_eigdiag* dgs = (oracle_eigdiag*)calloc((size_t)n, sizeof(oracle_eigdiag));
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel
@@ -568,18 +700,88 @@ int oracle_dpr1eig_all(const double* d, const double* z, double rho, int64_t n,
 #endif
     for (int64_t k = 0; k < n; ++k) {
       double lam;
-      oracle_eigdiag dg;
-      oracle_dpr1eig(dd, zz, r, n, k, opts, &lam, v, &dg);
+      oracle_dpr1eig(dd, zz, r, n, k, &op, &lam, v, &dgs[k]);
       int64_t ko = neg ? n - 1 - k : k;
       lambda[ko] = neg ? -lam : lam;
       if (V) {
         if (neg) for (int64_t j = 0; j < n; ++j) V[ko * ldv + (n - 1 - j)] = -v[j];
         else for (int64_t j = 0; j < n; ++j) V[ko * ldv + j] = v[j];
       }
-      if (diags) diags[ko] = dg;
     }
     free(v);
   }
+  /* K_nu of eq. (K0) for every eigenpair, from its neighbours' shifted
+   * representations; with opts.remedy, Algorithm 1's last branch: where
+   * K_nu > knu_thr, remedy (R1) -- the other neighbouring pole, when its K_nu
+   * is smaller and below the threshold -- else remedy (R2).  The remedied
+   * eigenvalue is then represented from its nearest pole d_i again (mu =
+   * lambda - d_i in binary128), and v and ||x|| are recomputed from it. */
+  double* kn = (double*)malloc(sizeof(double) * n);
+  for (int64_t k = 0; k < n; ++k) kn[k] = (n > 1) ? knu_at(dd, n, dgs, k, dgs[k].i) : 1.0;
+  for (int64_t k = 0; k < n; ++k) dgs[k].Knu = kn[k];
+  if (op.remedy && n > 1) {
+    int64_t* todo = (int64_t*)malloc(sizeof(int64_t) * n);
+    int64_t nt = 0;
+    for (int64_t k = 0; k < n; ++k)
+      if (kn[k] > op.knu_thr && !dgs[k].nearzero) todo[nt++] = k;   /* eq. (gamma) keeps its lambda */
+    oracle_eigdiag* upd = (oracle_eigdiag*)malloc(sizeof(oracle_eigdiag) * (nt > 0 ? nt : 1));
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+      double* v = V ? (double*)malloc(sizeof(double) * n) : NULL;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+      for (int64_t t = 0; t < nt; ++t) {
+        const int64_t k = todo[t];
+        oracle_eigdiag g = dgs[k];
+        const int64_t i = g.i;
+        const int64_t p = (i == k) ? k - 1 : k;   /* the other neighbouring pole */
+        double mu_new = NAN;
+        int how = 0;
+        if (k >= 1 && p >= 0 && knu_at(dd, n, dgs, k, p) < kn[k] && knu_at(dd, n, dgs, k, p) <= op.knu_thr) {
+          /* (R1): eigenpair k with the shift at d_p.  mu_i = (d_p - d_i) +
+           * mu_p carries the absolute error of mu_p, |mu_p/mu_i| times larger
+           * relative to mu_i, so nu_p is refined and carried in binary128 */
+          oracle_eigdiag gp;
+          double lp;
+          quad nuq = 0;
+          oracle_opts o1 = op;
+          o1.polish = 1;
+          o1.kappa_polish = 0.0;
+          dpr1eig_at(dd, zz, r, n, k, &o1, &lp, NULL, &gp, p, &nuq);
+          mu_new = (double)(((quad)dd[p] - (quad)dd[i]) + 1 / nuq);
+          how = 1;
+        } else {
+          mu_new = remedy_r2(dd, zz, r, n, i, g.mu);
+          how = 2;
+        }
+        if (mu_new == mu_new && mu_new != 0.0) {
+          g.mu = mu_new;
+          g.nu = 1.0 / mu_new;
+          g.lambda = (double)((quad)dd[i] + (quad)mu_new);
+          g.remedied = how;
+          g.xnorm = vector_from(dd, zz, n, i, mu_new, v);
+          const int64_t ko = neg ? n - 1 - k : k;
+          lambda[ko] = neg ? -g.lambda : g.lambda;
+          if (V) {
+            if (neg) for (int64_t j = 0; j < n; ++j) V[ko * ldv + (n - 1 - j)] = -v[j];
+            else for (int64_t j = 0; j < n; ++j) V[ko * ldv + j] = v[j];
+          }
+        }
+        upd[t] = g;
+      }
+      free(v);
+    }
+    for (int64_t t = 0; t < nt; ++t) dgs[todo[t]] = upd[t];
+    free(upd);
+    free(todo);
+  }
+  if (diags)
+    for (int64_t k = 0; k < n; ++k) diags[neg ? n - 1 - k : k] = dgs[k];
+  free(kn);
+  free(dgs);
   free(dn);
   return ORC_OK;
 }

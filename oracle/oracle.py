@@ -32,7 +32,8 @@ def build(force: bool = True) -> str:
 
 class Opts(C.Structure):
     _fields_ = [("mode_b", C.c_int32), ("polish", C.c_int32),
-                ("kappa_polish", C.c_double), ("nearzero", C.c_double)]
+                ("kappa_polish", C.c_double), ("nearzero", C.c_double),
+                ("remedy", C.c_int32), ("pad", C.c_int32), ("knu_thr", C.c_double)]
 
 
 class EigDiag(C.Structure):
@@ -42,7 +43,7 @@ class EigDiag(C.Structure):
                 ("sigma", C.c_double), ("mu", C.c_double), ("nu", C.c_double),
                 ("lam", C.c_double), ("b", C.c_double), ("Kb", C.c_double),
                 ("Kz", C.c_double), ("kappa_nu_bound", C.c_double), ("kappa_g", C.c_double),
-                ("xnorm", C.c_double)]
+                ("xnorm", C.c_double), ("Knu", C.c_double), ("remedied", C.c_int32), ("pad2", C.c_int32)]
 
 
 DIAG_FIELDS = [f for f, _ in EigDiag._fields_]
@@ -76,8 +77,8 @@ def _p(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
 
 
-def make_opts(mode_b=0, polish=1, kappa_polish=16.0, nearzero=10.0) -> Opts:
-    return Opts(mode_b, polish, kappa_polish, nearzero)
+def make_opts(mode_b=0, polish=1, kappa_polish=16.0, nearzero=10.0, remedy=0, knu_thr=32.0) -> Opts:
+    return Opts(mode_b, polish, kappa_polish, nearzero, remedy, 0, knu_thr)
 
 
 def diag_to_dict(dg: np.ndarray | EigDiag):

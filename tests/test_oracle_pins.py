@@ -276,6 +276,58 @@ def test_truth_arrow_beyond_binary64_large(orc, seed, ks):
     assert _pin_pairs(orc, d, z, rho, ks) >= 1
 
 
+# K_nu of eq. (K0) and the remedies (R1)/(R2) of Sec. 2 (Algorithm 1, last branch).
+def _knu_truth(d, k, i, tr_all):
+    """K_nu from the 256-bit eigenvalues: |lambda_k - d_i| / min |lambda_j - d_i|."""
+    with mp.workprec(T.PREC):
+        di = mp.mpf(float(d[i]))
+        return float(abs(tr_all[k]["lam"] - di) / min(abs(t["lam"] - di) for t in tr_all))
+
+
+@pytest.mark.parametrize("case", ["uniform48", "graded96", "rho10_64"])
+def test_knu_against_truth(orc, case):
+    """The oracle's K_nu (from its neighbours' shifted representations) equals ||A_i^{-1}||_2/|nu|
+    computed from the 256-bit eigenvalues, for every eigenpair."""
+    d, z, rho = {"uniform48": W.uniform(48, 0), "graded96": W.graded(96, 1, pair_every=12),
+                 "rho10_64": W.uniform(64, 11, rho=10.0)}[case]
+    lam, _, dg = orc.eig(d, z, rho, vectors=False, diags=True)
+    tr = T.eig(d, z, rho, vectors=False)
+    big = 0
+    for k in range(len(d)):
+        kt = _knu_truth(d, k, dg[k]["i"], tr)
+        assert abs(dg[k]["Knu"] - kt) <= 1e-10 * kt, (k, dg[k]["Knu"], kt)
+        big += kt > 32
+    assert big >= 1
+
+
+@pytest.mark.parametrize("case", ["C1_256", "graded96", "rho10_128", "uniform_zsqrt_256"])
+def test_remedies_against_truth(orc, case):
+    """With the double-precision polish off, the remedies alone keep every eigenpair whose K_nu
+    exceeds the threshold accurate: lambda and mu within 2e-14 of the 256-bit truth, v within
+    5e-14, and the shift index of the nearest pole kept; (R1) and (R2) are both exercised."""
+    d, z, rho = {"C1_256": W.uniform(256, 0), "graded96": W.graded(96, 1, pair_every=12),
+                 "rho10_128": W.uniform(128, 11, rho=10.0),
+                 "uniform_zsqrt_256": W.uniform(256, 2, zscale=1 / 16)}[case]
+    o = orc.make_opts(polish=0, remedy=1)
+    lam, V, dg = orc.eig(d, z, rho, diags=True, opts=o)
+    ks = [k for k in range(len(d)) if dg[k]["remedied"]]
+    assert len(ks) >= 1 and all(dg[k]["Knu"] > 32 for k in ks)
+    tr = T.eig(d, z, rho, ks=ks)
+    for m, k in enumerate(ks):
+        assert dg[k]["i"] == tr[m]["i"], k
+        assert T.rel(lam[k], tr[m]["lam"]) <= 2e-14, k
+        assert T.rel(dg[k]["mu"], tr[m]["mu"]) <= 2e-14, k
+        assert max(T.rel(V[j, k], tr[m]["v"][j]) for j in range(len(d))) <= 5e-14, k
+
+
+def test_remedies_use_both_kinds(orc):
+    kinds = set()
+    for d, z, rho in (W.uniform(256, 0), W.uniform(128, 11, rho=10.0)):
+        _, _, dg = orc.eig(d, z, rho, vectors=False, diags=True, opts=orc.make_opts(polish=0, remedy=1))
+        kinds |= {g["remedied"] for g in dg}
+    assert {1, 2} <= kinds
+
+
 def test_negative_rho_reduction(orc):
     d, z, _ = W.uniform(24, 5)
     lam, V = orc.eig(d, z, -0.7)
