@@ -84,7 +84,10 @@ extern "C" {
 #define DPR1_STAT_POLISH_STEPS_MAX 7 /* most double-double steps one polish
                                  took (including the one that confirmed the
                                  root)                                      */
-#define DPR1_NSTATS 8
+#define DPR1_STAT_KNU_GT 8    /* eigenpairs with K_nu > knu_thr (eq. K0)     */
+#define DPR1_STAT_REMEDY_R1 9 /* eigenpairs recomputed by remedy (R1)        */
+#define DPR1_STAT_REMEDY_R2 10 /* eigenpairs recomputed by remedy (R2)       */
+#define DPR1_NSTATS 11
 
 /* Options.  dpr1_default_opts fills the defaults noted below.               */
 typedef struct dpr1_opts {
@@ -128,6 +131,19 @@ typedef struct dpr1_opts {
                           default priority) while the second half is solved;
                           1 every column after the eigenvalue kernel, on
                           `stream` only.  dpr1_eig_noalloc always uses 1.    */
+  int32_t remedy;      /* Sec. 2, Algorithm 1's last branch: 1 = where K_nu
+                          of eq. (K0) exceeds knu_thr, recompute the
+                          eigenpair by remedy (R1) -- the other neighbouring
+                          pole, when its K_nu is smaller and below the
+                          threshold -- else by remedy (R2) -- A - sigma I with
+                          sigma between the nearest pole and lambda, its
+                          inverse in double-double; 0 (default) = K_nu only
+                          counted (and written to knu); the double-double
+                          polish (polish) acts either way                   */
+  double knu_thr;      /* threshold on K_nu; default 32                     */
+  double* knu;         /* optional device output [n] (a batch: [sum n_p],
+                          packed like lambda): K_nu of every eigenpair,
+                          ||A_i^{-1}||_2/|nu| at its shift pole             */
 } dpr1_opts;
 
 void dpr1_default_opts(dpr1_opts* opts);

@@ -96,7 +96,9 @@ struct KArgs {
   int32_t main_passes;
   double kappa_polish, nearzero;
   int32_t g0;           // single problem: first group of 64 eigenvalues of this launch
-  int32_t pad2;
+  int32_t remedy;       // apply (R1)/(R2) where K_nu > knu_thr
+  double knu_thr;
+  double* knu;          // optional output: K_nu per eigenpair (caller's order)
 };
 
 // ------------------------------------------------------------ bit helpers
@@ -109,6 +111,13 @@ __device__ __forceinline__ double fmid(double lo, double hi) {
   return unbits(a + (b - a) / 2);
 }
 __device__ __forceinline__ bool adjacent(double lo, double hi) { return bits(hi) - bits(lo) <= 1; }
+// the same for lo < hi of one sign (both negative: the bit patterns run backwards)
+__device__ __forceinline__ bool adjacent_signed(double lo, double hi) {
+  return lo > 0.0 ? bits(hi) - bits(lo) <= 1 : bits(lo) - bits(hi) <= 1;
+}
+__device__ __forceinline__ double fmid_signed(double lo, double hi) {
+  return lo > 0.0 ? fmid(lo, hi) : -fmid(-hi, -lo);
+}
 
 // Reciprocal from the hardware estimate refined by one Newton step: for the
 // signs that steer bisection, and as the seed of a quotient that is then
@@ -1061,6 +1070,86 @@ __device__ __forceinline__ double block_sum_comp3(double s, double c, double& a,
   return S + C;
 }
 
+// Safeguarded iteration for the extreme root of g (eq. secAi) at the shift
+// pole d_i (side s), g evaluated in double-double: far from the root the
+// rational model step of the main solver, close to it Newton (g exact to
+// ~2^-100, so the last step lands on the rounded root).  b' = s b in
+// double-double, xm the nearest pole of g (in nu), (lo0, hi0) a rigorous
+// bracket, cur the start.  Returns the last iterate; *last receives the
+// Newton correction at it (nu = cur + *last to about 2^-100), *steps the
+// number of double-double evaluations.  All threads of the block call it and
+// return the same values.
+__device__ double dd_polish(const double2* Z2v, const double* Zl, int n, int i, double s, double sigma, double zi,
+                           dd bdd, double xm, double lo0, double hi0, double cur, double* last, int* steps,
+                           double* sm) {
+  const int tid = threadIdx.x;
+  const double zi2 = zi * zi;
+  double lo = lo0, hi = hi0;
+  if (!(cur > lo && cur < hi)) cur = fmid(lo, hi);
+  // progress guard: when |g| has not halved over two steps away from the
+  // final Newton phase, the model is not describing g (a pole one ulp from
+  // the shift pole dominates it), and the step is a bisection
+  double gprev = INFINITY, newton = 0.0;
+  int slow = 0, pit;
+  for (pit = 0; pit < 100; ++pit) {
+    dd acc = {0.0, 0.0};
+    double sp = 0.0;
+#pragma unroll 4
+    for (int j = tid; j < n; j += FIXT) {
+      if (j == i) continue;
+      const double2 pj = Z2v[j];
+      double dj = pj.x, z2 = pj.y;
+      dd dl = two_sum(s * dj, -s * sigma);               // delta'_j exactly
+      dd pp = dd_add(dd_mul_d(dl, cur), dd{-1.0, 0.0});   // nu delta' - 1
+      dd q = dd_mul(dl, pp);
+      if (!(q.hi < DBL_MAX)) q = {DBL_MAX, 0.0};  // beyond binary64: the term is 0
+      // (zeta_j^2 hi + lo)/q: leading quotient from the refined reciprocal
+      // (2^-48.7) and one residual correction, about 2^-97
+      const double r = rcp_1nr(q.hi);
+      const double q1 = z2 * r;
+      double e = __builtin_fma(-q1, q.hi, z2);
+      e = __builtin_fma(-q1, q.lo, e + Zl[j]);
+      dd t = fast_two_sum(q1, e * r);
+      acc = dd_add_same(acc, t);
+      sp += z2 * rcp_1nr(pp.hi * pp.hi);  // g' only steers the step
+    }
+    acc = block_sum_same(acc, sm);
+    sp = block_sum(sp, sm);
+    dd Sdd = dd_div_sq(acc, zi);
+    dd gd = dd_add(dd_add(bdd, dd{-cur, 0.0}), Sdd);
+    double Spz = sp / zi2;
+    double gpv = -1.0 - Spz;
+    newton = 0.0;
+    if (gd.hi == 0.0) break;
+    if (gd.hi > 0) lo = cur; else hi = cur;
+    const double ag = fabs(gd.hi);
+    slow = ag > 0.5 * gprev ? slow + 1 : 0;
+    gprev = ag;
+    newton = -(gd.hi + gd.lo) / gpv;
+    double t;
+    if (fabs(newton) <= 0x1p-30 * cur) {
+      t = cur + newton;
+    } else {
+      double x = cur - xm;
+      double Am = Spz * x * x;
+      double C = (bdd.hi + (Sdd.hi - Spz * x)) - xm;
+      double disc = sqrt(C * C + 4.0 * Am);
+      double u = C >= 0 ? (C + disc) * 0.5 : (2.0 * Am) / (disc - C);
+      t = xm + u;
+    }
+    // stay inside the sign bracket and off the pole / rigorous lower end
+    if (!(t >= lo && t <= hi) || !(t > lo0) || !(t < INFINITY) || (slow >= 2 && fabs(newton) > 0x1p-30 * cur)) {
+      t = fmid(lo, hi);
+      slow = 0;
+    }
+    if (t == cur) break;
+    cur = t;
+  }
+  *last = fabs(newton) <= 0x1p-30 * cur ? newton : 0.0;
+  *steps = pit;
+  return cur;
+}
+
 // Item e of the list: the n0 long items sit at the front, the others at the
 // back in reverse order.
 __device__ __forceinline__ int fix_slot(const KArgs& A, int n0, int e) {
@@ -1175,74 +1264,12 @@ __device__ void fix_items(const KArgs& A) {
     }
 
     if (pol) {
-      // Safeguarded iteration with g evaluated in double-double: far from the
-      // root the rational model step of the main solver, close to it Newton
-      // (g exact to ~2^-100, so the last step lands on the rounded root).
       const dd bdd = {it.bhi, it.blo};
       const double xm = (k > 0) ? 1.0 / (Dv[k - 1] - Dv[k]) : 0.0;
-      double lo = it.lo, hi = it.hi;
       double cur = nu1;
-      if (!(cur > lo && cur < hi)) cur = nu0;
-      if (!(cur > lo && cur < hi)) cur = fmid(lo, hi);
-      // progress guard: when |g| has not halved over two steps away from the
-      // final Newton phase, the model is not describing g (a pole one ulp
-      // from the shift pole dominates it), and the step is a bisection
-      double gprev = INFINITY;
-      int slow = 0;
-      for (pit = 0; pit < 100; ++pit) {
-        dd acc = {0.0, 0.0};
-        double sp = 0.0;
-        #pragma unroll 4
-        for (int j = tid; j < n; j += FIXT) {
-          if (j == i) continue;
-          const double2 pj = Z2v[j];
-          double dj = pj.x, z2 = pj.y;
-          dd dl = two_sum(s * dj, -s * sigma);                   // delta'_j exactly
-          dd pp = dd_add(dd_mul_d(dl, cur), dd{-1.0, 0.0});       // nu delta' - 1
-          dd q = dd_mul(dl, pp);
-          if (!(q.hi < DBL_MAX)) q = {DBL_MAX, 0.0};  // beyond binary64: the term is 0
-          // (zeta_j^2 hi + lo)/q: leading quotient from the refined
-          // reciprocal (2^-48.7) and one residual correction, about 2^-97
-          const double r = rcp_1nr(q.hi);
-          const double q1 = z2 * r;
-          double e = __builtin_fma(-q1, q.hi, z2);
-          e = __builtin_fma(-q1, q.lo, e + Zl[j]);
-          dd t = fast_two_sum(q1, e * r);
-          acc = dd_add_same(acc, t);
-          sp += z2 * rcp_1nr(pp.hi * pp.hi);  // g' only steers the step
-        }
-        acc = block_sum_same(acc, sm);
-        sp = block_sum(sp, sm);
-        dd Sdd = dd_div_sq(acc, zi);
-        dd gd = dd_add(dd_add(bdd, dd{-cur, 0.0}), Sdd);
-        double Spz = sp / zi2;
-        double gpv = -1.0 - Spz;
-        if (gd.hi == 0.0) break;
-        if (gd.hi > 0) lo = cur; else hi = cur;
-        const double ag = fabs(gd.hi);
-        slow = ag > 0.5 * gprev ? slow + 1 : 0;
-        gprev = ag;
-        double newton = -(gd.hi + gd.lo) / gpv;
-        double t;
-        if (fabs(newton) <= 0x1p-30 * cur) {
-          t = cur + newton;
-        } else {
-          double x = cur - xm;
-          double Am = Spz * x * x;
-          double C = (bdd.hi + (Sdd.hi - Spz * x)) - xm;
-          double disc = sqrt(C * C + 4.0 * Am);
-          double u = C >= 0 ? (C + disc) * 0.5 : (2.0 * Am) / (disc - C);
-          t = xm + u;
-        }
-        // stay inside the sign bracket and off the pole / rigorous lower end
-        if (!(t >= lo && t <= hi) || !(t > it.lo) || !(t < INFINITY) ||
-            (slow >= 2 && fabs(newton) > 0x1p-30 * cur)) {
-          t = fmid(lo, hi);
-          slow = 0;
-        }
-        if (t == cur) break;
-        cur = t;
-      }
+      if (!(cur > it.lo && cur < it.hi)) cur = nu0;
+      double last;
+      cur = dd_polish(Z2v, Zl, n, i, s, sigma, zi, bdd, xm, it.lo, it.hi, cur, &last, &pit, sm);
       muv = s / cur;
       lam = sigma + muv;
       polished = true;
@@ -1334,6 +1361,7 @@ __device__ void fix_items(const KArgs& A) {
     }
     if (tid == 0) {
       A.lam[off + k] = lam;
+      if (nz) A.vflag[off + k] = 2;  // lambda from eq. (gamma): no remedy of K_nu
       if (polished || have_xs) {
         A.mu[off + k] = muv;
         A.xs[off + k] = fabs(it.bhi) < INFINITY ? xsv : NAN;
@@ -1628,6 +1656,262 @@ __global__ void __launch_bounds__(256) k_fixout(KArgs A, double* __restrict__ la
   }
 }
 
+// ------------------------------------------------------- K_nu, remedies
+// K_nu of eq. (K0) for eigenpair k shifted to d_i: ||A_i^{-1}||_2 =
+// 1/min_j |lambda_j - d_i|, and by the interlacing (eq. interlace) the
+// minimum is taken at lambda_k or at the other eigenvalue beside the pole,
+// lambda_o (o = k+1 if i = k, o = k-1 if i = k-1), so
+// K_nu = |lambda_k - d_i| / min(|lambda_k - d_i|, |lambda_o - d_i|), with the
+// distances from the shifted representations in double-double.  knu_pole
+// gives it for any neighbouring pole p of lambda_k (remedy (R1) compares the
+// two).
+__device__ double knu_pole(const double* Dv, const int32_t* ii, const double* mu, int n, int k, int p) {
+  const dd lk = dd_add(two_sum(Dv[ii[k]], -Dv[p]), dd{mu[k], 0.0});
+  const double ak = fabs(lk.hi + lk.lo);
+  const int o = (p == k) ? k + 1 : k - 1;
+  if (o < 0 || o >= n || ak == 0.0) return 1.0;
+  const dd lo = dd_add(two_sum(Dv[ii[o]], -Dv[p]), dd{mu[o], 0.0});
+  const double ao = fabs(lo.hi + lo.lo);
+  if (ao >= ak) return 1.0;
+  return ao > 0.0 ? ak / ao : INFINITY;
+}
+
+// A remedy: eigenpair k of problem p, nearest pole i; po the other
+// neighbouring pole for (R1), -1 for (R2).
+struct RemItem {
+  int32_t p, k, i, po;
+};
+
+// One thread per eigenpair (a batch: block p takes problem p): K_nu to the
+// optional output, the count of K_nu > knu_thr, and with opts.remedy the
+// remedy list (in the eigenpair list's memory, free once k_fix has run).
+// Pairs whose eigenvalue came from eq. (gamma) (vflag 2) keep it.
+__global__ void __launch_bounds__(256) k_knu(KArgs A, int nprob) {
+  const int p = nprob > 1 ? (int)blockIdx.x : 0;
+  const int k0 = nprob > 1 ? (int)threadIdx.x : (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int kstep = nprob > 1 ? (int)blockDim.x : (int)(gridDim.x * blockDim.x);
+  if (p >= nprob) return;
+  const Meta M = A.meta[p];
+  if (M.info != 0) return;
+  const int n = M.n;
+  const int64_t off = M.off;
+  const double* Dv = A.sd + off;
+  const int32_t* ii = A.ii + off;
+  const double* mu = A.mu + off;
+  RemItem* list = reinterpret_cast<RemItem*>(A.fix);
+  for (int k = k0; k < n; k += kstep) {
+    const int i = ii[k];
+    const double K = n > 1 ? knu_pole(Dv, ii, mu, n, k, i) : 1.0;
+    if (A.knu) A.knu[off + (M.neg ? n - 1 - k : k)] = K;
+    if (!(K > A.knu_thr)) continue;
+    if (A.stats) atomicAdd(&A.stats[DPR1_STAT_KNU_GT], 1);
+    if (!A.remedy || A.vflag[off + k] == 2) continue;
+    const int po = (i == k) ? k - 1 : k;  // the other neighbouring pole
+    int use = -1;
+    if (k >= 1 && po >= 0) {
+      const double K2 = knu_pole(Dv, ii, mu, n, k, po);
+      if (K2 < K && K2 <= A.knu_thr) use = po;
+    }
+    const int e = atomicAdd(&A.ctr[4], 1);
+    list[e] = RemItem{p, k, i, use};
+  }
+}
+
+// Outputs written by the remedy kernel.
+struct OArgs {
+  double* lam_out;
+  int32_t* idx_out;
+  double* mu_out;
+  double* xn_out;
+  double* V;
+  const int64_t* voffs;
+  int64_t ldv;
+  int32_t* info_out;
+};
+
+// Remedies of Sec. 2 (Algorithm 1, last branch), one block of FIXT threads
+// per listed eigenpair:
+//  (R1) the other neighbouring pole d_po: its tip b (eq. b_ob) in
+//       double-double, the extreme root of its g refined in double-double
+//       (dd_polish from the current eigenvalue), and mu_i = (d_po - d_i) +
+//       mu_po in double-double: mu_i inherits mu_po's absolute error, so the
+//       root is carried to about 2^-100;
+//  (R2) A - sigma I with sigma = d_i + mu (1 - 2^-e) between d_i and lambda
+//       (e = 20, or smaller when the sign of f(sigma) shows sigma past
+//       lambda): its inverse E + gamma u u^T with e_j = 1/(d_j - sigma), u_j =
+//       zeta_j e_j, gamma = -rho/f(sigma), f(sigma) = 1 + rho sum
+//       zeta_j^2/(d_j - sigma) in double-double from the exact differences;
+//       eta = 1/(lambda - sigma) is its exterior eigenvalue (right of every
+//       e_j when mu > 0, left when mu < 0), found by safeguarded Newton steps
+//       from the current estimate; mu_i = (sigma - d_i) + 1/eta.
+// The eigenpair keeps its nearest pole; ||x||, the outputs and its column of
+// V are recomputed from the new mu.
+__global__ void __launch_bounds__(FIXT) k_remedy(KArgs A, OArgs O) {
+  __shared__ double sm[20];
+  const int tid = threadIdx.x;
+  const int cnt = A.ctr[4];
+  const RemItem* list = reinterpret_cast<const RemItem*>(A.fix);
+  for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+    const RemItem it = list[e];
+    const Meta M = A.meta[it.p];
+    const int n = M.n;
+    const int64_t off = M.off;
+    const double* Dv = A.sd + off;
+    const double* Zv = A.sz + off;
+    const double2* Z2v = reinterpret_cast<const double2*>(A.pairs + 2 * off);
+    const double* Zl = A.z2lo + off;
+    const double rho = M.rho;
+    const int k = it.k, i = it.i;
+    const double muk = A.mu[off + k];
+    double newmu = NAN;
+    int how = 0;
+    if (it.po >= 0) {
+      // ---- (R1)
+      const int po = it.po;
+      const double s = (po == k) ? 1.0 : -1.0;
+      const double sigma = Dv[po], zp = Zv[po];
+      dd acc = {0.0, 0.0};
+      for (int j = tid; j < n; j += FIXT) {
+        if (j == po) continue;
+        const double2 pj = Z2v[j];
+        const dd dl = two_sum(pj.x, -sigma);
+        const double r = rcp_1nr(dl.hi);
+        const double q1 = pj.y * r;
+        double er = __builtin_fma(-q1, dl.hi, pj.y);
+        er = __builtin_fma(-q1, dl.lo, er + Zl[j]);
+        acc = dd_add(acc, fast_two_sum(q1, er * r));
+      }
+      acc = block_sum_dd(acc, sm);
+      const dd num = dd_add(dd_div(dd{1.0, 0.0}, dd{rho, 0.0}), acc);
+      const dd b = dd_div_sq(num, zp);
+      const dd bdd = {s * b.hi, s * b.lo};
+      const double xm = 1.0 / (Dv[k - 1] - Dv[k]);
+      // nu at d_po from the current eigenvalue: 1/(s (lambda - d_po))
+      const dd lp = dd_add(two_sum(Dv[i], -sigma), dd{muk, 0.0});
+      double cur = 1.0 / (s * (lp.hi + lp.lo));
+      double last;
+      int steps;
+      cur = dd_polish(Z2v, Zl, n, po, s, sigma, zp, bdd, xm, xm, INFINITY, cur, &last, &steps, sm);
+      const dd nu = fast_two_sum(cur, last);
+      const dd mup = dd_div(dd{s, 0.0}, nu);
+      const dd mi = dd_add(two_sum(sigma, -Dv[i]), mup);
+      newmu = mi.hi + mi.lo;
+      how = 1;
+    } else {
+      // ---- (R2)
+      const bool pos = muk > 0;
+      for (int ex = 20; ex >= 2; ex -= 6) {
+        const double ms = muk * (1.0 - ldexp(1.0, -ex));  // sigma - d_i
+        dd fs = {0.0, 0.0};
+        double uu = 0.0, emax = -INFINITY, emin = INFINITY, emag = 0.0;
+        for (int j = tid; j < n; j += FIXT) {
+          const double2 pj = Z2v[j];
+          const dd dl = dd_add(two_sum(pj.x, -Dv[i]), dd{-ms, 0.0});  // d_j - sigma
+          const double r = rcp_1nr(dl.hi);
+          const double q1 = pj.y * r;
+          double er = __builtin_fma(-q1, dl.hi, pj.y);
+          er = __builtin_fma(-q1, dl.lo, er + Zl[j]);
+          fs = dd_add(fs, fast_two_sum(q1, er * r));
+          const double dr = dl.hi + dl.lo, ej = 1.0 / dr, uj = Zv[j] / dr;
+          uu += uj * uj;
+          emax = fmax(emax, ej);
+          emin = fmin(emin, ej);
+          emag = fmax(emag, fabs(ej));
+        }
+        fs = block_sum_dd(fs, sm);
+        uu = block_sum(uu, sm);
+        emax = -block_min(-emax, sm);
+        emin = block_min(emin, sm);
+        emag = -block_min(-emag, sm);
+        const dd F = dd_add(dd{1.0, 0.0}, dd_mul_d(fs, rho));
+        if (pos ? !(F.hi < 0.0) : !(F.hi > 0.0)) continue;  // sigma is past lambda
+        const double gam = -rho / (F.hi + F.lo);
+        const double ub = (emag + fabs(gam) * uu) * GROW;
+        double lo, hi;
+        if (pos) {
+          lo = emax > 0.0 ? emax : 4.9406564584124654e-324;
+          hi = ub;
+        } else {
+          lo = -ub;
+          hi = emin < 0.0 ? emin : -4.9406564584124654e-324;
+        }
+        // eta from the current estimate 1/(mu - ms), kept in the bracket
+        double cur = 1.0 / (muk - ms);
+        for (int st = 0; st < 80; ++st) {
+          if (!(cur > lo && cur < hi)) cur = fmid_signed(lo, hi);
+          double hs = 0.0, hc = 0.0, hp = 0.0;
+          for (int j = tid; j < n; j += FIXT) {
+            const double2 pj = Z2v[j];
+            const dd dl = dd_add(two_sum(pj.x, -Dv[i]), dd{-ms, 0.0});
+            const double dr = dl.hi + dl.lo, ej = 1.0 / dr, uj = Zv[j] / dr;
+            const double den = ej - cur;
+            const double t = (uj * uj) / den;
+            const double y = hs + t;
+            hc += (fabs(hs) >= fabs(t)) ? ((hs - y) + t) : ((t - y) + hs);
+            hs = y;
+            hp += (uj * uj) / (den * den);
+          }
+          const double S = block_sum_comp(hs, hc, sm);
+          hp = block_sum(hp, sm);
+          const double h = 1.0 + gam * S;
+          if (h == 0.0) break;
+          // right branch: h rises, the root is above where h < 0; left branch:
+          // h falls, the root is above where h > 0
+          if (pos ? (h < 0.0) : (h > 0.0)) lo = cur; else hi = cur;
+          const double step = -h / (gam * hp);
+          double t = cur + step;
+          if (!(t > lo && t < hi)) t = fmid_signed(lo, hi);
+          if (t == cur || fabs(step) <= 0x1p-53 * fabs(cur) || adjacent_signed(lo, hi)) {
+            cur = t > lo && t < hi ? t : cur;
+            break;
+          }
+          cur = t;
+        }
+        newmu = ms + 1.0 / cur;
+        how = 2;
+        break;
+      }
+    }
+    if (!(newmu == newmu) || newmu == 0.0 || !(fabs(newmu) < INFINITY)) continue;
+    // ||x|| scaled by |mu| from the new mu, as after the polish
+    double acc = 0.0;
+    for (int j = tid; j < n; j += FIXT) {
+      const double r = (j == i) ? -1.0 : newmu / ((Dv[j] - Dv[i]) - newmu);
+      acc = __builtin_fma(Z2v[j].y * r, r, acc);
+    }
+    const double xsv = sqrt(block_sum(acc, sm));
+    const double lam = Dv[i] + newmu;
+    const int ko = M.neg ? n - 1 - k : k;
+    const double sg = M.neg ? -1.0 : 1.0;
+    if (tid == 0) {
+      A.mu[off + k] = newmu;
+      A.xs[off + k] = xsv;
+      A.lam[off + k] = lam;
+      const int64_t b = off + ko;
+      O.lam_out[b] = sg * lam;
+      if (O.idx_out) O.idx_out[b] = M.neg ? n - 1 - i : i;
+      if (O.mu_out) O.mu_out[b] = sg * newmu;
+      if (O.xn_out) O.xn_out[b] = xsv / fabs(newmu);
+      if (!range_ok(lam, newmu, xsv)) O.info_out[it.p] = DPR1_INFO_RANGE;
+      if (A.stats) atomicAdd(&A.stats[how == 1 ? DPR1_STAT_REMEDY_R1 : DPR1_STAT_REMEDY_R2], 1);
+    }
+    if (O.V) {
+      const double sc = Dv[i];
+      const double iv = fabs(newmu) / xsv;
+      const int64_t ld = O.voffs ? (int64_t)n : O.ldv;
+      double* col = O.V + (O.voffs ? O.voffs[it.p] : 0) + (int64_t)ko * ld;
+      for (int pos = tid; pos < n; pos += FIXT) {
+        const int j = M.neg ? n - 1 - pos : pos;
+        const double den = (Dv[j] - sc) - newmu;
+        const double rc = rcp_1nr(den);
+        double q = iv * rc;
+        q = __builtin_fma(__builtin_fma(-q, den, iv), rc, q);
+        __builtin_nontemporal_store((sg * Zv[j]) * q, &col[pos]);
+      }
+    }
+  }
+}
+
 // ===================================================================== host
 struct Layout {
   size_t meta, sd, sz, pairs, z2lo, ii, mu, xs, lam, csig, cinv, fix, vflag, items, groups, part, ctr, total;
@@ -1665,6 +1949,7 @@ static void fill_opts(const dpr1_opts* in, dpr1_opts* o) {
     *o = *in;
     if (!(o->kappa_polish > 0)) o->kappa_polish = 16.0;
     if (o->nearzero < 0) o->nearzero = 10.0;
+    if (!(o->knu_thr > 0)) o->knu_thr = 32.0;
   }
 }
 
@@ -1785,6 +2070,9 @@ void dpr1_default_opts(dpr1_opts* o) {
   o->waves_per_simd = 0;
   o->events = nullptr;
   o->vwrite = 0;
+  o->remedy = 0;
+  o->knu_thr = 32.0;
+  o->knu = nullptr;
 }
 
 size_t dpr1_workspace_size(int64_t n) {
@@ -1850,6 +2138,9 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   // write; a batch runs one more, since its many small problems would queue
   // their stragglers in k_fix.
   A.main_passes = o.main_passes > 0 ? o.main_passes : (persistent_grid ? 3 : 2);
+  A.remedy = o.remedy;
+  A.knu_thr = o.knu_thr;
+  A.knu = o.knu;
 
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, A.ctr, 16);
   if (stats) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, stats, DPR1_NSTATS);
@@ -1876,7 +2167,6 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   va.cend = (int32_t)N;
   auto launch_eig = [&](unsigned grid, int g0) {
     A.g0 = g0;
-    A.pad2 = 0;
     switch (occ_of(o)) {
       case 6: hipLaunchKernelGGL(k_eig<6>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
       case 8: hipLaunchKernelGGL(k_eig<8>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
@@ -1892,6 +2182,25 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
                        dim3(nprob > 1 ? (unsigned)nprob : (unsigned)std::min<int64_t>((cnt + 255) / 256, 1024)),
                        dim3(256), 0, st, meta, (int)nprob, A.ii, A.mu, A.xs, A.lam, A.sd, csig, cinv, lambda,
                        shift_idx, mu, xnorm, A.vflag, info, (int)kb, (int)ke);
+  };
+  // K_nu of every eigenpair and, with opts.remedy, the remedies (after every
+  // eigenpair and column is final, on `stream`)
+  auto launch_knu = [&]() {
+    hipLaunchKernelGGL(k_knu, dim3(nprob > 1 ? (unsigned)nprob : (unsigned)std::min<int64_t>((N + 255) / 256, 1024)),
+                       dim3(256), 0, st, A, (int)nprob);
+    if (o.remedy) {
+      OArgs oa;
+      oa.lam_out = lambda;
+      oa.idx_out = shift_idx;
+      oa.mu_out = mu;
+      oa.xn_out = xnorm;
+      oa.V = V;
+      oa.voffs = voffs;
+      oa.ldv = ldv;
+      oa.info_out = info;
+      hipLaunchKernelGGL(k_remedy, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(N / 16, 1), 2048)),
+                         dim3(FIXT), 0, st, A, oa);
+    }
   };
   auto launch_vec = [&](int64_t cb, int64_t ce, hipStream_t s2) {
     const int64_t cg = (ce - cb + VEC_C_SINGLE - 1) / VEC_C_SINGLE;
@@ -1952,6 +2261,10 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
           hipStreamWaitEvent(st, ec, 0) != hipSuccess || (ev && hipEventRecord(ev[3], st) != hipSuccess))
         rc = DPR1_EHIP;
     }
+    if (rc == DPR1_OK) {
+      launch_knu();
+      if (hipGetLastError() != hipSuccess) rc = DPR1_EHIP;
+    }
     (void)hipEventDestroy(ea);
     (void)hipEventDestroy(eb);
     (void)hipEventDestroy(ec);
@@ -1993,6 +2306,8 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
                      A, lambda, shift_idx, mu, xnorm, V, voffs, ldv, info);
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[3], st));
+  launch_knu();
+  HIPCHECK(hipGetLastError());
   return DPR1_OK;
 }
 

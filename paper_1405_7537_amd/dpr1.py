@@ -19,16 +19,16 @@ LIB_PATH = os.path.join(HERE, "libdpr1.so")
 INFO_TEXT = {0: "ok", 1: "d is not strictly decreasing", 2: "some z_j is zero (reducible)",
              3: "non-finite input", 4: "rho is zero or not finite",
              5: "a shifted representation left the binary64 range"}
-NSTATS = 8
+NSTATS = 11
 STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "iters_sum", "continued",
-              "polish_steps_max"]
+              "polish_steps_max", "knu_gt", "remedy_r1", "remedy_r2"]
 
 
 class Opts(C.Structure):
     _fields_ = [("mode_b", C.c_int32), ("root", C.c_int32), ("polish", C.c_int32),
                 ("split", C.c_int32), ("kappa_polish", C.c_double), ("nearzero", C.c_double),
                 ("main_passes", C.c_int32), ("waves_per_simd", C.c_int32), ("events", C.c_void_p),
-                ("vwrite", C.c_int32)]
+                ("vwrite", C.c_int32), ("remedy", C.c_int32), ("knu_thr", C.c_double), ("knu", C.c_void_p)]
 
 
 class Plan(C.Structure):
@@ -87,8 +87,9 @@ def lib():
 
 
 def opts(mode_b=0, root=1, polish=1, split=0, kappa_polish=16.0, nearzero=10.0, main_passes=0,
-         events=None, waves_per_simd=0, vwrite=0) -> Opts:
-    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, main_passes, waves_per_simd, events, vwrite)
+         events=None, waves_per_simd=0, vwrite=0, remedy=0, knu_thr=32.0) -> Opts:
+    return Opts(mode_b, root, polish, split, kappa_polish, nearzero, main_passes, waves_per_simd, events, vwrite,
+                remedy, knu_thr, None)
 
 
 class HipEvents:
@@ -161,7 +162,7 @@ def workspace_bytes(n):
 
 
 def eig(d, z, rho, vectors=True, opts: Opts | None = None, check=True, want_stats=False,
-        work=None, out=None, device="cuda", ldv=None):
+        work=None, out=None, device="cuda", ldv=None, want_knu=False):
     """All eigenpairs of D + rho z z^T.  d, z: 1-D float64 (device tensors or host data).
 
     Returns a Result with lam [n], V [n, n] (V[:, k] = v_k, column-major storage with leading
@@ -190,12 +191,22 @@ def eig(d, z, rho, vectors=True, opts: Opts | None = None, check=True, want_stat
     if Vt is not None and (tuple(Vt.shape) != (n, n) or (n > 1 and Vt.stride(1) != 1)):
         raise ValueError("V storage must be an [n, n] view with unit column stride")
     ld = max(n, 1) if Vt is None or n <= 1 else Vt.stride(0)
+    knu = None
+    if want_knu:
+        knu = torch.empty(n, dtype=torch.float64, device=dev)
+        o = Opts()
+        if opts is not None:
+            C.memmove(C.byref(o), C.byref(opts), C.sizeof(Opts))
+        else:
+            lib().dpr1_default_opts(C.byref(o))
+        o.knu = knu.data_ptr()
+        opts = o
     rc = lib().dpr1_eig(_ptr(d), _ptr(z), float(rho), n, _ptr(lam), _ptr(Vt), ld, _ptr(idx), _ptr(mu),
                         _ptr(xn), _ptr(info), _ptr(stats), C.byref(opts) if opts is not None else None,
                         _ptr(work), wb, _stream())
     _rc(rc, "dpr1_eig")
     r = Result(lam=lam, V=Vt.t() if Vt is not None else None, shift_idx=idx, mu=mu, xnorm=xn,
-               info=info, stats=stats, work=work)
+               info=info, stats=stats, work=work, knu=knu)
     if check:
         code = int(info.item())
         if code != 0:
