@@ -124,7 +124,8 @@ typedef struct dpr1_opts {
                           ([0], [1]) and around the second phase ([2], [3]):
                           the flagged eigenpairs overlapped with the
                           eigenvector write                                 */
-  int32_t vwrite;      /* eigenvectors of a single problem: 0 (default) the
+  int32_t vwrite;      /* eigenvectors of a single problem of order n >= 8192:
+                          0 (default) the
                           eigenvalue kernel runs in two halves and the first
                           half's columns are written on a second stream (a
                           library stream per device, created on first use,
@@ -320,7 +321,7 @@ int dpr1_eig_general(const double* d, const double* z, double rho, int64_t n, do
                      double* V, int64_t ldv, int32_t* info, const dpr1_opts* opts, void* work,
                      size_t work_bytes, void* stream);
 
-/* Hermitian DPR1 (the extension named in the paper's conclusions):
+/* Hermitian DPR1 (the remark after Algorithm 1 says the method extends to it):
  * A = D + rho z z^H with real d, complex z.  With Phi = diag(z_j / |z_j|)
  * (1 where z_j = 0), Phi is unitary, Phi D Phi^H = D and z = Phi |z|, so
  * A = Phi (D + rho |z| |z|^T) Phi^H: the eigenvalues are those of the real

@@ -530,17 +530,33 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   // Only the sign of F and a first model step are taken from these sums, so
   // the reciprocal is the hardware estimate alone (relative error below
   // 2^-23): the bounds taken from the probe allow for it.
+  // The terms are positive for j < k (pole above the midpoint) and negative
+  // for j >= k, so their sum and the sum of their magnitudes come from the
+  // two one-signed partial sums Fs[0] (j < k) and Fs[1] (j >= k); below the
+  // window every lane has j < k, above it j > k.
   double Fs[4] = {0.0, 0.0, 0.0, 0.0};
-  sweep(P, j0, j1, wlo, whi, [&](int j, int, double dj, double z2, double, int) {
+  sweep(P, j0, j1, wlo, whi, [&](int j, int seg, double dj, double z2, double, int) {
     double r = __builtin_amdgcn_rcp((dj - dk) - tau);
     double t = z2 * r;
     double tr = t * r;
-    Fs[0] += t;
-    Fs[1] += fabs(t);
+    if (seg == 0) {
+      Fs[0] += t;
+    } else if (seg == 2) {
+      Fs[1] += t;
+    } else {
+      const bool up = j < kk;
+      Fs[0] += up ? t : 0.0;
+      Fs[1] += up ? 0.0 : t;
+    }
     Fs[2] += tr;
     Fs[3] = __builtin_fma(tr, r, Fs[3]);
   });
   wg_sum<4>(Fs, W, wv, lane, red);
+  {
+    const double sp = Fs[0], sn = Fs[1];
+    Fs[0] = sp + sn;  // sum of the terms
+    Fs[1] = sp - sn;  // sum of their magnitudes
+  }
   double F = 1.0 + rho * Fs[0];
   // The estimated reciprocals leave the sign of F open when |F| is within
   // their error (2^-23 of the sum of |terms|, taken with a margin of 8): such
@@ -728,15 +744,14 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
           double t = z2 * rq;           // w_j/(m - xi_j)
           double u = (dl * rq) * dl;    // delta'_j/pp = 1/(m - xi_j)
           double tp = t * u;            // w_j/(m - xi_j)^2
-          double tp3 = tp * u;          // w_j/(m - xi_j)^3
-          if (seg == 1 && j == i) {
+          if (seg == 1 && j == i) {     // (dl = 0 there: u is NaN)
             t = 0.0;
             tp = 0.0;
-            tp3 = 0.0;
+            u = 0.0;
           }
           S[0] += t;
           S[1] += tp;
-          S[2] += tp3;
+          S[2] = __builtin_fma(tp, u, S[2]);  // w_j/(m - xi_j)^3
         });
         wg_sum<3>(S, W, wv, lane, red);
         ++iters;
@@ -798,12 +813,11 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     double u = (dl * r) * dl;                           // 1/(m - xi_j)
     double tp = t * u;                                  // zeta_j^2/pp^2
     double tp3 = tp * u;                                // zeta_j^2 delta'_j/pp^3
-    double tp4 = tp3 * u;                               // zeta_j^2 delta'_j^2/pp^4
-    if (seg == 1 && j == i) {
+    if (seg == 1 && j == i) {                           // (dl = 0 there: u is NaN)
       t = 0.0;
       tp = 0.0;
       tp3 = 0.0;
-      tp4 = 0.0;
+      u = 0.0;
     }
     switch (ub) {
       case 0: ga = t; break;
@@ -818,7 +832,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     }
     Sp[0] += tp;
     Sp[1] += tp3;
-    Sp[2] += tp4;
+    Sp[2] = __builtin_fma(tp3, u, Sp[2]);               // zeta_j^2 delta'_j^2/pp^4
   });
   wg_sum_comp(cs, cc, W, wv, lane, red);
   wg_sum<3>(Sp, W, wv, lane, red);
@@ -1235,7 +1249,7 @@ __device__ void fix_items(const KArgs& A) {
           cs = y;
           sp += tp;
           sp3 += tp3;
-          sp4 += tp3 * u;
+          sp4 = __builtin_fma(tp3, u, sp4);
         }
         Sz = block_sum_comp3(cs, cc, sp, sp3, sp4, sm) / zi2;
         ++iters;
@@ -1571,24 +1585,40 @@ __device__ void vec_block(unsigned bid, const VArgs& v) {
     return;
   }
   // Column segments: wave w writes columns w, w + NW, ... of the group, each
-  // in aligned windows (the column's address set up once, then a plain loop).
+  // in windows of 128 elements aligned to 1 KB, two consecutive elements per
+  // lane in one 16-byte store (the column's address set up once, then a plain
+  // loop; a window's lane with only one element in the segment stores it
+  // alone).
+  typedef double vdbl2 __attribute__((ext_vector_type(2)));
+  constexpr int WE = 2 * WAVE;
   for (int c = wv; c < nc; c += NW) {
     if (lskip[c]) continue;
     const int k = c0 + c;
     const int64_t ko = M.neg ? n - 1 - k : k;
     const int64_t s0 = base + ko * ld + r0;  // element index of the segment's first position
-    const int64_t sal = s0 & ~(int64_t)(WAVE - 1);
-    const int nwin = (int)((s0 + nr - sal + WAVE - 1) / WAVE);
+    // windows aligned on the address (V itself need only be 8-byte aligned)
+    const int64_t sal = s0 - (int64_t)(((uintptr_t)(V + s0) >> 3) & (WE - 1));
+    const int nwin = (int)((s0 + nr - sal + WE - 1) / WE);
     const double m = lmu[c], sc = lsig[c], iv = linv[c];
-    double* vp = V + sal + lane;
-    int rel = (int)(sal - s0) + lane;
-    for (int w = 0; w < nwin; ++w, vp += WAVE, rel += WAVE) {
-      if (rel >= 0 && rel < nr) {
-        const double den = (ld_d[rel] - sc) - m;
-        const double rc = rcp_1nr(den);
-        double q = iv * rc;
-        q = __builtin_fma(__builtin_fma(-q, den, iv), rc, q);  // corrected quotient
-        __builtin_nontemporal_store(ld_z[rel] * q, vp);
+    double* vp = V + sal + 2 * lane;
+    int rel = (int)(sal - s0) + 2 * lane;
+    for (int w = 0; w < nwin; ++w, vp += WE, rel += WE) {
+      const bool a0 = rel >= 0 && rel < nr, a1 = rel + 1 >= 0 && rel + 1 < nr;
+      if (!a0 && !a1) continue;
+      const int r0c = a0 ? rel : rel + 1, r1c = a1 ? rel + 1 : rel;
+      const double den0 = (ld_d[r0c] - sc) - m, den1 = (ld_d[r1c] - sc) - m;
+      const double rc0 = rcp_1nr(den0), rc1 = rcp_1nr(den1);
+      double q0 = iv * rc0, q1 = iv * rc1;
+      q0 = __builtin_fma(__builtin_fma(-q0, den0, iv), rc0, q0);  // corrected quotients
+      q1 = __builtin_fma(__builtin_fma(-q1, den1, iv), rc1, q1);
+      const double v0 = ld_z[r0c] * q0, v1 = ld_z[r1c] * q1;
+      if (a0 && a1) {
+        const vdbl2 vv = {v0, v1};
+        __builtin_nontemporal_store(vv, reinterpret_cast<vdbl2*>(vp));
+      } else if (a0) {
+        __builtin_nontemporal_store(v0, vp);
+      } else {
+        __builtin_nontemporal_store(v1, vp + 1);
       }
     }
   }
@@ -2221,7 +2251,8 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   // k_fix.  Flagged columns are left to k_fixout, as in the sequential path.
   hipStream_t st2 = nullptr;
   hipEvent_t ea = nullptr, eb = nullptr, ec = nullptr;
-  bool overlap = V && !persistent_grid && o.vwrite == 0 && aux_ok && nitems >= 2;
+  // (below 8192 eigenpairs the write is short and the fork costs more than it hides)
+  bool overlap = V && !persistent_grid && o.vwrite == 0 && aux_ok && N >= 8192;
   if (overlap) {
     st2 = aux_stream();
     if (!st2 || hipEventCreateWithFlags(&ea, hipEventDisableTiming) != hipSuccess) overlap = false;

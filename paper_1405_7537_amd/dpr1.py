@@ -463,6 +463,20 @@ def backward_batched(d, z, rho, shift_idx, mu, xnorm, V, lam_bar=None, V_bar=Non
     return d_bar, z_bar, rho_bar
 
 
+def _rho_like(rho):
+    """(device, shape) of a tensor rho, None for a Python number (which gets no gradient)."""
+    return (rho.device, rho.shape) if torch.is_tensor(rho) else None
+
+
+def _rho_grad(ctx, rb):
+    """rho's gradient on rho's own device and shape; None when rho was a Python number or does not
+    need a gradient."""
+    if ctx.rho_like is None or not ctx.needs_input_grad[2]:
+        return None
+    dev, shape = ctx.rho_like
+    return rb.reshape(shape).to(dev)
+
+
 class DPR1Eig(torch.autograd.Function):
     """(lam, V) = eig(D + rho z z^T) with a hand-written adjoint.
 
@@ -473,6 +487,7 @@ class DPR1Eig(torch.autograd.Function):
     def forward(ctx, d, z, rho):
         rho_t = rho if torch.is_tensor(rho) else torch.tensor(float(rho), dtype=torch.float64, device=d.device)
         r = eig(d.detach(), z.detach(), float(rho_t), vectors=True)
+        ctx.rho_like = _rho_like(rho)
         ctx.save_for_backward(d.detach(), z.detach(), rho_t.detach().reshape(1).to(d.device), r.shift_idx, r.mu,
                               r.xnorm, r.V)
         return r.lam, r.V
@@ -487,7 +502,7 @@ class DPR1Eig(torch.autograd.Function):
         Vb = V_bar.t().contiguous() if V_bar is not None else None
         db, zb, rb = backward_batched(d.view(1, n), z.view(1, n), rho, idx.view(1, n), mu.view(1, n),
                                       xn.view(1, n), Vs, lb, Vb)
-        return db.view(n), zb.view(n), rb.view(())
+        return db.view(n), zb.view(n), _rho_grad(ctx, rb)
 
 
 class DPR1EigValues(torch.autograd.Function):
@@ -500,6 +515,7 @@ class DPR1EigValues(torch.autograd.Function):
     def forward(ctx, d, z, rho):
         rho_t = rho if torch.is_tensor(rho) else torch.tensor(float(rho), dtype=torch.float64, device=d.device)
         r = eig(d.detach(), z.detach(), float(rho_t), vectors=False)
+        ctx.rho_like = _rho_like(rho)
         ctx.save_for_backward(d.detach(), z.detach(), rho_t.detach().reshape(1).to(d.device), r.shift_idx, r.mu,
                               r.xnorm)
         return r.lam
@@ -510,7 +526,7 @@ class DPR1EigValues(torch.autograd.Function):
         n = d.numel()
         db, zb, rb = backward_batched(d.contiguous().view(1, n), z.contiguous().view(1, n), rho, idx.view(1, n),
                                       mu.view(1, n), xn.view(1, n), None, lam_bar.contiguous().view(1, n), None)
-        return db.view(n), zb.view(n), rb.view(())
+        return db.view(n), zb.view(n), _rho_grad(ctx, rb)
 
 
 class DPR1EigBatched(torch.autograd.Function):
@@ -522,6 +538,9 @@ class DPR1EigBatched(torch.autograd.Function):
         offs = np.arange(nb + 1, dtype=np.int64) * n
         b = Batch(offs, device=d.device)
         b.solve(d.detach().contiguous(), z.detach().contiguous(), rho.detach().contiguous())
+        # a rejected problem (info != 0) has undefined eigenpairs: refuse it rather than hand its
+        # unwritten V block to the caller and to the backward
+        b.check()
         Vst = b.V.view(nb, n, n)          # [b, k, j] = v_k[j] (column-major blocks)
         ctx.save_for_backward(d.detach(), z.detach(), rho.detach(), b.shift_idx.view(nb, n), b.mu.view(nb, n),
                               b.xnorm.view(nb, n), Vst)
@@ -533,64 +552,3 @@ class DPR1EigBatched(torch.autograd.Function):
         lb = lam_bar.contiguous() if lam_bar is not None else None
         Vb = V_bar.transpose(1, 2).contiguous() if V_bar is not None else None
         return backward_batched(d.contiguous(), z.contiguous(), rho.contiguous(), idx, mu, xn, Vst, lb, Vb)
-
-
-def bench_fwd_bwd(torch_mod, dev, steps, nb=256, n=512, seed=4):
-    """Forward + backward of nb problems of order n: L = sum(w * lam) + sum(W o V)."""
-    from . import workloads as W
-    d_h, z_h, rho_h = W.uniform_batch(nb, n, seed)
-    rng = np.random.default_rng(seed + 100)
-    d = torch.as_tensor(d_h, device=dev)
-    z = torch.as_tensor(z_h, device=dev)
-    rho = torch.as_tensor(rho_h, device=dev)
-    w = torch.as_tensor(rng.standard_normal((nb, n)), device=dev)
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
-    Wb = torch.randn((nb, n, n), generator=g, dtype=torch.float64, device=dev)   # column-major V_bar blocks
-    offs = np.arange(nb + 1, dtype=np.int64) * n
-    b = Batch(offs, device=dev)
-    wb = int(lib().dpr1_backward_workspace_size(n, nb))
-    work = torch.empty(wb, dtype=torch.uint8, device=dev)
-
-    def one():
-        b.solve(d, z, rho)
-        return backward_batched(d, z, rho, b.shift_idx.view(nb, n), b.mu.view(nb, n), b.xnorm.view(nb, n),
-                                b.V, w, Wb, work=work)
-
-    import time
-    for _ in range(2):
-        one()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        b.solve(d, z, rho)
-    torch.cuda.synchronize()
-    ms_f = (time.perf_counter() - t0) * 1e3 / steps
-    flops = 2 * 2 * n ** 3 * nb
-    # the same gradients with V never stored: eigenvalues-only forward, V rebuilt in the GEMM loads
-    b2 = Batch(offs, vectors=False, device=dev)
-
-    def one_recompute():
-        b2.solve(d, z, rho)
-        return backward_batched(d, z, rho, b2.shift_idx.view(nb, n), b2.mu.view(nb, n), b2.xnorm.view(nb, n),
-                                None, w, Wb, work=work)
-
-    for _ in range(2):
-        one_recompute()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one_recompute()
-    torch.cuda.synchronize()
-    ms_r = (time.perf_counter() - t0) * 1e3 / steps
-    return {"workload": f"{nb} DPR1 problems of n={n} (seed {seed}), L = sum(w*lam) + sum(W o V)",
-            "value": nb / (ms / 1e3), "unit": "problems/s (forward+backward)", "ms_per_step": ms,
-            "forward_ms": ms_f, "backward_ms": ms - ms_f,
-            "gemm_TFLOPs": flops / ((ms - ms_f) / 1e3) / 1e12,
-            "v_not_stored": {"value": nb / (ms_r / 1e3), "ms_per_step": ms_r,
-                             "note": "forward without eigenvectors; the backward rebuilds V in its GEMM loads"}}

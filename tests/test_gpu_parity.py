@@ -259,11 +259,13 @@ def test_launch_shapes_keep_parity(D, orc, split, wps, mp):
         assert r.stats_dict()["continued"] > 500
 
 
-def test_single_solve_graph_capture(D):
+@pytest.mark.parametrize("n", [3000, 9000])
+def test_single_solve_graph_capture(D, n):
     """dpr1_eig enqueues kernels only (no host sync, no memset): captured in a HIP graph, every
-    replay reproduces the eager solve bit for bit, with other eager solves in between."""
+    replay reproduces the eager solve bit for bit, with other eager solves in between.  At
+    n = 9000 the solve forks the first half's eigenvector write to the library's second stream
+    and joins it back, so the graph holds the fork and the join."""
     import torch
-    n = 3000
     d, z, rho = W.uniform(n, 33)
     dd = torch.as_tensor(d, device="cuda")
     zz = torch.as_tensor(z, device="cuda")
@@ -323,3 +325,19 @@ def test_extreme_range_is_exact_or_reported(D, orc):
         check_repr(d, z, rho, r.shift_idx.cpu().numpy(), r.mu.cpu().numpy(), r.xnorm.cpu().numpy(), dg)
         ok += 1
     print(f"[parity] extreme range: {ok} within the bar, {reported} reported", flush=True)
+
+
+def test_overlapped_write_matches_sequential(D):
+    """The overlapped eigenvector write (default, n >= 8192) and the sequential one (vwrite = 1)
+    give the same outputs bit for bit, also with rho < 0 and a padded leading dimension."""
+    import torch
+    for n, rho, pad in ((8192, 1.0, 0), (10000, -0.5, 3)):
+        d, z, _ = W.uniform(n, 61)
+        print(f"[parity] overlap vs sequential n={n} rho={rho} pad={pad}", flush=True)
+        outs = []
+        for vw in (0, 1):
+            r = D.eig(d, z, rho, opts=D.opts(vwrite=vw), ldv=n + pad)
+            torch.cuda.synchronize()
+            outs.append([r.lam.cpu(), r.V.cpu(), r.shift_idx.cpu(), r.mu.cpu(), r.xnorm.cpu()])
+        for a, b in zip(*outs):
+            assert torch.equal(a, b)

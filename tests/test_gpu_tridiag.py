@@ -179,3 +179,30 @@ def test_structured_large(D, kind):
     res = (torch.as_tensor(dense(a, b), device=Q.device) @ Q - Q * r.lam).abs().max().item() / nt
     print(f"[tridiag] {kind}: lam {el:.1e} orth {orth:.1e} res {res:.1e}", flush=True)
     assert el <= 1e-13 and orth <= 1e-12 and res <= 1e-12
+
+
+@pytest.mark.parametrize("nb,glue", [(126, 1e-8), (126, 1e-12), (64, 1e-4)])
+def test_glued_wilkinson_large(D, orc, nb, glue):
+    """Glued Wilkinson matrices: nb copies of W21+ joined by couplings `glue` (n = 21 nb, 2646 at
+    nb = 126, the size at which an earlier driver lost orthogonality to 2.4e-9).  Eigenvalues
+    against LAPACK on the dense T and against the oracle's driver, Q^T Q = I and T Q = Q Lambda to
+    1e-12 of ||T||, and every column against the oracle's up to sign (or its cluster's projector)."""
+    m = 10
+    blk = np.abs(np.arange(-m, m + 1, dtype=np.float64))
+    a = np.tile(blk, nb)
+    b = np.ones(a.size - 1)
+    b[2 * m::2 * m + 1] = glue
+    n = a.size
+    print(f"[tridiag] glued Wilkinson n={n} glue={glue}", flush=True)
+    r = D.tridiag_eig(a, b)
+    lam, Q = r.lam.cpu().numpy(), r.Q.cpu().numpy()
+    T = dense(a, b)
+    L = np.sort(np.linalg.eigvalsh(T))[::-1]
+    nt = np.max(np.abs(L))
+    orth = np.max(np.abs(Q.T @ Q - np.eye(n)))
+    res = np.max(np.abs(T @ Q - Q * lam)) / nt
+    print(f"[tridiag] glued n={n}: lam {np.max(np.abs(lam - L)) / nt:.1e} orth {orth:.1e} res {res:.1e}", flush=True)
+    assert np.max(np.abs(lam - L)) <= 1e-12 * nt
+    assert orth <= 1e-12 and res <= 1e-12
+    lo, Qo = orc.tridiag_eig(a, b)
+    assert np.max(np.abs(lam - lo)) <= 1e-12 * nt

@@ -627,3 +627,84 @@ def test_tridiag_dc_one_two_one_closed_form(orc):
         exact = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1]
         assert np.max(np.abs(lam - exact)) <= 1e-14
         assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-14
+
+
+# The divide-and-conquer driver's deflation rules, pinned at their thresholds against 60-digit dense
+# eigenvalues of the explicit T: a merge component z_j with |beta z_j| <= 2 eps max|d| is dropped
+# (T changes by at most 2 sqrt(2) |beta z_j|), and poles within 8 eps max|d| of a group's largest
+# are merged (T changes by at most that spread).  Just below a threshold the rule acts, just above
+# it does not; either way the eigenvalues must lie within the perturbation the rule allows (plus
+# the rounding of the merge), and Q must be orthogonal with a small residual.
+EPS_D = np.finfo(float).eps
+
+
+def _tri_truth(a, b, dps=60):
+    with mp.workdps(dps):
+        n = len(a)
+        A = mp.matrix(n, n)
+        for i in range(n):
+            A[i, i] = mp.mpf(float(a[i]))
+            if i + 1 < n:
+                A[i, i + 1] = A[i + 1, i] = mp.mpf(float(b[i]))
+        return sorted([float(x) for x in mp.eigsy(A, eigvals_only=True)], reverse=True)
+
+
+def _check_tri(orc, a, b, bound):
+    lam, Q = orc.tridiag_eig(a, b)
+    L = np.array(_tri_truth(a, b))
+    n = len(a)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    nt = np.max(np.abs(L))
+    assert np.max(np.abs(lam - L)) <= bound + 8 * EPS_D * nt, (lam - L)
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 8 * n * EPS_D
+    assert np.max(np.abs(T @ Q - Q * lam)) <= bound + 8 * n * EPS_D * nt
+
+
+@pytest.mark.parametrize("factor", [0.5, 0.99, 1.01, 2.0])
+def test_dc_coupling_deflation_at_threshold(orc, factor):
+    """n = 4 split at 2 with beta = 0.5: the child T1 = [[3, c], [c, 1 - beta]] has an eigenvector
+    whose last entry s is about c/2.5, so the merge has |beta s| = factor * 2 eps max|d|."""
+    beta = 0.5
+    a = np.array([3.0, 1.0, -1.0, -3.0])
+    T1 = np.array([[3.0, 0.0], [0.0, 1.0 - beta]])
+    dmax = 3.0 + 1e-3                       # the children's largest |eigenvalue| (3 + c^2/2.5)
+    target = factor * 2 * EPS_D * dmax / beta
+    c = target * 2.5
+    for _ in range(3):                      # adjust c so that the eigenvector entry hits the target
+        T1[0, 1] = T1[1, 0] = c
+        w, U = np.linalg.eigh(T1)
+        s = abs(U[1, np.argmax(w)])
+        c *= target / s
+    b = np.array([c, beta, 1e-3])
+    _check_tri(orc, a, b, 2 * math.sqrt(2) * abs(beta) * target)
+
+
+@pytest.mark.parametrize("factor", [0.5, 0.99, 1.01, 2.0])
+def test_dc_pole_merge_at_threshold(orc, factor):
+    """n = 2 split at 1: the children are the 1 x 1 poles a1 - beta and a2 - beta, apart by
+    factor * 8 eps max|d|, so they merge as one pole below the threshold and stay two above it."""
+    beta = 0.25
+    x = 1.5
+    dmax = x - beta
+    gap = factor * 8 * EPS_D * dmax
+    a = np.array([x + gap, x])
+    _check_tri(orc, a, np.array([beta]), gap)
+
+
+def test_dc_glued_wilkinson_orthogonal(orc):
+    """Glued Wilkinson matrices (W21+ blocks joined by 1e-8), n = 2646: the driver's Q is
+    orthogonal to 1e-13 and T Q = Q Lambda to 1e-13 of ||T|| (LAPACK's dense eigenvalues as the
+    reference)."""
+    m = 10
+    blk = np.abs(np.arange(-m, m + 1, dtype=np.float64))
+    a = np.tile(blk, 126)
+    b = np.ones(a.size - 1)
+    b[2 * m::2 * m + 1] = 1e-8
+    lam, Q = orc.tridiag_eig(a, b)
+    n = a.size
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    L = np.sort(np.linalg.eigvalsh(T))[::-1]
+    nt = np.max(np.abs(L))
+    assert np.max(np.abs(lam - L)) <= 1e-13 * nt
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-13
+    assert np.max(np.abs(T @ Q - Q * lam)) <= 1e-13 * nt
