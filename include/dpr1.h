@@ -125,13 +125,16 @@ typedef struct dpr1_opts {
                           the flagged eigenpairs overlapped with the
                           eigenvector write                                 */
   int32_t vwrite;      /* eigenvectors of a single problem of order n >= 8192:
-                          0 (default) the
-                          eigenvalue kernel runs in two halves and the first
-                          half's columns are written on a second stream (a
-                          library stream per device, created on first use,
-                          default priority) while the second half is solved;
-                          1 every column after the eigenvalue kernel, on
-                          `stream` only.  dpr1_eig_noalloc always uses 1.    */
+                          0 (default) = 2; K = 2 .. 8: the eigenvalue
+                          kernel runs in K launches over consecutive chunks
+                          of the eigenvalues, and each chunk's columns but
+                          the last are written on a second stream (a library
+                          stream per device, created on first use, default
+                          priority) while the next chunk is solved; 1 every
+                          column after the eigenvalue kernel, on `stream`
+                          only.  Results are the same bit for bit.  Other
+                          values are rejected.  dpr1_eig_noalloc always
+                          uses 1.                                          */
   int32_t remedy;      /* Sec. 2, Algorithm 1's last branch: 1 = where K_nu
                           of eq. (K0) exceeds knu_thr, recompute the
                           eigenpair by remedy (R1) -- the other neighbouring

@@ -731,9 +731,10 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     // and curvature of the sum term at nu; the root of the model built from
     // them (the nearest pole exact, the rest one fitted pole) is the next
     // iterate.  The last pass of the budget is the accurate one below.
+    // The step from the probe costs no pass and is always taken.
     const int budget = max(A.main_passes, 1);
     int passes = 0;
-    while (passes < budget - 1 && wave_any(!done)) {
+    while (wave_any(!done) && (passes < budget - 1 || wave_any(pre))) {
       double m = nu;
       double S[3] = {0.0, 0.0, 0.0};
       if (wave_any(!done && !pre)) {
@@ -1472,6 +1473,8 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
 constexpr int VEC_T = 256;
 constexpr int VEC_ROWS = 2048;
 constexpr int VEC_C_SINGLE = 32, VEC_C_BATCH = 64;
+// chunks of the overlapped single-problem solve (opts.vwrite)
+constexpr int VEC_CHUNKS_DEFAULT = 2, VEC_CHUNKS_MAX = 8;
 
 // Arguments of the eigenvector writer.  Columns flagged in vflag belong to
 // eigenpairs that k_fix finishes; they are skipped here and written by
@@ -1490,6 +1493,7 @@ struct VArgs {
   const int64_t* voffs;
   int64_t ldv;
   int32_t cbase, cend;  // single problem: columns cbase .. cend-1
+  int32_t prio;         // k_vec: raise the waves' issue priority
 };
 
 template <int CB>
@@ -1628,6 +1632,11 @@ __device__ void vec_block(unsigned bid, const VArgs& v) {
 // The eigenvector writer alone (single problem, a range of columns).
 template <int CB>
 __global__ void __launch_bounds__(VEC_T) k_vec(VArgs v) {
+  // beside the eigenvalue kernel of the next chunk its waves issue first, so
+  // that the stores keep flowing while the sweeps take the remaining issue
+  // slots; beside k_fix (the last chunk) they do not, since k_fix is latency-
+  // bound and would starve
+  if (v.prio) __builtin_amdgcn_s_setprio(3);
   vec_block<CB>(blockIdx.x, v);
 }
 
@@ -2195,9 +2204,10 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   va.ldv = ldv;
   va.cbase = 0;
   va.cend = (int32_t)N;
-  auto launch_eig = [&](unsigned grid, int g0) {
+  va.prio = 0;
+  auto launch_eig = [&](unsigned grid, int g0, int occ) {
     A.g0 = g0;
-    switch (occ_of(o)) {
+    switch (occ) {
       case 6: hipLaunchKernelGGL(k_eig<6>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
       case 8: hipLaunchKernelGGL(k_eig<8>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
       default: hipLaunchKernelGGL(k_eig<4>, dim3(grid), dim3(64 * W), red_bytes(W), st, A); break;
@@ -2232,7 +2242,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
                          dim3(FIXT), 0, st, A, oa);
     }
   };
-  auto launch_vec = [&](int64_t cb, int64_t ce, hipStream_t s2) {
+  auto launch_vec = [&](int64_t cb, int64_t ce, hipStream_t s2, bool prio) {
     const int64_t cg = (ce - cb + VEC_C_SINGLE - 1) / VEC_C_SINGLE;
     const int64_t rt = (N + VEC_ROWS - 1) / VEC_ROWS;
     VArgs vb = va;
@@ -2240,73 +2250,64 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
     vb.ncolgroups = cg;
     vb.cbase = (int32_t)cb;
     vb.cend = (int32_t)ce;
+    vb.prio = prio ? 1 : 0;
     hipLaunchKernelGGL((k_vec<VEC_C_SINGLE>), dim3((unsigned)(cg * rt)), dim3(VEC_T), 0, s2, vb);
   };
 
-  // A single problem with eigenvectors: the eigenvalue kernel runs in two
-  // launches over the two halves of its groups of 64 eigenvalues, and the
-  // eigenvector writer of the first half runs on a second stream while the
-  // second half is solved, so that the HBM-bound stores overlap the
-  // ALU-bound sweeps; the second half's columns are written after it, beside
-  // k_fix.  Flagged columns are left to k_fixout, as in the sequential path.
-  hipStream_t st2 = nullptr;
-  hipEvent_t ea = nullptr, eb = nullptr, ec = nullptr;
+  // A single problem with eigenvectors: the eigenvalue kernel runs in K
+  // launches over consecutive chunks of its groups of 64 eigenvalues, and the
+  // columns of chunk c are written on a second stream while chunk c + 1 is
+  // solved, so that the HBM-bound stores overlap the ALU-bound sweeps; the
+  // last chunk's columns are written beside k_fix.  Flagged columns are left
+  // to k_fixout, as in the sequential path.
   // (below 8192 eigenpairs the write is short and the fork costs more than it hides)
-  bool overlap = V && !persistent_grid && o.vwrite == 0 && aux_ok && N >= 8192;
+  const int nchunks = o.vwrite == 0 ? VEC_CHUNKS_DEFAULT : o.vwrite;
+  bool overlap = V && !persistent_grid && nchunks >= 2 && aux_ok && N >= 8192 && nitems >= nchunks;
+  hipStream_t st2 = overlap ? aux_stream() : nullptr;
+  if (overlap && !st2) overlap = false;
   if (overlap) {
-    st2 = aux_stream();
-    if (!st2 || hipEventCreateWithFlags(&ea, hipEventDisableTiming) != hipSuccess) overlap = false;
-    else if (hipEventCreateWithFlags(&eb, hipEventDisableTiming) != hipSuccess) overlap = false;
-    else if (hipEventCreateWithFlags(&ec, hipEventDisableTiming) != hipSuccess) overlap = false;
-  }
-  if (overlap) {
-    const int64_t g1 = nitems / 2;
-    const int64_t kmid = g1 * WAVE;
-    int rc = DPR1_OK;
-    if (ev && hipEventRecord(ev[0], st) != hipSuccess) rc = DPR1_EHIP;
-    if (rc == DPR1_OK) {
-      launch_eig((unsigned)g1, 0);
-      launch_out(0, kmid);
-      if (hipGetLastError() != hipSuccess || hipEventRecord(ea, st) != hipSuccess ||
-          hipStreamWaitEvent(st2, ea, 0) != hipSuccess)
+    hipEvent_t evs[VEC_CHUNKS_MAX + 1];
+    int nev = 0, rc = DPR1_OK;
+    for (; nev <= nchunks; ++nev)
+      if (hipEventCreateWithFlags(&evs[nev], hipEventDisableTiming) != hipSuccess) {
         rc = DPR1_EHIP;
-    }
-    if (rc == DPR1_OK) {
-      launch_vec(0, kmid, st2);
-      launch_eig((unsigned)(nitems - g1), (int)g1);
-      if (hipGetLastError() != hipSuccess || (ev && hipEventRecord(ev[1], st) != hipSuccess)) rc = DPR1_EHIP;
-    }
-    if (rc == DPR1_OK) {
-      launch_out(kmid, N);
-      if (hipGetLastError() != hipSuccess || (ev && hipEventRecord(ev[2], st) != hipSuccess) ||
-          hipEventRecord(eb, st) != hipSuccess || hipStreamWaitEvent(st2, eb, 0) != hipSuccess)
+        break;
+      }
+    if (rc == DPR1_OK && ev && hipEventRecord(ev[0], st) != hipSuccess) rc = DPR1_EHIP;
+    for (int c = 0; c < nchunks && rc == DPR1_OK; ++c) {
+      const int64_t ga = nitems * c / nchunks, gb = nitems * (c + 1) / nchunks;
+      const int64_t ka = ga * WAVE, kb = std::min<int64_t>(gb * WAVE, N);
+      // the chunks solved beside the writer take at least the 6-wave register
+      // budget, so that writer waves fit next to a 16-wave block
+      launch_eig((unsigned)(gb - ga), (int)ga, c == 0 ? occ_of(o) : std::max(occ_of(o), 6));
+      if (c == nchunks - 1 && ev && hipEventRecord(ev[1], st) != hipSuccess) rc = DPR1_EHIP;
+      launch_out(ka, kb);
+      if (hipGetLastError() != hipSuccess || hipEventRecord(evs[c], st) != hipSuccess ||
+          hipStreamWaitEvent(st2, evs[c], 0) != hipSuccess)
         rc = DPR1_EHIP;
+      if (rc == DPR1_OK) launch_vec(ka, kb, st2, c < nchunks - 1);
     }
+    if (rc == DPR1_OK && ev && hipEventRecord(ev[2], st) != hipSuccess) rc = DPR1_EHIP;
     if (rc == DPR1_OK) {
-      launch_vec(kmid, N, st2);
       unsigned fgrid = (unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048);
       hipLaunchKernelGGL(k_fix, dim3(fgrid), dim3(FIXT), 0, st, A);
       hipLaunchKernelGGL(k_fixout, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(N, 1), 2048)), dim3(256), 0,
                          st, A, lambda, shift_idx, mu, xnorm, V, voffs, ldv, info);
-      if (hipGetLastError() != hipSuccess || hipEventRecord(ec, st2) != hipSuccess ||
-          hipStreamWaitEvent(st, ec, 0) != hipSuccess || (ev && hipEventRecord(ev[3], st) != hipSuccess))
+      if (hipGetLastError() != hipSuccess || hipEventRecord(evs[nchunks], st2) != hipSuccess ||
+          hipStreamWaitEvent(st, evs[nchunks], 0) != hipSuccess || (ev && hipEventRecord(ev[3], st) != hipSuccess))
         rc = DPR1_EHIP;
     }
     if (rc == DPR1_OK) {
       launch_knu();
       if (hipGetLastError() != hipSuccess) rc = DPR1_EHIP;
     }
-    (void)hipEventDestroy(ea);
-    (void)hipEventDestroy(eb);
-    (void)hipEventDestroy(ec);
+    for (int e = 0; e < nev; ++e) (void)hipEventDestroy(evs[e]);
     return rc;
   }
-  if (ea) (void)hipEventDestroy(ea);
-  if (eb) (void)hipEventDestroy(eb);
 
   unsigned grid = persistent_grid ? (unsigned)persistent_grid : (unsigned)nitems;
   if (ev) HIPCHECK(hipEventRecord(ev[0], st));
-  launch_eig(grid, 0);
+  launch_eig(grid, 0, occ_of(o));
   HIPCHECK(hipGetLastError());
   if (ev) HIPCHECK(hipEventRecord(ev[1], st));
   launch_out(0, N);
@@ -2357,7 +2358,7 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
   if (work_bytes < L.total) return -15;
   dpr1_opts o;
   fill_opts(opts, &o);
-  if (!occ_valid(o.waves_per_simd)) return -13;
+  if (!occ_valid(o.waves_per_simd) || o.vwrite < 0 || o.vwrite > VEC_CHUNKS_MAX) return -13;
   int64_t nblocks = (n + WAVE - 1) / WAVE;
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
   return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
@@ -2381,7 +2382,7 @@ int dpr1_eig_noalloc(const double* d, const double* z, double rho, int64_t n, do
   if (!info) return -11;
   dpr1_opts o;
   fill_opts(opts, &o);
-  if (!occ_valid(o.waves_per_simd)) return -13;
+  if (!occ_valid(o.waves_per_simd) || o.vwrite < 0 || o.vwrite > VEC_CHUNKS_MAX) return -13;
   void* work = scratch_on_current_device();
   if (!work) return DPR1_EHIP;
   const Layout L = layout(1, n, 0);

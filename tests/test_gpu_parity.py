@@ -328,16 +328,18 @@ def test_extreme_range_is_exact_or_reported(D, orc):
 
 
 def test_overlapped_write_matches_sequential(D):
-    """The overlapped eigenvector write (default, n >= 8192) and the sequential one (vwrite = 1)
-    give the same outputs bit for bit, also with rho < 0 and a padded leading dimension."""
+    """The overlapped eigenvector write (default: two chunks, n >= 8192; vwrite = 3 and 8: that
+    many chunks) and the sequential one (vwrite = 1) give the same outputs bit for bit, also with
+    rho < 0 and a padded leading dimension."""
     import torch
     for n, rho, pad in ((8192, 1.0, 0), (10000, -0.5, 3)):
         d, z, _ = W.uniform(n, 61)
         print(f"[parity] overlap vs sequential n={n} rho={rho} pad={pad}", flush=True)
         outs = []
-        for vw in (0, 1):
+        for vw in (1, 0, 3, 8):
             r = D.eig(d, z, rho, opts=D.opts(vwrite=vw), ldv=n + pad)
             torch.cuda.synchronize()
             outs.append([r.lam.cpu(), r.V.cpu(), r.shift_idx.cpu(), r.mu.cpu(), r.xnorm.cpu()])
-        for a, b in zip(*outs):
-            assert torch.equal(a, b)
+        for o in outs[1:]:
+            for a, b in zip(outs[0], o):
+                assert torch.equal(a, b)
