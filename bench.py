@@ -195,8 +195,10 @@ def main():
         "v_write": {"kernel": "k_fixvec+k_fixout (V written after the eigenvalue kernel, k_fix's work beside it)",
                     "ms": vec_ms, "GB/s": vec_gbs, "frac_hbm": vec_gbs / HBM_PEAK_GBS,
                     "ms_per_step_sequential": ms_seq,
-                    "note": "value is timed with the default overlap: the first half's columns are written on a "
-                            "second stream while the second half's eigenvalues are solved"},
+                    "note": "value is timed with the default overlap: the eigenvalue kernel runs in two chunks and "
+                            "the first chunk's columns are written on a second stream while the second chunk is "
+                            "solved; k_eig and the write are timed here with the write after the eigenvalue "
+                            "kernel, same options"},
         "stats": st,
     }
 
