@@ -337,8 +337,16 @@ def test_overlapped_write_matches_sequential(D):
         print(f"[parity] overlap vs sequential n={n} rho={rho} pad={pad}", flush=True)
         outs = []
         for vw in (1, 0, 3, 8):
-            r = D.eig(d, z, rho, opts=D.opts(vwrite=vw), ldv=n + pad)
+            # outputs poisoned first: a fresh allocation may hold the previous solve's results
+            o = (torch.full((n,), float("nan"), dtype=torch.float64, device="cuda"),
+                 torch.full((n, n + pad), float("nan"), dtype=torch.float64, device="cuda")[:, :n],
+                 torch.full((n,), -1, dtype=torch.int32, device="cuda"),
+                 torch.full((n,), float("nan"), dtype=torch.float64, device="cuda"),
+                 torch.full((n,), float("nan"), dtype=torch.float64, device="cuda"),
+                 torch.full((1,), -1, dtype=torch.int32, device="cuda"))
+            r = D.eig(d, z, rho, opts=D.opts(vwrite=vw), out=o)
             torch.cuda.synchronize()
+            assert not torch.isnan(r.V).any() and not torch.isnan(r.lam).any()
             outs.append([r.lam.cpu(), r.V.cpu(), r.shift_idx.cpu(), r.mu.cpu(), r.xnorm.cpu()])
         for o in outs[1:]:
             for a, b in zip(outs[0], o):
