@@ -3,9 +3,11 @@ against the oracle's tridiag_eig on the same inputs, and its properties at large
 
 The two sides run the same reductions and DPR1 solves; they differ in the order of the sums of
 the products diag(Q1, Q2) V, so results agree to rounding propagated through the merges:
-eigenvalues to 1e-13 ||T|| (absolute: Weyl's bound scale), eigenvector columns to 1e-9 where the
-eigenvalue is separated from the others by more than 1e-6 ||T|| (else the projector onto the
-group is compared), Q^T Q = I and T Q = Q Lambda to 1e-13 n ||T||.
+eigenvalues to 1e-13 ||T|| (absolute: Weyl's bound scale), eigenvector columns to
+1e-12 + 4 n eps ||T|| / gap where the eigenvalue is separated from the others by gap > 1e-6 ||T||
+(the two sides' roundings are a perturbation of T of order n eps ||T||, which moves an eigenvector
+by at most its size over the gap: Davis and Kahan), else the projector onto the group, to the same
+bound with the group's distance to the rest; Q^T Q = I and T Q = Q Lambda to 1e-13 n ||T||.
 
 Columns are compared up to sign.  A merged column is q = diag(Q1, Q2) v with v_j proportional to
 z_j / (d_j - lambda); when z_j is far below the absolute accuracy of the children's Q (a
@@ -52,6 +54,11 @@ def check(D, orc, a, b, tag):
         sep[:-1] = np.minimum(sep[:-1], gaps)
         sep[1:] = np.minimum(sep[1:], gaps)
     worst_c = worst_p = 0.0
+    ratio = 0.0
+    eps = np.finfo(float).eps
+
+    def bound(g):
+        return 1e-12 + 4 * n * eps * nt / g
     k = 0
     while k < n:
         e = k + 1
@@ -60,17 +67,20 @@ def check(D, orc, a, b, tag):
         if e - k == 1 and sep[k] > 1e-6 * nt:
             dc = min(np.max(np.abs(Q[:, k] - Qo[:, k])), np.max(np.abs(Q[:, k] + Qo[:, k])))
             worst_c = max(worst_c, dc)
-            assert dc <= 1e-9, (tag, k, dc)
+            ratio = max(ratio, dc / bound(sep[k]))
+            assert dc <= bound(sep[k]), (tag, k, dc, sep[k])
         else:
+            g = min(abs(lo[k - 1] - lo[k]) if k > 0 else np.inf, abs(lo[e - 1] - lo[e]) if e < n else np.inf)
             dp = np.max(np.abs(Q[:, k:e] @ Q[:, k:e].T - Qo[:, k:e] @ Qo[:, k:e].T))
             worst_p = max(worst_p, dp)
-            assert dp <= 1e-9, (tag, k, e, dp)
+            ratio = max(ratio, dp / bound(g))
+            assert dp <= bound(g), (tag, k, e, dp, g)
         k = e
     orth = np.max(np.abs(Q.T @ Q - np.eye(n)))
     res = np.max(np.abs(T @ Q - Q * lam)) / nt
     assert orth <= 1e-13 * n and res <= 1e-13 * n, (tag, orth, res)
-    print(f"[tridiag] {tag}: lam {el:.2e} col {worst_c:.2e} proj {worst_p:.2e} orth {orth:.2e} res {res:.2e}",
-          flush=True)
+    print(f"[tridiag] {tag}: lam {el:.2e} col {worst_c:.2e} proj {worst_p:.2e} (at most {ratio:.1e} of the bound) "
+          f"orth {orth:.2e} res {res:.2e}", flush=True)
     return lam, Q
 
 
