@@ -195,10 +195,11 @@ def main():
         "v_write": {"kernel": "k_fixvec+k_fixout (V written after the eigenvalue kernel, k_fix's work beside it)",
                     "ms": vec_ms, "GB/s": vec_gbs, "frac_hbm": vec_gbs / HBM_PEAK_GBS,
                     "ms_per_step_sequential": ms_seq,
-                    "note": "value is timed with the default overlap: the eigenvalue kernel runs in two chunks and "
-                            "the first chunk's columns are written on a second stream while the second chunk is "
-                            "solved; k_eig and the write are timed here with the write after the eigenvalue "
-                            "kernel, same options"},
+                    "note": ("value is timed with the tuned write: " + (
+                        "after the eigenvalue kernel (opts.vwrite = 1), as here" if int(base.vwrite) == 1 else
+                        "the eigenvalue kernel in two chunks, the first chunk's columns written on a second "
+                        "stream while the second chunk is solved (opts.vwrite = 0); k_eig and the write are timed "
+                        "here with the write after the eigenvalue kernel, same launch shape"))},
         "stats": st,
     }
 
@@ -306,9 +307,9 @@ def tuned(D, args, d, z, rho, vectors):
     from paper_1405_7537_amd import tuning
     o, entry, hit = tuning.tuned_opts(d, z, rho, vectors=vectors, opts=o)
     log(f"[bench] tuned (vectors={vectors}): split {o.split}, waves/SIMD {o.waves_per_simd}, "
-        f"main_passes {o.main_passes} ({'cache' if hit else 'tuned now'}, {entry['ms']:.3f} ms)")
+        f"main_passes {o.main_passes}, vwrite {o.vwrite} ({'cache' if hit else 'tuned now'}, {entry['ms']:.3f} ms)")
     return o, {"split": int(o.split), "waves_per_simd": int(o.waves_per_simd), "main_passes": int(o.main_passes),
-               "from_cache": bool(hit)}
+               "vwrite": int(o.vwrite), "from_cache": bool(hit)}
 
 
 def bench_batched(D, W, torch, dev, args):

@@ -236,8 +236,9 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
  * The candidates are the split W in {1, 2, 4, 8, 12, 16} (waves sharing one
  * block of 64 eigenvalues, i.e. W threads per eigenvalue; every wave's slice
  * of the inner sum keeps at least 64 terms), the register budget
- * waves_per_simd in {4, 6, 8} and, for the model iteration (root = 1), the
- * pass budget main_passes ({2, 3} single, {2, 3, 4} batched).  Each
+ * waves_per_simd in {4, 6, 8}, for the model iteration (root = 1) the pass
+ * budget main_passes ({2, 3} single, {2, 3, 4} batched) and, for one problem
+ * with eigenvectors at n >= 8192, the write vwrite in {0 (overlapped), 1}.  Each
  * candidate is solved once untimed and then `reps` times (0 = 3) between two
  * events on `stream`; the fastest mean wins, ties keep the earlier candidate
  * (smaller W, then fewer waves, then the smaller budget).  Both calls run on
@@ -245,8 +246,8 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
  * valid solution in the outputs (that of the last candidate, equal to the
  * tuned one's within the parity bounds) and synchronise `stream`.
  * dpr1_autotune: arguments as dpr1_eig; opts (in/out, required) supplies the
- *   other options and receives the chosen split, waves_per_simd and
- *   main_passes; best_ms
+ *   other options and receives the chosen split, waves_per_simd,
+ *   main_passes and vwrite; best_ms
  *   (optional) the fastest mean time.
  * dpr1_batched_autotune: arguments as dpr1_eig_batched; plan (in/out, from
  *   dpr1_batched_plan for these offsets) receives the chosen split, grid,

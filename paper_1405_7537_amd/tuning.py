@@ -1,12 +1,13 @@
-"""Persistent cache of autotuned launch shapes (split W, register budget, pass budget).
+"""Persistent cache of autotuned launch shapes (split W, register budget, pass budget, and for a
+single problem with eigenvectors the overlapped or sequential write).
 
 The library's autotuner (dpr1_autotune / dpr1_batched_autotune) times every
 candidate on real data; this module remembers the winner in a JSON file keyed
 by GPU architecture, operation and a size bucket, so that later solves of a
 similar shape reuse it without timing again.  File: $DPR1_TUNING_CACHE, else
 ~/.cache/paper_1405_7537_amd/tuning.json.  Entries hold only integers
-(split, waves_per_simd, main_passes) and the measured time; a corrupt or
-unreadable file is treated as empty.
+(split, waves_per_simd, main_passes, vwrite) and the measured time; a corrupt
+or unreadable file is treated as empty.
 """
 from __future__ import annotations
 
@@ -17,7 +18,7 @@ import tempfile
 
 import numpy as np
 
-VERSION = 2
+VERSION = 3
 
 
 def cache_path() -> str:
@@ -66,7 +67,8 @@ def store(key: str, entry: dict, path: str | None = None) -> bool:
 def _store(key: str, entry: dict, path: str) -> None:
     data = load(path)
     data[key] = {"split": int(entry["split"]), "main_passes": int(entry["main_passes"]),
-                 "waves_per_simd": int(entry.get("waves_per_simd", 0)), "ms": float(entry["ms"])}
+                 "waves_per_simd": int(entry.get("waves_per_simd", 0)), "vwrite": int(entry.get("vwrite", 0)),
+                 "ms": float(entry["ms"])}
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     fd, tmp = tempfile.mkstemp(dir=os.path.dirname(os.path.abspath(path)), suffix=".tmp")
     with os.fdopen(fd, "w") as f:
@@ -91,9 +93,11 @@ def tuned_opts(d, z, rho, vectors=True, opts=None, reps=3, device="cuda", path=N
         o.split = int(hit["split"])
         o.main_passes = int(hit["main_passes"])
         o.waves_per_simd = int(hit.get("waves_per_simd", 0))
+        o.vwrite = int(hit.get("vwrite", 0))
         return o, hit, True
     o, ms = D.autotune(d, z, rho, vectors=vectors, opts=o, reps=reps, device=device)
-    entry = {"split": o.split, "main_passes": o.main_passes, "waves_per_simd": o.waves_per_simd, "ms": ms}
+    entry = {"split": o.split, "main_passes": o.main_passes, "waves_per_simd": o.waves_per_simd,
+             "vwrite": o.vwrite, "ms": ms}
     store(key, entry, path)
     return o, entry, False
 
@@ -114,6 +118,6 @@ def tuned_batch(offs, d, z, rho, vectors=True, opts=None, reps=3, device="cuda",
     b = D.Batch(offs, opts=o, vectors=vectors, device=device)
     ms = b.autotune(d, z, rho, reps=reps)
     entry = {"split": b.plan.split, "main_passes": b.plan.opts.main_passes,
-             "waves_per_simd": b.plan.opts.waves_per_simd, "ms": ms}
+             "waves_per_simd": b.plan.opts.waves_per_simd, "vwrite": b.plan.opts.vwrite, "ms": ms}
     store(key, entry, path)
     return b, entry, False

@@ -26,11 +26,12 @@ def test_batched_key_uses_count_largest_size_and_volume():
 def test_store_and_load_round_trip(tmp_path):
     p = str(tmp_path / "sub" / "tuning.json")
     assert T.load(p) == {}
-    T.store("k1", {"split": 8, "main_passes": 2, "waves_per_simd": 8, "ms": 4.25}, p)
+    T.store("k1", {"split": 8, "main_passes": 2, "waves_per_simd": 8, "vwrite": 1, "ms": 4.25}, p)
     T.store("k2", {"split": 4, "main_passes": 3, "ms": 1.5}, p)
     got = T.load(p)
-    assert got["k1"] == {"split": 8, "main_passes": 2, "waves_per_simd": 8, "ms": 4.25}
+    assert got["k1"] == {"split": 8, "main_passes": 2, "waves_per_simd": 8, "vwrite": 1, "ms": 4.25}
     assert got["k2"]["waves_per_simd"] == 0          # absent: the library default
+    assert got["k2"]["vwrite"] == 0
     assert got["k2"]["split"] == 4
     T.store("k1", {"split": 16, "main_passes": 2, "ms": 4.0}, p)
     assert T.load(p)["k1"]["split"] == 16
