@@ -2143,6 +2143,10 @@ static int split_candidates(int64_t nmax, int* out) {
   return c;
 }
 static const int OCC_CAND[3] = {4, 6, 8};
+// The 6- and 8-wave register budgets spill part of k_eig's state to scratch
+// (about 7 to 18 times the HBM bytes of the 4-wave variant at n = 32768):
+// they are chosen only when at least 2 % faster, not on timing noise.
+static double occ_margin(int oc) { return oc > 4 ? 0.98 : 1.0; }
 
 // Number of (problem, column group, row tile) blocks of the batched
 // eigenvector launch.
@@ -2616,7 +2620,7 @@ int dpr1_autotune(const double* d, const double* z, double rho, int64_t n, doubl
                                                     nullptr, &c, work, work_bytes, stream); },
                             reps, (hipStream_t)stream, &ms);
         if (rc != 0) return rc;
-        if (ms < best) {
+        if (ms < best * occ_margin(oc)) {
           best = ms;
           bw = c.split;
           bp = c.main_passes;
@@ -2660,7 +2664,7 @@ int dpr1_batched_autotune(dpr1_plan* plan, const int64_t* offs, const double* d,
                                                             xnorm, info, nullptr, work, work_bytes, stream); },
                             reps, (hipStream_t)stream, &ms);
         if (rc != 0) return rc;
-        if (ms < best) {
+        if (ms < best * occ_margin(oc)) {
           best = ms;
           bestp = c;
         }
