@@ -292,6 +292,17 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
                               const double* xnorm, const double* V, const double* lambda_bar,
                               const double* V_bar, double* d_bar, double* z_bar,
                               double* rho_bar, void* work, size_t work_bytes, void* stream);
+/* One problem, the same reverse mode with rho a host scalar (!= 0, finite) and
+ * V, V_bar column-major with leading dimensions ldv, ldvb >= n (ignored when
+ * the matrix is NULL); workspace dpr1_backward_workspace_size(n, 1) bytes;
+ * rho_bar [1] device.  Argument errors -p as the parameter list orders them
+ * (z may be NULL only when V is given: -2; ldv: -9, ldvb: -12, work_bytes:
+ * -17).  Kernel launches only.                                              */
+int dpr1_eig_backward(const double* d, const double* z, double rho, int64_t n,
+                      const int32_t* shift_idx, const double* mu, const double* xnorm,
+                      const double* V, int64_t ldv, const double* lambda_bar,
+                      const double* V_bar, int64_t ldvb, double* d_bar, double* z_bar,
+                      double* rho_bar, void* work, size_t work_bytes, void* stream);
 
 /* Reducible inputs (Sec. 1): any finite d (any order, repeated values) and
  * any finite z (zeros allowed).  The poles are sorted decreasingly; a pole

@@ -69,6 +69,8 @@ struct GArgs {
   double* part_d;         // [nb][ntile][n]  sum_k Q_jk V_jk
   double* part_z;         // [nb][ntile][n]  sum_k V_jk u_k
   int has_B;              // 0: V_bar is null, P = 0
+  int64_t lda;            // leading dimension of V (A), column-major
+  int64_t ldb;            // leading dimension of V_bar (EPI_X's B), column-major
 };
 
 // Element (j, k) of V for problem offset vo, recomputed from the forward's
@@ -87,7 +89,9 @@ __device__ __forceinline__ double v_elem(const GArgs& g, int64_t vo, int64_t j, 
   return q * g.ixn[vo + k];
 }
 
-// Column-major n x n matrices (ld = n).  EPI_X computes op(A) = A^T (A = V),
+// Column-major n x n matrices (V with ld = lda, V_bar with ld = ldb; a
+// batch's problems lda * n and ldb * n apart; X row-major with ld = n).
+// EPI_X computes op(A) = A^T (A = V),
 // EPI_D op(A) = A.  The linear block index is mapped so that all tiles of a
 // problem run on one XCD and share its L2.
 // RV: V is not passed in; its elements are rebuilt by v_elem (a separate
@@ -105,8 +109,9 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
   const int tm = t % tiles, tn = t / tiles;
   const int64_t mo = (int64_t)pb * n * n;
   const int64_t vo = (int64_t)pb * n;
-  const double* A = RV ? nullptr : g.A + mo;
-  const double* Bm = g.B + mo;
+  const double* A = RV ? nullptr : g.A + (int64_t)pb * g.lda * n;
+  const double* Bm = g.B + (EPI == EPI_X ? (int64_t)pb * g.ldb * n : mo);
+  const int64_t lda = g.lda, ldb = g.ldb;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
   const int wv = tid / 64, lane = tid % 64;
@@ -135,20 +140,20 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
       int e = tid + e2 * NT;
       int m, kk;
       if (EPI == EPI_X) {
-        kk = e % BK;   // A^T(m, k) = V[k + m n], contiguous along k
+        kk = e % BK;   // A^T(m, k) = V[k + m lda], contiguous along k
         m = e / BK;
         int64_t gm = m0 + m, gk = k0 + kk;
-        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gk, gm) : A[gk + gm * n]) : 0.0;
+        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gk, gm) : A[gk + gm * lda]) : 0.0;
       } else {
-        m = e % BM;    // A(m, k) = V[m + k n], contiguous along m
+        m = e % BM;    // A(m, k) = V[m + k lda], contiguous along m
         kk = e / BM;
         int64_t gm = m0 + m, gk = k0 + kk;
-        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gm, gk) : A[gm + gk * n]) : 0.0;
+        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gm, gk) : A[gm + gk * lda]) : 0.0;
       }
       if (EPI == EPI_X) {
-        int kb = e % BK, c = e / BK;  // V_bar(k, c) = V_bar[k + c n], contiguous along k
+        int kb = e % BK, c = e / BK;  // V_bar(k, c) = V_bar[k + c ldb], contiguous along k
         int64_t gk = k0 + kb, gc = n0 + c;
-        rb[e2] = (gk < n && gc < n) ? Bm[gk + gc * n] : 0.0;
+        rb[e2] = (gk < n && gc < n) ? Bm[gk + gc * ldb] : 0.0;
       } else {
         int c = e % BN, kb = e / BN;  // X(k, c) = X[k n + c] (row-major), contiguous along c
         int64_t gk = k0 + kb, gc = n0 + c;
@@ -277,7 +282,7 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
           cs[b] += x * ry[rl];
         } else {
           // Q(row = j, col = k) V(j, k) for d_bar, V(j, k) u_k for z_bar
-          double vjk = RV ? v_elem(g, vo, row, col) : A[row + col * n];
+          double vjk = RV ? v_elem(g, vo, row, col) : A[row + col * lda];
           rs1[q] += v * vjk;
           rs2[q] += vjk * cy[cl];
         }
@@ -406,7 +411,7 @@ __global__ void __launch_bounds__(256) k_bwd_eigonly(GArgs g, const double* __re
                                                      double* __restrict__ z_bar, double* __restrict__ rho_bar) {
   const int64_t n = g.n;
   const int64_t p = blockIdx.y;
-  const int64_t vo = p * n, mo = p * n * n;
+  const int64_t vo = p * n;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x == 0) {
     __shared__ double red[256];
@@ -428,7 +433,7 @@ __global__ void __launch_bounds__(256) k_bwd_eigonly(GArgs g, const double* __re
   double sd = 0.0, sz = 0.0;
   for (int64_t k = 0; k < n; ++k) {
     const double lb = lam_bar ? lam_bar[vo + k] : 0.0;
-    const double v = g.A ? g.A[mo + j + k * n] : v_elem(g, vo, j, k);
+    const double v = g.A ? g.A[p * g.lda * n + j + k * g.lda] : v_elem(g, vo, j, k);
     const double t = lb * v;
     sd = __builtin_fma(t, v, sd);
     sz += t / xnorm[vo + k];
@@ -437,8 +442,12 @@ __global__ void __launch_bounds__(256) k_bwd_eigonly(GArgs g, const double* __re
   z_bar[vo + j] = -2.0 * sz;
 }
 
+// rho of the single-problem call, moved to the device as a kernel argument
+// (no copy from host memory, so the call can be captured in a graph)
+__global__ void k_set_rho(double* __restrict__ dst, double v) { *dst = v; }
+
 struct BLayout {
-  size_t X, y, u, pr, pc, pd, pz, sig, ixn, total;
+  size_t X, y, u, pr, pc, pd, pz, sig, ixn, rho, total;
 };
 static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 static BLayout blayout(int64_t n, int64_t nb) {
@@ -454,40 +463,16 @@ static BLayout blayout(int64_t n, int64_t nb) {
   L.pz = o; o = al(o + sizeof(double) * n * nt * nb);
   L.sig = o; o = al(o + sizeof(double) * n * nb);
   L.ixn = o; o = al(o + sizeof(double) * n * nb);
+  L.rho = o; o = al(o + sizeof(double));
   L.total = o;
   return L;
 }
 
-}  // namespace bwd
-}  // namespace dpr1
-
-using namespace dpr1::bwd;
-
-extern "C" {
-
-size_t dpr1_backward_workspace_size(int64_t n, int64_t nbatch) {
-  if (n < 1 || nbatch < 1) return 0;
-  return blayout(n, nbatch).total;
-}
-
-int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const double* z, const double* rho,
-                              const int32_t* shift_idx, const double* mu, const double* xnorm, const double* V,
-                              const double* lambda_bar, const double* V_bar, double* d_bar, double* z_bar,
-                              double* rho_bar, void* work, size_t work_bytes, void* stream) {
-  if (nbatch < 1 || nbatch > 65535) return -1;
-  if (n < 1 || n > (1 << 20)) return -2;
-  if (!d) return -3;
-  if (!z && !V) return -4;
-  if (!rho) return -5;
-  if (!shift_idx) return -6;
-  if (!mu) return -7;
-  if (!xnorm) return -8;
-  if (!d_bar) return -12;
-  if (!z_bar) return -13;
-  if (!rho_bar) return -14;
-  if (!work) return -15;
-  BLayout L = blayout(n, nbatch);
-  if (work_bytes < L.total) return -16;
+// The launches of both entry points (arguments checked there).
+static int run_backward(int64_t nbatch, int64_t n, const double* d, const double* z, const double* rho,
+                        const int32_t* shift_idx, const double* mu, const double* xnorm, const double* V, int64_t lda,
+                        const double* lambda_bar, const double* V_bar, int64_t ldb, double* d_bar, double* z_bar,
+                        double* rho_bar, void* work, const BLayout& L, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   char* w = (char*)work;
   double* X = (double*)(w + L.X);
@@ -525,6 +510,8 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
   g.part_d = pd;
   g.part_z = pz;
   g.has_B = V_bar != nullptr;
+  g.lda = lda;
+  g.ldb = ldb;
   if (!V_bar) {
     hipLaunchKernelGGL(k_bwd_eigonly, dim3((unsigned)((n + 255) / 256), (unsigned)nbatch), dim3(256), 0, st, g,
                        lambda_bar, xnorm, rho, d_bar, z_bar, rho_bar);
@@ -547,6 +534,66 @@ int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const 
                      rho, pd, pz, d_bar, z_bar);
   if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
   return DPR1_OK;
+}
+
+}  // namespace bwd
+}  // namespace dpr1
+
+using namespace dpr1::bwd;
+
+extern "C" {
+
+size_t dpr1_backward_workspace_size(int64_t n, int64_t nbatch) {
+  if (n < 1 || nbatch < 1) return 0;
+  return blayout(n, nbatch).total;
+}
+
+int dpr1_eig_backward_batched(int64_t nbatch, int64_t n, const double* d, const double* z, const double* rho,
+                              const int32_t* shift_idx, const double* mu, const double* xnorm, const double* V,
+                              const double* lambda_bar, const double* V_bar, double* d_bar, double* z_bar,
+                              double* rho_bar, void* work, size_t work_bytes, void* stream) {
+  if (nbatch < 1 || nbatch > 65535) return -1;
+  if (n < 1 || n > (1 << 20)) return -2;
+  if (!d) return -3;
+  if (!z && !V) return -4;
+  if (!rho) return -5;
+  if (!shift_idx) return -6;
+  if (!mu) return -7;
+  if (!xnorm) return -8;
+  if (!d_bar) return -12;
+  if (!z_bar) return -13;
+  if (!rho_bar) return -14;
+  if (!work) return -15;
+  BLayout L = blayout(n, nbatch);
+  if (work_bytes < L.total) return -16;
+  return run_backward(nbatch, n, d, z, rho, shift_idx, mu, xnorm, V, n, lambda_bar, V_bar, n, d_bar, z_bar, rho_bar,
+                      work, L, stream);
+}
+
+int dpr1_eig_backward(const double* d, const double* z, double rho, int64_t n, const int32_t* shift_idx,
+                      const double* mu, const double* xnorm, const double* V, int64_t ldv, const double* lambda_bar,
+                      const double* V_bar, int64_t ldvb, double* d_bar, double* z_bar, double* rho_bar, void* work,
+                      size_t work_bytes, void* stream) {
+  if (!d) return -1;
+  if (!z && !V) return -2;
+  if (!(rho == rho) || rho == 0.0 || rho == INFINITY || rho == -INFINITY) return -3;
+  if (n < 1 || n > (1 << 20)) return -4;
+  if (!shift_idx) return -5;
+  if (!mu) return -6;
+  if (!xnorm) return -7;
+  if (V && ldv < n) return -9;
+  if (V_bar && ldvb < n) return -12;
+  if (!d_bar) return -13;
+  if (!z_bar) return -14;
+  if (!rho_bar) return -15;
+  if (!work) return -16;
+  BLayout L = blayout(n, 1);
+  if (work_bytes < L.total) return -17;
+  double* drho = (double*)((char*)work + L.rho);
+  hipLaunchKernelGGL(k_set_rho, dim3(1), dim3(1), 0, (hipStream_t)stream, drho, rho);
+  if (hipGetLastError() != hipSuccess) return DPR1_EHIP;
+  return run_backward(1, n, d, z, drho, shift_idx, mu, xnorm, V, V ? ldv : n, lambda_bar, V_bar, V_bar ? ldvb : n,
+                      d_bar, z_bar, rho_bar, work, L, stream);
 }
 
 }  // extern "C"

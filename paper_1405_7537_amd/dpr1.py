@@ -71,6 +71,8 @@ def lib():
             L.dpr1_backward_workspace_size.argtypes = [i64, i64]
             L.dpr1_backward_workspace_size.restype = C.c_size_t
             L.dpr1_eig_backward_batched.argtypes = [i64, i64] + [vp] * 12 + [vp, C.c_size_t, vp]
+            L.dpr1_eig_backward.argtypes = [vp, vp, C.c_double, i64, vp, vp, vp, vp, i64, vp, vp, i64, vp, vp,
+                                            vp, vp, C.c_size_t, vp]
         L.dpr1_general_workspace_size.argtypes = [i64]
         L.dpr1_general_workspace_size.restype = C.c_size_t
         L.dpr1_eig_general.argtypes = [vp, vp, C.c_double, i64, vp, vp, i64, vp, C.POINTER(Opts), vp,
@@ -463,6 +465,38 @@ def backward_batched(d, z, rho, shift_idx, mu, xnorm, V, lam_bar=None, V_bar=Non
     return d_bar, z_bar, rho_bar
 
 
+def backward(d, z, rho, shift_idx, mu, xnorm, V=None, lam_bar=None, V_bar=None, work=None):
+    """Reverse mode for one problem (dpr1_eig_backward): d, z, shift_idx, mu, xnorm, lam_bar [n],
+    rho a number; V as returned by eig() (V[:, k] = v_k, column-major storage with any leading
+    dimension) or None (recomputed from z and the shifted representation); V_bar [n, n] in either
+    layout.  Returns (d_bar [n], z_bar [n], rho_bar [1])."""
+    n = d.numel()
+    dev = d.device
+    d_bar = torch.empty(n, dtype=torch.float64, device=dev)
+    z_bar = torch.empty(n, dtype=torch.float64, device=dev)
+    rho_bar = torch.empty(1, dtype=torch.float64, device=dev)
+    wb = int(lib().dpr1_backward_workspace_size(n, 1))
+    if work is None or work.numel() < wb:
+        work = torch.empty(wb, dtype=torch.uint8, device=dev)
+
+    def colmajor(M):
+        if M is None:
+            return None, n
+        if M.stride(0) == 1 and M.stride(1) >= n:
+            return M, M.stride(1)
+        return M.t().contiguous().t(), n
+    Vc, ldv = colmajor(V)
+    Vbc, ldvb = colmajor(V_bar)
+    for t in (d, z, shift_idx, mu, xnorm, lam_bar):
+        if t is not None:
+            assert t.is_contiguous() and t.device == dev
+    rc = lib().dpr1_eig_backward(_ptr(d), _ptr(z), float(rho), n, _ptr(shift_idx), _ptr(mu), _ptr(xnorm), _ptr(Vc),
+                                 ldv, _ptr(lam_bar), _ptr(Vbc), ldvb, _ptr(d_bar), _ptr(z_bar), _ptr(rho_bar),
+                                 _ptr(work), wb, _stream())
+    _rc(rc, "dpr1_eig_backward")
+    return d_bar, z_bar, rho_bar
+
+
 def _rho_like(rho):
     """(device, shape) of a tensor rho, None for a Python number (which gets no gradient)."""
     return (rho.device, rho.shape) if torch.is_tensor(rho) else None
@@ -480,29 +514,24 @@ def _rho_grad(ctx, rb):
 class DPR1Eig(torch.autograd.Function):
     """(lam, V) = eig(D + rho z z^T) with a hand-written adjoint.
 
-    Forward: dpr1_eig.  Backward: dpr1_eig_backward_batched with nb = 1, which needs only
-    V and the shifted representation (shift_idx, mu, ||x||) saved by the forward."""
+    Forward: dpr1_eig.  Backward: dpr1_eig_backward, which needs only V and the shifted
+    representation (shift_idx, mu, ||x||) saved by the forward."""
 
     @staticmethod
     def forward(ctx, d, z, rho):
-        rho_t = rho if torch.is_tensor(rho) else torch.tensor(float(rho), dtype=torch.float64, device=d.device)
-        r = eig(d.detach(), z.detach(), float(rho_t), vectors=True)
+        rho_v = float(rho)
+        r = eig(d.detach(), z.detach(), rho_v, vectors=True)
         ctx.rho_like = _rho_like(rho)
-        ctx.save_for_backward(d.detach(), z.detach(), rho_t.detach().reshape(1).to(d.device), r.shift_idx, r.mu,
-                              r.xnorm, r.V)
+        ctx.rho_v = rho_v
+        ctx.save_for_backward(d.detach(), z.detach(), r.shift_idx, r.mu, r.xnorm, r.V)
         return r.lam, r.V
 
     @staticmethod
     def backward(ctx, lam_bar, V_bar):
-        d, z, rho, idx, mu, xn, V = ctx.saved_tensors
-        n = d.numel()
-        lb = lam_bar.contiguous().view(1, n) if lam_bar is not None else None
-        # V is the transpose view of a row-major [k, j] buffer: column-major storage
-        Vs = V.t().contiguous()
-        Vb = V_bar.t().contiguous() if V_bar is not None else None
-        db, zb, rb = backward_batched(d.view(1, n), z.view(1, n), rho, idx.view(1, n), mu.view(1, n),
-                                      xn.view(1, n), Vs, lb, Vb)
-        return db.view(n), zb.view(n), _rho_grad(ctx, rb)
+        d, z, idx, mu, xn, V = ctx.saved_tensors
+        lb = lam_bar.contiguous() if lam_bar is not None else None
+        db, zb, rb = backward(d.contiguous(), z.contiguous(), ctx.rho_v, idx, mu, xn, V, lb, V_bar)
+        return db, zb, _rho_grad(ctx, rb)
 
 
 class DPR1EigValues(torch.autograd.Function):

@@ -151,3 +151,30 @@ def test_noalloc_limits_need_no_gpu(lib):
                                 None, None, None) == -4
     assert lib.dpr1_eig_noalloc(None, fake, 1.0, 5, fake, None, 0, None, None, None, fake,
                                 None, None, None) == -1
+
+
+def test_single_backward_argument_errors_need_no_gpu(lib):
+    """dpr1_eig_backward checks its arguments before any launch (-p as the parameter list orders them)."""
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.dpr1_eig_backward.argtypes = [vp, vp, ctypes.c_double, i64, vp, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp, vp,
+                                      ctypes.c_size_t, vp]
+    f = vp(0x1000)
+    ok = dict(d=f, z=f, rho=1.0, n=8, si=f, mu=f, xn=f, V=f, ldv=8, lb=None, Vb=f, ldvb=8, db=f, zb=f, rb=f, w=f,
+              wb=1 << 24)
+
+    def call(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return lib.dpr1_eig_backward(a["d"], a["z"], a["rho"], a["n"], a["si"], a["mu"], a["xn"], a["V"], a["ldv"],
+                                     a["lb"], a["Vb"], a["ldvb"], a["db"], a["zb"], a["rb"], a["w"], a["wb"], None)
+    assert call(d=None) == -1
+    assert call(z=None, V=None) == -2
+    assert call(rho=0.0) == -3 and call(rho=float("nan")) == -3
+    assert call(n=0) == -4
+    assert call(si=None) == -5
+    assert call(ldv=7) == -9
+    assert call(ldvb=7) == -12
+    assert call(rb=None) == -15
+    assert call(w=None) == -16
+    assert call(wb=16) == -17

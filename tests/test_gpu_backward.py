@@ -229,3 +229,35 @@ def test_eigenvalues_only_autograd(D):
     for a, b in zip(g1, g2):
         scale = float(b.abs().max())
         assert float((a - b).abs().max()) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n,seed,rho", [(100, 31, 1.0), (333, 32, -0.7)])
+def test_single_problem_entry(D, n, seed, rho):
+    """dpr1_eig_backward (one problem, rho a host number, V and V_bar with leading dimensions)
+    gives the batched call's results for nb = 1 bit for bit: with V stored (also padded to
+    ld = n + 5, V_bar to ld = n + 3), and with V recomputed."""
+    import torch
+    d, z, _ = W.uniform(n, seed)
+    rng = np.random.default_rng(seed)
+    r = D.eig(d, z, rho, ldv=n + 5)
+    torch.cuda.synchronize()
+    dd = torch.as_tensor(d, device="cuda")
+    zz = torch.as_tensor(z, device="cuda")
+    lb = torch.as_tensor(rng.standard_normal(n), device="cuda")
+    Vb = torch.as_tensor(rng.standard_normal((n, n)), device="cuda")
+    Vb_pad = torch.empty((n, n + 3), dtype=torch.float64, device="cuda")[:, :n]   # column-major, ld n + 3
+    Vb_pad.copy_(Vb.t())
+    Vb_cm = Vb_pad.t()                                                             # V_bar[j, k], stride (1, n + 3)
+    V = r.V                                                                        # stride (1, n + 5)
+    assert V.stride() == (1, n + 5) and Vb_cm.stride() == (1, n + 3)
+    rho_t = torch.tensor([rho], dtype=torch.float64, device="cuda")
+    for Vin in (V, None):
+        ref = D.backward_batched(dd.view(1, n), zz.view(1, n), rho_t, r.shift_idx.view(1, n), r.mu.view(1, n),
+                                 r.xnorm.view(1, n), V.contiguous().t().contiguous() if Vin is not None else None,
+                                 lb.view(1, n), Vb.t().contiguous())
+        got = D.backward(dd, zz, rho, r.shift_idx, r.mu, r.xnorm, Vin, lb, Vb_cm)
+        torch.cuda.synchronize()
+        print(f"[backward] single entry n={n} rho={rho} V {'stored' if Vin is not None else 'recomputed'}",
+              flush=True)
+        for a, b in zip(ref, got):
+            assert torch.equal(a.reshape(-1), b.reshape(-1))
