@@ -87,13 +87,19 @@ extern "C" {
 #define DPR1_STAT_KNU_GT 8    /* eigenpairs with K_nu > knu_thr (eq. K0)     */
 #define DPR1_STAT_REMEDY_R1 9 /* eigenpairs recomputed by remedy (R1)        */
 #define DPR1_STAT_REMEDY_R2 10 /* eigenpairs recomputed by remedy (R2)       */
-#define DPR1_NSTATS 11
+#define DPR1_STAT_EXT_B 11    /* eigenvalues whose tip b (eq. b_ob) was formed
+                                 in double-double                          */
+#define DPR1_NSTATS 12
 
 /* Options.  dpr1_default_opts fills the defaults noted below.               */
 typedef struct dpr1_opts {
   int32_t mode_b;      /* tip b of A_i^{-1}: 0 double-double always (default);
-                          1 double-double only when K_b > 100 (the paper's
-                          gate); 2 never (the paper's dpr1eig_nd)            */
+                          1 double-double only when K_b > 100; 2 never (the
+                          paper's dpr1eig_nd); 3 Algorithm 1's gate:
+                          double-double when the bound of eq. (knu2),
+                          min((n+4) sqrt(n) K_b, 3 sqrt(n) + (n+4)(1 + 2 K_z))
+                          from the standard-precision K_b, exceeds
+                          100 (n+4) sqrt(n)                                  */
   int32_t root;        /* 0 bisection (Alg. 1); 1 (default) safeguarded
                           model iteration: the nearest pole exact plus one
                           pole fitted to the value, slope and curvature of

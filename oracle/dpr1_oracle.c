@@ -65,7 +65,9 @@
 typedef __float128 quad;
 
 typedef struct {
-  int32_t mode_b;        /* 0 quad always, 1 quad iff K_b > 100, 2 never     */
+  int32_t mode_b;        /* 0 quad always, 1 quad iff K_b > 100, 2 never,
+                            3 quad iff the bound of eq. (knu2) exceeds
+                            100 (n+4) sqrt(n)                              */
   int32_t polish;        /* 1: extended-precision polish when flagged        */
   double kappa_polish;   /* threshold on kappa_g*max(1,|mu/lambda|)          */
   double nearzero;       /* factor of the near-zero test                     */
@@ -301,7 +303,14 @@ static int dpr1eig_at(const double* d, const double* z, double rho, int64_t n, i
   int use_ext;
   if (opts.mode_b == 0) use_ext = 1;
   else if (opts.mode_b == 1) use_ext = (Kb64 > 100.0);
-  else use_ext = 0;
+  else if (opts.mode_b == 3) {
+    /* Algorithm 1's gate: the bound of eq. (knu2) from the standard-precision
+     * K_b, "much larger than O(n)" read as above 100 (n+4) sqrt(n), i.e.
+     * K_b > 100 unless K_z shows that b cannot influence ||A_i^{-1}|| */
+    double sn = sqrt((double)n);
+    double k1 = (n + 4) * sn * Kb64, k2 = 3 * sn + (n + 4) * (1 + 2 * dg.Kz);
+    use_ext = (k1 < k2 ? k1 : k2) > 100.0 * (n + 4) * sn;
+  } else use_ext = 0;
   A.b = use_ext ? (double)A.bq : b64;
   if (!use_ext) A.bq = (quad)b64;   /* the polish then sees the b in use */
   /* An arrow entry whose square leaves binary64 (|w_j| >= 2^511), or a tip

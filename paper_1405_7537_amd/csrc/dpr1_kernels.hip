@@ -60,6 +60,7 @@ struct Meta {
   int32_t pad;
   double rho;    // |rho|
   double zz;     // sum zeta_j^2
+  double zabs;   // sum |zeta_j| (K_z of eq. knu2)
 };
 
 enum : int32_t { FIX_POLISH = 1, FIX_NEARZERO = 2, FIX_CONTINUE = 4 };
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, int nsplit, const int64
                                               double rho_host, Meta* __restrict__ meta, double* __restrict__ sd,
                                               double* __restrict__ sz, double* __restrict__ pairs,
                                               double* __restrict__ z2lo, int32_t* __restrict__ info,
-                                              double2* __restrict__ part, int32_t* __restrict__ done_ctr) {
+                                              double* __restrict__ part, int32_t* __restrict__ done_ctr) {
   const int p = nsplit == 1 ? (int)blockIdx.x : 0;
   const int bs = nsplit == 1 ? 0 : (int)blockIdx.x;
   if (p >= nprob) return;
@@ -277,12 +278,12 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, int nsplit, const int64
   const int neg = rho < 0;
   const int64_t chunk = (n + nsplit - 1) / nsplit;
   const int64_t ja = min(n, (int64_t)bs * chunk), jb = min(n, ja + chunk);
-  __shared__ double red[256];
+  __shared__ double red[256], red2[256];
   __shared__ int flags, last;
   if (threadIdx.x == 0) flags = 0;
   __syncthreads();
   int f = 0;
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0;
   for (int64_t j = ja + threadIdx.x; j < jb; j += blockDim.x) {
     int64_t src = neg ? n - 1 - j : j;
     double dj = d[off + src], zj = z[off + src];
@@ -306,19 +307,27 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, int nsplit, const int64
     pairs[2 * (off + j) + 1] = z2;
     z2lo[off + j] = __builtin_fma(zj, zj, -z2);
     acc += z2;
+    acc2 += fabs(zj);
   }
   if (f) atomicOr(&flags, f);
   red[threadIdx.x] = acc;
+  red2[threadIdx.x] = acc2;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      red2[threadIdx.x] += red2[threadIdx.x + s];
+    }
     __syncthreads();
   }
-  double zz = red[0];
+  double zz = red[0], za = red2[0];
   int fl = flags;
   if (nsplit > 1) {
+    // part: (sum zeta^2, sum |zeta|, flags) per slice
     if (threadIdx.x == 0) {
-      part[bs] = make_double2(zz, (double)fl);
+      part[3 * bs] = zz;
+      part[3 * bs + 1] = za;
+      part[3 * bs + 2] = (double)fl;
       __threadfence();
       last = atomicAdd(done_ctr, 1) == nsplit - 1;
     }
@@ -326,12 +335,14 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, int nsplit, const int64
     if (!last) return;
     __threadfence();
     if (threadIdx.x == 0) {
-      const volatile double2* vp = part;
+      const volatile double* vp = part;
       zz = 0.0;
+      za = 0.0;
       fl = 0;
       for (int q = 0; q < nsplit; ++q) {
-        zz += vp[q].x;
-        fl |= (int)vp[q].y;
+        zz += vp[3 * q];
+        za += vp[3 * q + 1];
+        fl |= (int)vp[3 * q + 2];
       }
     }
   }
@@ -350,6 +361,7 @@ __global__ void __launch_bounds__(256) k_prep(int nprob, int nsplit, const int64
     m.pad = 0;
     m.rho = fabs(rho);
     m.zz = zz;
+    m.zabs = za;
     meta[p] = m;
     if (info) info[p] = code;
   }
@@ -629,6 +641,15 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   const double Pr = rho * Pd.hi, Nr = rho * Nd.hi;
   const double Kb64 = (1.0 + Pr - Nr) / fabs(1.0 + Pr + Nr);
   bool use_ext = A.mode_b == 0 || (A.mode_b == 1 && Kb64 > 100.0);
+  if (A.mode_b == 3) {
+    // Algorithm 1's gate: the bound of eq. (knu2) from the standard-precision
+    // K_b above 100 (n+4) sqrt(n) (K_b > 100 unless K_z shows that b cannot
+    // influence ||A_i^{-1}||)
+    const double sn = sqrt((double)n), azi = fabs(zi);
+    const double Kz = (M.zabs - azi) / azi;
+    const double k1 = (n + 4) * sn * Kb64, k2 = 3.0 * sn + (n + 4) * (1.0 + 2.0 * Kz);
+    use_ext = fmin(k1, k2) > 100.0 * (n + 4) * sn;
+  }
   const double rzi = 1.0 / zi;
   const double b64 = ((1.0 / rho + Pd.hi) + Nd.hi) * (rzi * rzi);
   const double bh = use_ext ? bdd.hi : b64;
@@ -915,6 +936,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
   if (A.stats && wv == 0) {
     bool kb = valid && Kb64 > 100.0;
     unsigned long long bal = __ballot(kb);
+    const unsigned long long bext = __ballot(valid && use_ext);
     int itv = valid ? iters : 0;
     int imax = itv, isum = itv;
     for (int o = 32; o > 0; o >>= 1) {
@@ -923,6 +945,7 @@ __device__ void eig_block(const KArgs& A, int p, int k0, double* red) {
     }
     if (lane == 0) {
       if (bal) atomicAdd(&A.stats[DPR1_STAT_KB_GT_100], __popcll(bal));
+      if (bext) atomicAdd(&A.stats[DPR1_STAT_EXT_B], __popcll(bext));
       atomicMax(&A.stats[DPR1_STAT_ITERS_MAX], imax);
       atomicAdd(&A.stats[DPR1_STAT_ITERS_SUM], isum);
     }
@@ -2070,7 +2093,7 @@ static constexpr Layout layout(int64_t nprob, int64_t N, int64_t nitems, int64_t
   L.vflag = o; o = al(o + N);
   L.items = o; o = al(o + sizeof(int2) * nitems);
   L.groups = o; o = al(o + sizeof(int4) * ngroups);
-  L.part = o; o = al(o + sizeof(double2) * PREP_MAX_SPLIT);
+  L.part = o; o = al(o + 3 * sizeof(double) * PREP_MAX_SPLIT);
   L.ctr = o; o = al(o + 64);
   L.total = o;
   return L;
@@ -2284,7 +2307,7 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
   const int nsplit = nprob == 1 ? (int)std::min<int64_t>(PREP_MAX_SPLIT, std::max<int64_t>(1, N / 512)) : 1;
   hipLaunchKernelGGL(k_prep, dim3((unsigned)(nsplit > 1 ? nsplit : nprob)), dim3(256), 0, st, (int)nprob, nsplit,
                      offs, n_single, d, z, rho_dev, rho_host, meta, (double*)A.sd, (double*)A.sz,
-                     (double*)A.pairs, (double*)A.z2lo, info, (double2*)(w + L.part), A.ctr + 8);
+                     (double*)A.pairs, (double*)A.z2lo, info, (double*)(w + L.part), A.ctr + 8);
   HIPCHECK(hipGetLastError());
   hipEvent_t* ev = (hipEvent_t*)o.events;
   double* csig = (double*)(w + L.csig);
@@ -2461,7 +2484,8 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
   if (work_bytes < L.total) return -15;
   dpr1_opts o;
   fill_opts(opts, &o);
-  if (!occ_valid(o.waves_per_simd) || o.vwrite < 0 || o.vwrite > VEC_CHUNKS_MAX) return -13;
+  if (!occ_valid(o.waves_per_simd) || o.vwrite < 0 || o.vwrite > VEC_CHUNKS_MAX || o.mode_b < 0 || o.mode_b > 3)
+    return -13;
   int64_t nblocks = (n + WAVE - 1) / WAVE;
   int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
   return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
@@ -2485,7 +2509,8 @@ int dpr1_eig_noalloc(const double* d, const double* z, double rho, int64_t n, do
   if (!info) return -11;
   dpr1_opts o;
   fill_opts(opts, &o);
-  if (!occ_valid(o.waves_per_simd) || o.vwrite < 0 || o.vwrite > VEC_CHUNKS_MAX) return -13;
+  if (!occ_valid(o.waves_per_simd) || o.vwrite < 0 || o.vwrite > VEC_CHUNKS_MAX || o.mode_b < 0 || o.mode_b > 3)
+    return -13;
   void* work = scratch_on_current_device();
   if (!work) return DPR1_EHIP;
   const Layout L = layout(1, n, 0);
@@ -2525,7 +2550,7 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
   if (work_bytes < L0.total) return -6;
   dpr1_opts o;
   fill_opts(opts, &o);
-  if (!occ_valid(o.waves_per_simd)) return -3;
+  if (!occ_valid(o.waves_per_simd) || o.mode_b < 0 || o.mode_b > 3) return -3;
   // longest-processing-time order: larger problems first
   std::vector<int32_t> order(nprob);
   for (int64_t p = 0; p < nprob; ++p) order[p] = (int32_t)p;

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(HERE, "libdpr1.so")
 INFO_TEXT = {0: "ok", 1: "d is not strictly decreasing", 2: "some z_j is zero (reducible)",
              3: "non-finite input", 4: "rho is zero or not finite",
              5: "a shifted representation left the binary64 range"}
-NSTATS = 11
+NSTATS = 12
 STAT_NAMES = ["kb_gt_100", "polished", "nearzero", "singular", "iters_max", "iters_sum", "continued",
-              "polish_steps_max", "knu_gt", "remedy_r1", "remedy_r2"]
+              "polish_steps_max", "knu_gt", "remedy_r1", "remedy_r2", "ext_b"]
 
 
 class Opts(C.Structure):

@@ -88,6 +88,13 @@ def test_invalid_register_budget_is_rejected_before_launch(lib):
     offs = (ctypes.c_int64 * 3)(0, 5, 9)
     plan = Plan()
     assert lib.dpr1_batched_plan(2, offs, ctypes.byref(o), ctypes.byref(plan), fake, 1 << 24, None) == -3
+    # opts.mode_b: 0 .. 3, anything else is argument 13 (dpr1_eig) / 3 (dpr1_batched_plan)
+    for bad in (-1, 4):
+        o.mode_b = bad
+        assert lib.dpr1_eig(fake, fake, 1.0, 8, fake, None, 8, None, None, None, fake, None, ctypes.byref(o),
+                            fake, 1 << 20, None) == -13
+        assert lib.dpr1_batched_plan(2, offs, ctypes.byref(o), ctypes.byref(plan), fake, 1 << 24, None) == -3
+    o.mode_b = 0
     # opts.vwrite: 0 .. 8 (chunks of the overlapped write), anything else is argument 13 as well
     o.waves_per_simd = 0
     for bad in (-1, 9):

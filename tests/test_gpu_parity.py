@@ -110,6 +110,49 @@ def test_example4_kb_counts(D, orc):
         assert r.stats_dict()["kb_gt_100"] == count
 
 
+def test_knu2_gate(D, orc):
+    """Algorithm 1's gate on the bound of eq. (knu2) (mode_b = 3): Example 4's printed counts of
+    double-precision tips (25, 201, 201), Example 3's k = 2, 3, 4, and Example 1's none, each with
+    parity against the oracle under the same gate.  On the C2-like graded matrix the gate leaves b
+    in standard precision for eigenvalues whose result is sensitive to it, where the two sides'
+    binary64 tips (summed in different orders) legitimately differ beyond the parity bar (the
+    reason the default forms b in double-double always): there the GPU takes the oracle's
+    decisions eigenvalue by eigenvalue, the count of double-precision tips among them."""
+    cases = [(W.example4(b), c, f"ex4 beta={b}") for b, c in [(1e-3, 25), (1e-8, 201), (1e-15, 201)]]
+    cases += [(W.example3(), 3, "ex3"), (W.example1(), 0, "ex1")]
+    for (d, z, rho), count, tag in cases:
+        r, *_ = compare(D, orc, d, z, rho, opts=D.opts(mode_b=3), oopts=orc.make_opts(mode_b=3), tag=tag + " knu2")
+        assert r.stats_dict()["ext_b"] == count, (tag, r.stats_dict())
+    d, z, rho = W.graded(1024, 2, pair_every=64)
+    r = D.eig(d, z, rho, opts=D.opts(mode_b=3), want_stats=True)
+    _, _, dg = orc.eig(d, z, rho, opts=orc.make_opts(mode_b=3), diags=True)
+    n_orc = sum(x["used_ext_b"] for x in dg)
+    print(f"[parity] graded1024 knu2: double-precision tips GPU {r.stats_dict()['ext_b']}, oracle {n_orc}",
+          flush=True)
+    assert r.stats_dict()["ext_b"] == n_orc
+
+
+def test_example4_orthogonality_without_extended_b(D):
+    """Table 1's pattern on the GPU: with the tip b in standard precision only (mode_b = 2, the
+    paper's dpr1eig_nd) the eigenvectors of Example 4 lose orthogonality as beta falls (O of
+    order 1e4 at beta = 1e-8 and beyond 1e6 at 1e-15), while b in double-double keeps O < 1."""
+    import torch
+    for beta, lo_nd in [(1e-3, None), (1e-8, 1e2), (1e-15, 1e6)]:
+        d, z, rho = W.example4(beta)
+        n = d.size
+        out = {}
+        for mb in (0, 2):
+            r = D.eig(d, z, rho, opts=D.opts(mode_b=mb, polish=0 if mb == 2 else 1))
+            torch.cuda.synchronize()
+            V = r.V.cpu().numpy()
+            G = V.T @ V - np.eye(n)
+            out[mb] = np.max(np.linalg.norm(G, axis=0)) / (n * np.finfo(float).eps)
+        print(f"[parity] Table 1 beta={beta}: O(nd) {out[2]:.3g}, O(dd) {out[0]:.3g}", flush=True)
+        assert out[0] < 1.0
+        if lo_nd is not None:
+            assert out[2] > lo_nd
+
+
 def test_near_zero_and_singular(D, orc):
     d = np.array([2.0, 1.0, -1.0, -2.0])
     z = np.array([0.7, -1.1, 0.9, 0.0])

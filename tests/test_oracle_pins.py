@@ -100,6 +100,36 @@ def test_example4_extended_b_count(orc, beta, count):
     assert sum(x["used_ext_b"] for x in dg) == count
 
 
+@pytest.mark.parametrize("beta,count", [(1e-3, 25), (1e-8, 201), (1e-15, 201)])
+def test_example4_knu2_gate_count(orc, beta, count):
+    """Algorithm 1's gate on the bound of eq. (knu2) (mode_b = 3) gives the printed counts of
+    Example 4 as well: the eigenvalue shifted to the pole 10/3 (zeta = 2, K_z about 1) never
+    needs double the working precision, the others exactly when K_b exceeds 100."""
+    g = load("example4.txt")
+    table = {float(r[0]): int(r[1]) for r in g["count"]}
+    assert table[beta] == count
+    d, z, rho = W.example4(beta)
+    lam, V, dg = orc.eig(d, z, rho, opts=orc.make_opts(mode_b=3), diags=True)
+    assert sum(x["used_ext_b"] for x in dg) == count
+    n = d.size
+    for x in dg:
+        # the decision is the bound of eq. (knu2) with the standard-precision K_b
+        if x["used_ext_b"]:
+            assert x["Kz"] > 1.0
+
+
+def test_example3_and_example1_knu2_gate(orc):
+    """Example 3: kappa_nu of eq. (knu2) is of order 1e7 for k = 2, 3, 4, which need b in double
+    the working precision, and small for k = 1; Example 1: K_b is about 1 for every eigenvalue,
+    standard precision suffices throughout (mode_b = 3)."""
+    d, z, rho = W.example3()
+    _, _, dg = orc.eig(d, z, rho, opts=orc.make_opts(mode_b=3), diags=True)
+    assert [x["used_ext_b"] for x in dg] == [0, 1, 1, 1]
+    d, z, rho = W.example1()
+    _, _, dg = orc.eig(d, z, rho, opts=orc.make_opts(mode_b=3), diags=True)
+    assert not any(x["used_ext_b"] for x in dg)
+
+
 def test_example4_orthogonality_needs_extended_b(orc):
     """Table 1: without double precision b (dpr1eig_nd) orthogonality is lost for
     beta = 1e-15 (O ~ 1e11) while dpr1eig keeps O < 1."""
