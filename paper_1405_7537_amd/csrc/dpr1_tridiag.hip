@@ -454,7 +454,9 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
   std::vector<fe::Col> all;
   std::vector<int64_t> roff, rcnt;  // per merge: offset and size of its reduced problem
   std::vector<std::vector<fe::Col>> mcols;
-  std::vector<double> hnew(n), hpole(n);
+  std::vector<double> hnew(n), hpole(n), gval(n);
+  std::vector<char> seen(n);
+  fe::Scratch scr;
   dpr1_plan plan;
   // host mirrors of contiguous workspace regions, so that each region moves
   // in one copy per depth: the solver's inputs [rd, offsp], its outputs
@@ -527,11 +529,12 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
       // a coupling |beta| <= 8 eps max|d| decouples the halves (the matrix
       // changes by less than the children's accuracy)
       const bool decoupled = std::fabs(beta) <= ptol;
+      // the children's eigenvalues are each decreasing: their order is one merge
       fe::reduce(hlam.data() + nd.start, hz.data() + nd.start, nd.size, decoupled, rd, rz,
-                 hgrp.data() + nd.start, hpos.data() + nd.start, hru.data() + nd.start, mcols[p], ptol);
+                 hgrp.data() + nd.start, hpos.data() + nd.start, hru.data() + nd.start, mcols[p], ptol, nd.m,
+                 &scr);
       {
-        std::vector<double> gval(nd.size, 0.0);
-        std::vector<char> seen(nd.size, 0);
+        std::fill(seen.begin(), seen.begin() + nd.size, 0);
         for (int64_t i = 0; i < nd.size; ++i) {
           const int g = hgrp[nd.start + i];
           if (!seen[g] || hlam[nd.start + i] > gval[g]) gval[g] = hlam[nd.start + i];
@@ -599,7 +602,7 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     for (size_t p = 0; p < lv.size(); ++p) {
       const Node& nd = *lv[p];
       const int64_t o = nd.start, s = nd.size;
-      fe::merge_cols(mcols[p], lamr.data() + roff[p], rcnt[p], all);
+      fe::merge_cols(mcols[p], lamr.data() + roff[p], rcnt[p], all, &scr);
       for (int64_t c = 0; c < s; ++c) {
         const fe::Col& q = all[c];
         hnew[o + c] = q.val;

@@ -80,18 +80,43 @@ inline void sort_decreasing(const double* d, int64_t n, std::vector<int64_t>& or
   }
 }
 
+// The same order when d[0 .. m) and d[m .. n) are each non-increasing (the
+// children's eigenvalues in a divide-and-conquer merge): one stable merge,
+// the first run first among equal values, as the stable sort orders them.
+inline void merge_decreasing(const double* d, int64_t n, int64_t m, std::vector<int64_t>& order) {
+  order.resize(n);
+  int64_t a = 0, b = m, s = 0;
+  while (a < m && b < n) order[s++] = (d[b] > d[a]) ? b++ : a++;
+  while (a < m) order[s++] = a++;
+  while (b < n) order[s++] = b++;
+}
+
+// Work buffers of reduce and merge_cols, kept by a caller that reduces many
+// problems so that they are allocated once.
+struct Scratch {
+  std::vector<int64_t> order;
+  std::vector<double> u;
+  std::vector<Col> red;
+};
+
 // Reduce one problem (host d, z of length n; zero_all treats every z_j as 0;
-// poles within tol of a group's largest are merged into that group).
+// poles within tol of a group's largest are merged into that group; runs >= 0:
+// d[0 .. runs) and d[runs .. n) are each non-increasing).
 // Appends the reduced poles and z to rd, rz (decreasing poles, no zero z);
 // writes per row i: rgrp[i] group id (local), rpos[i] position in the group,
 // ru[i] reflection component (0 for groups without one); appends the
 // deflated and reflected columns to cols in decreasing pole order.
 inline void reduce(const double* hd, const double* hz, int64_t n, bool zero_all, std::vector<double>& rd,
                    std::vector<double>& rz, int32_t* rgrp, int32_t* rpos, double* ru, std::vector<Col>& cols,
-                   double tol = 0.0) {
-  std::vector<int64_t> order;
-  sort_decreasing(hd, n, order);
-  std::vector<double> u;
+                   double tol = 0.0, int64_t runs = -1, Scratch* scratch = nullptr) {
+  Scratch local;
+  Scratch& sc = scratch ? *scratch : local;
+  std::vector<int64_t>& order = sc.order;
+  if (runs >= 0)
+    merge_decreasing(hd, n, runs, order);
+  else
+    sort_decreasing(hd, n, order);
+  std::vector<double>& u = sc.u;
   int32_t ngrp = 0;
   for (int64_t s = 0; s < n;) {
     int64_t e = s + 1;
@@ -142,8 +167,11 @@ inline void reduce(const double* hd, const double* hz, int64_t n, bool zero_all,
 // Both lists are decreasing: merge the deflated/reflected columns with the
 // reduced eigenvalues lamr[0..m) (deflated and reflected first among equal
 // values).
-inline void merge_cols(const std::vector<Col>& cols, const double* lamr, int64_t m, std::vector<Col>& out) {
-  std::vector<Col> red(m);
+inline void merge_cols(const std::vector<Col>& cols, const double* lamr, int64_t m, std::vector<Col>& out,
+                       Scratch* scratch = nullptr) {
+  Scratch local;
+  std::vector<Col>& red = (scratch ? *scratch : local).red;
+  red.resize(m);
   for (int64_t k = 0; k < m; ++k) red[k] = {lamr[k], COL_REDUCED, (int32_t)k, 0, 0.0};
   out.resize(cols.size() + m);
   std::merge(cols.begin(), cols.end(), red.begin(), red.end(), out.begin(),
