@@ -110,6 +110,27 @@ def test_example4_kb_counts(D, orc):
         assert r.stats_dict()["kb_gt_100"] == count
 
 
+@pytest.mark.parametrize("n,ldv,rho", [(2001, 2002, -0.8), (2048, 2050, 1.3), (1537, 1538, 0.6)])
+def test_address_ordered_writer_edges(D, orc, n, ldv, rho):
+    """The address-ordered eigenvector writer (columns 16-byte aligned: even ldv) with an odd n
+    (the last position of every column stored alone), a padded leading dimension and rho < 0
+    (positions and columns reversed): every eigenpair against the oracle, the padding untouched."""
+    import torch
+    d, z, _ = W.uniform(n, 41)
+    Vt = torch.full((n, ldv), 7.0, dtype=torch.float64, device="cuda")
+    out = (torch.empty(n, dtype=torch.float64, device="cuda"), Vt[:, :n],
+           torch.empty(n, dtype=torch.int32, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"),
+           torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.int32, device="cuda"))
+    print(f"[parity] writer edges n={n} ldv={ldv} rho={rho}", flush=True)
+    r = D.eig(d, z, rho, opts=D.opts(vwrite=1), out=out)
+    torch.cuda.synchronize()
+    assert int(r.info.item()) == 0
+    lo, Vo = orc.eig(d, z, rho)
+    assert rel(r.lam.cpu().numpy(), lo).max() <= LAM_TOL
+    assert rel(r.V.cpu().numpy(), Vo).max() <= VEC_TOL
+    assert torch.all(Vt[:, n:] == 7.0)
+
+
 def test_knu2_gate(D, orc):
     """Algorithm 1's gate on the bound of eq. (knu2) (mode_b = 3): Example 4's printed counts of
     double-precision tips (25, 201, 201), Example 3's k = 2, 3, 4, and Example 1's none, each with
