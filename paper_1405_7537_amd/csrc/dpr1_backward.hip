@@ -96,8 +96,11 @@ __device__ __forceinline__ double v_elem(const GArgs& g, int64_t vo, int64_t j, 
 // problem run on one XCD and share its L2.
 // RV: V is not passed in; its elements are rebuilt by v_elem (a separate
 // instance, so that the path with V keeps its plain loads).
+// Two blocks per CU (66.5 KB of LDS each) are 4 waves per SIMD, which leaves
+// 128 VGPRs a lane: the bound asks for that budget (the instance that rebuilds
+// V^T spills a few registers to stay in it, still faster than one block per CU).
 template <int EPI, bool RV>
-__global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
+__global__ void __launch_bounds__(NT, 4) k_gemm(GArgs g) {
   const int64_t n = g.n;
   const int tiles = (int)((n + BM - 1) / BM);
   const int T = tiles * tiles;
@@ -133,31 +136,29 @@ __global__ void __launch_bounds__(NT, 2) k_gemm(GArgs g) {
     for (int b = 0; b < NBT; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
   constexpr int PER = (BM * BK) / NT;  // elements of each operand per thread
+  static_assert(BM == BN && NT % BM == 0 && NT % BK == 0, "tile shape");
+  // Element e2 of a thread: EPI_X: k = ek, m (or c) = em + STEP e2; EPI_D: m (or
+  // c) = em, k = ek + STEP e2.  The per-thread part of each address is formed
+  // once; what changes with k0 and e2 is uniform across the block.
+  constexpr int STEP = EPI == EPI_X ? NT / BK : NT / BM;
+  const int ek = EPI == EPI_X ? tid % BK : tid / BM;
+  const int em = EPI == EPI_X ? tid / BK : tid % BM;
+  const double* pA = RV ? nullptr : (EPI == EPI_X ? A + ek + (m0 + em) * lda : A + (m0 + em) + ek * lda);
+  const double* pB = EPI == EPI_X ? Bm + ek + (n0 + em) * ldb : Bm + (int64_t)ek * n + (n0 + em);
   double ra[PER], rb[PER];
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int e2 = 0; e2 < PER; ++e2) {
-      int e = tid + e2 * NT;
-      int m, kk;
       if (EPI == EPI_X) {
-        kk = e % BK;   // A^T(m, k) = V[k + m lda], contiguous along k
-        m = e / BK;
-        int64_t gm = m0 + m, gk = k0 + kk;
-        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gk, gm) : A[gk + gm * lda]) : 0.0;
+        // A^T(m, k) = V[k + m lda] and V_bar(k, c) = V_bar[k + c ldb], contiguous along k
+        const int64_t gk = k0 + ek, gm = m0 + em + STEP * e2, gc = n0 + em + STEP * e2;
+        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gk, gm) : pA[k0 + STEP * e2 * lda]) : 0.0;
+        rb[e2] = (gk < n && gc < n) ? pB[k0 + STEP * e2 * ldb] : 0.0;
       } else {
-        m = e % BM;    // A(m, k) = V[m + k lda], contiguous along m
-        kk = e / BM;
-        int64_t gm = m0 + m, gk = k0 + kk;
-        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gm, gk) : A[gm + gk * lda]) : 0.0;
-      }
-      if (EPI == EPI_X) {
-        int kb = e % BK, c = e / BK;  // V_bar(k, c) = V_bar[k + c ldb], contiguous along k
-        int64_t gk = k0 + kb, gc = n0 + c;
-        rb[e2] = (gk < n && gc < n) ? Bm[gk + gc * ldb] : 0.0;
-      } else {
-        int c = e % BN, kb = e / BN;  // X(k, c) = X[k n + c] (row-major), contiguous along c
-        int64_t gk = k0 + kb, gc = n0 + c;
-        rb[e2] = (gk < n && gc < n) ? Bm[gk * n + gc] : 0.0;
+        // A(m, k) = V[m + k lda], contiguous along m; X(k, c) = X[k n + c] (row-major), contiguous along c
+        const int64_t gk = k0 + ek + STEP * e2, gm = m0 + em, gc = n0 + em;
+        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gm, gk) : pA[(k0 + STEP * e2) * lda]) : 0.0;
+        rb[e2] = (gk < n && gc < n) ? pB[(k0 + STEP * e2) * n] : 0.0;
       }
     }
   };
