@@ -200,7 +200,9 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // 16x16x4 instruction: A(row = lane % 16, k = lane / 16), B(k = lane / 16,
 // col = lane % 16); accumulator element q of a lane is row lane / 16 + 4 q,
 // column lane % 16 of its block.
-__global__ void __launch_bounds__(GNT, 2) k_dgemm(const GDesc* __restrict__ desc, const int4* __restrict__ tiles) {
+// Two blocks per CU (66.5 KB of LDS each) are 4 waves per SIMD: the bound keeps
+// the kernel within the 128 VGPRs a lane that this leaves.
+__global__ void __launch_bounds__(GNT, 4) k_dgemm(const GDesc* __restrict__ desc, const int4* __restrict__ tiles) {
   __shared__ double As[2][GKS][GT + GPAD];
   __shared__ double Bs[2][GKS][GT + GPAD];
   const int4 t = tiles[blockIdx.x];
@@ -215,19 +217,23 @@ __global__ void __launch_bounds__(GNT, 2) k_dgemm(const GDesc* __restrict__ desc
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
   constexpr int PER = GT * GKS / GNT;  // 4 elements of each operand per thread
+  static_assert(GNT % GT == 0 && GNT % GKS == 0, "tile shape");
+  // Element e2 of a thread: A(m, k) with m = tid % GT, k = tid / GT + (GNT / GT) e2
+  // (consecutive threads along m); B(k, c) with k = tid % GKS, c = tid / GKS +
+  // (GNT / GKS) e2 (consecutive threads along k).  The per-thread part of each
+  // address is formed once; what changes with k0 and e2 is uniform.
+  const int ma = tid % GT, ka = tid / GT, kb = tid % GKS, cb = tid / GKS;
+  const double* pA = g.A + (r0 + ma) + (int64_t)ka * g.lda;
+  const double* pB = g.B + kb + (int64_t)(c0 + cb) * g.ldb;
+  const bool rowA = r0 + ma < g.M;
   double ra[PER], rb[PER];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int e2 = 0; e2 < PER; ++e2) {
-      const int e = tid + e2 * GNT;
-      // A(m, k) = A[m + k lda]: consecutive threads along m
-      const int m = e % GT, ka = e / GT;
-      const int gr = r0 + m, gka = k0 + ka;
-      ra[e2] = (gr < g.M && gka < g.K) ? g.A[gr + (int64_t)gka * g.lda] : 0.0;
-      // B(k, c) = B[k + c ldb]: consecutive threads along k
-      const int kb = e % GKS, c = e / GKS;
-      const int gkb = k0 + kb, gc = c0 + c;
-      rb[e2] = (gkb < g.K && gc < g.N) ? g.B[gkb + (int64_t)gc * g.ldb] : 0.0;
+      const int gka = k0 + ka + (GNT / GT) * e2;
+      ra[e2] = (rowA && gka < g.K) ? pA[(int64_t)(k0 + (GNT / GT) * e2) * g.lda] : 0.0;
+      const int gkb = k0 + kb, gc = c0 + cb + (GNT / GKS) * e2;
+      rb[e2] = (gkb < g.K && gc < g.N) ? pB[k0 + (int64_t)((GNT / GKS) * e2) * g.ldb] : 0.0;
     }
   };
   auto sstore = [&](int buf) {
