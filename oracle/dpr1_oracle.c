@@ -37,7 +37,7 @@
  *    g at the root.  When kappa_g * max(1,|mu/lambda|) exceeds a threshold
  *    (16), the result is polished by safeguarded Newton steps with g
  *    evaluated in binary128: the paper's remedy (R2) in its last form, which
- *    falls back to double the working precision.  This also covers k = 1,
+ *    falls back to twice the working precision.  This also covers k = 1,
  *    where (R1) is impossible (there is no pole on the other side).
  *  - The near-zero rule (Alg. 1, last test) fires when
  *    10*|lambda| < min |lambda - neighbouring pole|.
@@ -609,8 +609,8 @@ static double vector_from(const double* d, const double* z, int64_t n, int64_t i
  * eigenvalue of A - sigma I closest to zero.  Its inverse is the DPR1 matrix
  * E + gamma u u^T with e_j = 1/(d_j - sigma), u_j = zeta_j e_j,
  * gamma = -rho/f(sigma), f(sigma) = 1 + rho sum zeta_j^2/(d_j - sigma) (the
- * same form as eq. gamma, shifted), everything in binary128 ("the DPR1 matrix
- * must be computed in double the working precision").  eta = 1/(lambda -
+ * same form as eq. gamma, shifted), everything in binary128 (remedy (R2)
+ * forms this matrix in extended precision).  eta = 1/(lambda -
  * sigma) is its exterior eigenvalue: the root of h(eta) = 1 + gamma sum
  * u_j^2/(e_j - eta) right of every e_j when mu > 0 (then f(sigma) < 0), left of
  * every e_j when mu < 0.  Returns mu_new = lambda - d_i = (sigma - d_i) + 1/eta,

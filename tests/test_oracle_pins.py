@@ -104,7 +104,7 @@ def test_example4_extended_b_count(orc, beta, count):
 def test_example4_knu2_gate_count(orc, beta, count):
     """Algorithm 1's gate on the bound of eq. (knu2) (mode_b = 3) gives the printed counts of
     Example 4 as well: the eigenvalue shifted to the pole 10/3 (zeta = 2, K_z about 1) never
-    needs double the working precision, the others exactly when K_b exceeds 100."""
+    needs twice the working precision, the others exactly when K_b exceeds 100."""
     g = load("example4.txt")
     table = {float(r[0]): int(r[1]) for r in g["count"]}
     assert table[beta] == count
