@@ -376,7 +376,10 @@ int dpr1_eig_hermitian(const double* d, const double* z, double rho, int64_t n, 
  *   work, work_bytes  >= dpr1_tridiag_workspace_size(n): about 16 n^2 bytes
  *           (a second Q buffer and the merges' V) plus O(n)
  * 1 <= n <= 65536.  Synchronises the host with `stream` a few times per
- * depth of the split tree (the merges are reduced on the host).  Returns 0,
+ * depth of the split tree (the merges are reduced on the host); the merges'
+ * DPR1 solves run on a second stream of the library (created once per
+ * device, default priority) beside the products on `stream`, and the call
+ * returns when the work on both has finished.  Returns 0,
  * -p for an invalid argument p (-10 also when the workspace is too small),
  * or DPR1_EHIP.                                                             */
 size_t dpr1_tridiag_workspace_size(int64_t n);

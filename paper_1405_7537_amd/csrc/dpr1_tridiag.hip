@@ -10,7 +10,10 @@
 //   z = Q^T u = [last row of Q1, first row of Q2],
 // and its eigenvectors are Q V for the DPR1 eigenvectors V.  The split tree
 // goes down to 1 x 1 leaves; all merges of one depth are done together:
-//   1. k_gather_z reads z of every merge from the current Q buffer;
+//   1. z of every merge: a 1 x 1 child gives 1; the row of a larger child's Q
+//      was formed by k_zrows when that child was merged, straight from its
+//      children's Q and its V, so it is on the host before that child's
+//      product (step 5) has finished;
 //   2. the host reduces each merge as in Sec. 1 (unsorted poles, equal poles,
 //      zero z_j: reduce.h), a z_j below 2^-300 max|z| counting as zero and
 //      poles within 8 eps max|d| merged like equal ones;
@@ -25,12 +28,17 @@
 // lands in the caller's Q.  A block is written only by its own merge and read
 // only by its parent's, and a leaf's 1 x 1 block (= 1) is set in both buffers
 // at the start, so no buffer is ever cleared.
+// Steps 2 and 3 of a depth overlap the product of the depth below: the
+// host work runs while that product occupies the caller's stream, and the
+// DPR1 solves go to a second stream of the library (nothing they read or
+// write is touched by the assembly or the products).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/dpr1.h"
@@ -46,15 +54,16 @@ using fe::COL_UNIT;
 struct Node {
   int64_t start, size, m;
   int depth;
+  int side;  // 0 the root, 1 the left child of its parent, 2 the right child
 };
 
-static void build_tree(int64_t start, int64_t size, int depth, std::vector<Node>& out, int& maxd) {
+static void build_tree(int64_t start, int64_t size, int depth, std::vector<Node>& out, int& maxd, int side = 0) {
   if (size < 2) return;
   const int64_t m = size / 2;
-  out.push_back({start, size, m, depth});
+  out.push_back({start, size, m, depth, side});
   maxd = std::max(maxd, depth);
-  build_tree(start, m, depth + 1, out, maxd);
-  build_tree(start + m, size - m, depth + 1, out, maxd);
+  build_tree(start, m, depth + 1, out, maxd, 1);
+  build_tree(start + m, size - m, depth + 1, out, maxd, 2);
 }
 
 // The diagonal of every leaf after the splits above it: each split subtracts
@@ -76,14 +85,55 @@ __global__ void k_diag_one(double* Q, int64_t ld, int64_t n) {
   if (i < n) Q[i + i * ld] = 1.0;
 }
 
-// z_i = Q[src_i, i] (the last row of the left child's block or the first row
-// of the right child's), 0 for a row not merged at this depth.
-__global__ void k_gather_z(const double* __restrict__ Q, int64_t ld, const int32_t* __restrict__ src, int64_t n,
-                           double* __restrict__ z) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int r = src[i];
-  z[i] = r >= 0 ? Q[r + i * ld] : 0.0;
+// The row of a merged block's Q that its parent's z takes (the last row for a
+// left child, the first for a right one), formed from the same operands as
+// the block's product: row r of diag(Q1, Q2) V is row r of the child block
+// that holds r times that block's rows of V.  One item is up to ZC columns of
+// one merge; the row segment is staged in LDS in chunks of ZCH, and wave w
+// takes columns w, w + 4, ... with its lanes along the segment.
+struct ZItem {
+  int64_t q;    // Q-buffer offset of the segment's first element: r + kbeg ldq
+  int64_t v;    // offset in the merges' V of element (kbeg - start, c0) of this merge's V
+  int32_t len;  // segment length (rows of the child block holding r)
+  int32_t ldv;  // leading dimension of this merge's V (its size)
+  int32_t z0;   // output index of column c0 (start + c0)
+  int32_t nc;   // columns of the item, <= ZC
+};
+constexpr int ZC = 16, ZT = 256, ZCH = 2048;
+
+__global__ void __launch_bounds__(ZT) k_zrows(const ZItem* __restrict__ items, const double* __restrict__ Q,
+                                              int64_t ldq, const double* __restrict__ V, double* __restrict__ z) {
+  __shared__ double row[ZCH];
+  const ZItem it = items[blockIdx.x];
+  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  constexpr int PW = ZC / (ZT / 64);  // columns per wave
+  double acc[PW];
+#pragma unroll
+  for (int c = 0; c < PW; ++c) acc[c] = 0.0;
+  for (int k0 = 0; k0 < it.len; k0 += ZCH) {
+    const int kn = min(ZCH, it.len - k0);
+    __syncthreads();  // the previous chunk is consumed
+    for (int k = threadIdx.x; k < kn; k += ZT) row[k] = Q[it.q + (int64_t)(k0 + k) * ldq];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < PW; ++c) {
+      const int col = wv + (ZT / 64) * c;
+      if (col < it.nc) {
+        const double* vc = V + it.v + (int64_t)col * it.ldv + k0;
+        double a = acc[c];
+        for (int k = lane; k < kn; k += 64) a = __builtin_fma(row[k], vc[k], a);
+        acc[c] = a;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < PW; ++c) {
+    double a = acc[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    const int col = wv + (ZT / 64) * c;
+    if (lane == 0 && col < it.nc) z[it.z0 + col] = a;
+  }
 }
 
 struct ANode {
@@ -289,9 +339,9 @@ static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct TLayout {
-  size_t Qw, Vw, zl, dl, src, rd, rz, lamr, mur, xnr, sidx, infop, rhop, offsp, rgrp, rpos, ru, ckind, cidx, ct,
-      csig, cmu, cic, cub, anodes, atab, gdesc, gtab, solver, total;
-  int64_t maxV, maxAsm, maxTiles, maxNodes;
+  size_t Qw, Vw, zl, dl, rd, rz, lamr, mur, xnr, sidx, infop, rhop, offsp, rgrp, rpos, ru, ckind, cidx, ct,
+      csig, cmu, cic, cub, anodes, atab, gdesc, gtab, zit, solver, total;
+  int64_t maxV, maxAsm, maxTiles, maxNodes, maxZ;
   size_t solver_bytes;
 };
 
@@ -301,10 +351,11 @@ static TLayout tlayout(int64_t n, const std::vector<Node>& nodes, int maxd) {
   L.maxAsm = 0;
   L.maxTiles = 0;
   L.maxNodes = 0;
+  L.maxZ = 0;
   L.solver_bytes = 0;
   std::vector<int64_t> offs;
   for (int D = maxd; D >= 0; --D) {
-    int64_t v = 0, as = 0, ti = 0, cnt = 0;
+    int64_t v = 0, as = 0, ti = 0, cnt = 0, zi = 0;
     offs.assign(1, 0);
     for (const Node& nd : nodes) {
       if (nd.depth != D) continue;
@@ -312,6 +363,7 @@ static TLayout tlayout(int64_t n, const std::vector<Node>& nodes, int maxd) {
       v += nd.size * nd.size;
       as += cdiv(nd.size, TA_CB) * cdiv(nd.size, TA_T * TA_R);
       ti += (cdiv(nd.m, GT) + cdiv(nd.size - nd.m, GT)) * cdiv(nd.size, GT);
+      if (nd.side) zi += cdiv(nd.size, ZC);
       offs.push_back(offs.back() + nd.size);
     }
     if (!cnt) continue;
@@ -319,6 +371,7 @@ static TLayout tlayout(int64_t n, const std::vector<Node>& nodes, int maxd) {
     L.maxAsm = std::max(L.maxAsm, as);
     L.maxTiles = std::max(L.maxTiles, ti);
     L.maxNodes = std::max(L.maxNodes, cnt);
+    L.maxZ = std::max(L.maxZ, zi);
     // the reduced problems of a depth are no more and no larger than its merges
     L.solver_bytes = std::max(L.solver_bytes, dpr1_batched_workspace_size(cnt, offs.data()));
   }
@@ -328,7 +381,6 @@ static TLayout tlayout(int64_t n, const std::vector<Node>& nodes, int maxd) {
   L.Vw = o; o = al(o + 8 * (size_t)L.maxV);
   L.zl = o; o = al(o + 8 * n);
   L.dl = o; o = al(o + 8 * n);
-  L.src = o; o = al(o + 4 * n);
   L.rd = o; o = al(o + 8 * n);
   L.rz = o; o = al(o + 8 * n);
   L.lamr = o; o = al(o + 8 * n);
@@ -352,6 +404,7 @@ static TLayout tlayout(int64_t n, const std::vector<Node>& nodes, int maxd) {
   L.atab = o; o = al(o + sizeof(int4) * std::max<int64_t>(L.maxAsm, 1));
   L.gdesc = o; o = al(o + sizeof(GDesc) * 2 * P);
   L.gtab = o; o = al(o + sizeof(int4) * std::max<int64_t>(L.maxTiles, 1));
+  L.zit = o; o = al(o + sizeof(ZItem) * std::max<int64_t>(L.maxZ, 1));
   L.solver = o; o = al(o + L.solver_bytes);
   L.total = o;
   return L;
@@ -368,16 +421,41 @@ namespace fe = dpr1::fe;
     if ((x) != hipSuccess) return DPR1_EHIP; \
   } while (0)
 
-template <typename T>
-static hipError_t h2d(void* dst, const std::vector<T>& src, size_t count, hipStream_t st) {
-  return count ? hipMemcpyAsync(dst, src.data(), sizeof(T) * count, hipMemcpyHostToDevice, st) : hipSuccess;
-}
-
 static int tri_set_info(int32_t* info, int32_t code, hipStream_t st) {
   TCHECK(hipMemcpyAsync(info, &code, 4, hipMemcpyHostToDevice, st));
   TCHECK(hipStreamSynchronize(st));
   return DPR1_OK;
 }
+
+// Second stream of the current device for the merges' DPR1 solves: created
+// once per device (default priority, non-blocking) and kept until the
+// process ends; nullptr if it cannot be created.
+constexpr int TRI_MAX_DEVICES = 64;
+static std::mutex tri_mutex;
+static hipStream_t tri_streams[TRI_MAX_DEVICES];
+static hipStream_t tri_aux_stream() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= TRI_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(tri_mutex);
+  if (!tri_streams[dev]) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    tri_streams[dev] = s;
+  }
+  return tri_streams[dev];
+}
+
+// On every return: wait for both streams (the host buffers that their copies
+// use are freed after this) and release the event.
+struct TriDone {
+  hipStream_t st, st2;
+  hipEvent_t ev = nullptr;
+  ~TriDone() {
+    (void)hipStreamSynchronize(st2);
+    (void)hipStreamSynchronize(st);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
 
 extern "C" {
 
@@ -431,7 +509,6 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
 
   double* zl = (double*)(w + L.zl);
   double* dl = (double*)(w + L.dl);
-  int32_t* src = (int32_t*)(w + L.src);
   TArgs ta;
   ta.d = dl;
   ta.z = zl;
@@ -449,8 +526,9 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
 
   // host staging, reused by every depth (each is rewritten only after the
   // stream has been synchronised at the start of the next depth)
-  std::vector<int32_t> hsrc(n), hgrp(n, 0), hpos(n, 0), hkind(n, 0), hidx(n, 0), hct(n, 0);
-  std::vector<double> hz(n), hru(n, 0.0), hsig(n, 0.0), hmu(n, 0.0), hic(n, 0.0), hub(n, 0.0);
+  std::vector<int32_t> hgrp(n, 0), hpos(n, 0), hkind(n, 0), hidx(n, 0), hct(n, 0);
+  std::vector<double> hz(n), hzr(n, 0.0), hru(n, 0.0), hsig(n, 0.0), hmu(n, 0.0), hic(n, 0.0), hub(n, 0.0);
+  std::vector<ZItem> zit;
   std::vector<double> rd, rz, lamr, mur, xnr, rhop;
   std::vector<int32_t> sidx, infop;
   std::vector<int64_t> offs;
@@ -466,14 +544,19 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
   dpr1_plan plan;
   // host mirrors of contiguous workspace regions, so that each region moves
   // in one copy per depth: the solver's inputs [rd, offsp], its outputs
-  // [lamr, infop], the merges' poles and z [zl, dl], and the assembly and
-  // GEMM arrays [rgrp, gtab]
+  // [lamr, infop], the merges' poles and z [zl, dl], and the assembly, GEMM
+  // and z-row arrays [rgrp, zit]
   const int64_t P = std::max<int64_t>(L.maxNodes, 1);
   std::vector<char> mirA(L.offsp + 8 * (P + 1) - L.rd), mirB(L.infop + 4 * P - L.lamr), mirZ(L.dl + 8 * n - L.zl),
       mirC(L.solver - L.rgrp);
   auto put = [](std::vector<char>& mir, size_t base, size_t off, const void* src, size_t bytes) {
     if (bytes) memcpy(mir.data() + (off - base), src, bytes);
   };
+  hipStream_t st2 = tri_aux_stream();
+  if (!st2) return DPR1_EHIP;
+  TriDone fin{st, st2};
+  TCHECK(hipEventCreateWithFlags(&fin.ev, hipEventDisableTiming));
+  bool zpending = false;  // rows of this depth's z in flight to hzr (event fin.ev)
 
   for (int D = maxd; D >= 0; --D) {
     std::vector<const Node*> lv;
@@ -486,16 +569,18 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     double* Qc = (D % 2 == 0) ? Qw : Q;
     const int64_t ldc = (D % 2 == 0) ? n : ldq;
 
-    // 1. z of every merge
-    std::fill(hsrc.begin(), hsrc.end(), -1);
-    for (const Node* nd : lv)
-      for (int64_t i = nd->start; i < nd->start + nd->size; ++i)
-        hsrc[i] = (int32_t)(i < nd->start + nd->m ? nd->start + nd->m - 1 : nd->start + nd->m);
-    TCHECK(h2d(src, hsrc, n, st));
-    hipLaunchKernelGGL(k_gather_z, dim3(g1), dim3(256), 0, st, Qc, ldc, src, n, zl);
-    TCHECK(hipGetLastError());
-    TCHECK(hipMemcpyAsync(hz.data(), zl, 8 * n, hipMemcpyDeviceToHost, st));
-    TCHECK(hipStreamSynchronize(st));
+    // 1. z of every merge: the rows k_zrows formed for its merged children
+    // (copied to hzr), 1 for a 1 x 1 child; 0 outside this depth's merges
+    if (zpending) {
+      TCHECK(hipEventSynchronize(fin.ev));
+      zpending = false;
+    }
+    std::fill(hz.begin(), hz.end(), 0.0);
+    for (const Node* nd : lv) {
+      const int64_t o = nd->start, m = nd->m, s2 = nd->size - nd->m;
+      if (m == 1) hz[o] = 1.0; else std::copy(hzr.begin() + o, hzr.begin() + o + m, hz.begin() + o);
+      if (s2 == 1) hz[o + m] = 1.0; else std::copy(hzr.begin() + o + m, hzr.begin() + o + m + s2, hz.begin() + o + m);
+    }
 
     // 2. reduce each merge (hlam holds the current eigenvalues of every block)
     rd.clear();
@@ -565,7 +650,7 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     sidx.resize(mtot);
     if (nprob > 0) {
       infop.assign(nprob, 0);
-      const int prc = dpr1_batched_plan(nprob, offs.data(), opts, &plan, w + L.solver, L.solver_bytes, stream);
+      const int prc = dpr1_batched_plan(nprob, offs.data(), opts, &plan, w + L.solver, L.solver_bytes, (void*)st2);
       if (prc != DPR1_OK) return prc == DPR1_EHIP ? DPR1_EHIP : -10;
       double* drd = (double*)(w + L.rd);
       double* drz = (double*)(w + L.rz);
@@ -580,12 +665,12 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
       put(mirA, L.rd, L.rz, rz.data(), 8 * mtot);
       put(mirA, L.rd, L.rhop, rhop.data(), 8 * nprob);
       put(mirA, L.rd, L.offsp, offs.data(), 8 * (nprob + 1));
-      TCHECK(hipMemcpyAsync(w + L.rd, mirA.data(), L.offsp + 8 * (nprob + 1) - L.rd, hipMemcpyHostToDevice, st));
+      TCHECK(hipMemcpyAsync(w + L.rd, mirA.data(), L.offsp + 8 * (nprob + 1) - L.rd, hipMemcpyHostToDevice, st2));
       const int rc = dpr1_eig_batched(&plan, doffs, drd, drz, drho, dlr, nullptr, nullptr, dsi, dmu, dxn, dinf,
-                                      nullptr, w + L.solver, L.solver_bytes, stream);
+                                      nullptr, w + L.solver, L.solver_bytes, (void*)st2);
       if (rc != DPR1_OK) return rc;
-      TCHECK(hipMemcpyAsync(mirB.data(), w + L.lamr, mirB.size(), hipMemcpyDeviceToHost, st));
-      TCHECK(hipStreamSynchronize(st));
+      TCHECK(hipMemcpyAsync(mirB.data(), w + L.lamr, mirB.size(), hipMemcpyDeviceToHost, st2));
+      TCHECK(hipStreamSynchronize(st2));
       memcpy(lamr.data(), mirB.data() + (L.lamr - L.lamr), 8 * mtot);
       memcpy(mur.data(), mirB.data() + (L.mur - L.lamr), 8 * mtot);
       memcpy(xnr.data(), mirB.data() + (L.xnr - L.lamr), 8 * mtot);
@@ -603,6 +688,7 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     atab.clear();
     gdesc.clear();
     gtab.clear();
+    zit.clear();
     int64_t voff = 0;
     hnew = hlam;
     for (size_t p = 0; p < lv.size(); ++p) {
@@ -643,9 +729,20 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
         for (int32_t tc = 0; tc < (int32_t)cdiv(s, GT); ++tc) gtab.push_back({d1, tr, tc, 0});
       for (int32_t tr = 0; tr < (int32_t)cdiv(s - nd.m, GT); ++tr)
         for (int32_t tc = 0; tc < (int32_t)cdiv(s, GT); ++tc) gtab.push_back({d1 + 1, tr, tc, 0});
+      // the row of this block's Q that the parent's z takes: the last (left
+      // child, in the Q2 block) or the first (right child, in the Q1 block)
+      if (nd.side) {
+        const int64_t r = nd.side == 1 ? o + s - 1 : o;
+        const int64_t kbeg = nd.side == 1 ? o2 : o, len = nd.side == 1 ? s - nd.m : nd.m;
+        for (int64_t c0 = 0; c0 < s; c0 += ZC)
+          zit.push_back({r + kbeg * ldc, voff + (kbeg - o) + c0 * s, (int32_t)len, (int32_t)s, (int32_t)(o + c0),
+                         (int32_t)std::min<int64_t>(ZC, s - c0)});
+      }
       voff += s * s;
     }
-    if (voff > L.maxV || (int64_t)atab.size() > L.maxAsm || (int64_t)gtab.size() > L.maxTiles) return -10;
+    if (voff > L.maxV || (int64_t)atab.size() > L.maxAsm || (int64_t)gtab.size() > L.maxTiles ||
+        (int64_t)zit.size() > L.maxZ)
+      return -10;
     hlam.swap(hnew);
     TCHECK(hipMemcpyAsync(lambda, hlam.data(), 8 * n, hipMemcpyHostToDevice, st));
     put(mirC, L.rgrp, L.rgrp, hgrp.data(), 4 * n);
@@ -662,7 +759,10 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     put(mirC, L.rgrp, L.atab, atab.data(), sizeof(int4) * atab.size());
     put(mirC, L.rgrp, L.gdesc, gdesc.data(), sizeof(GDesc) * gdesc.size());
     put(mirC, L.rgrp, L.gtab, gtab.data(), sizeof(int4) * gtab.size());
-    TCHECK(hipMemcpyAsync(w + L.rgrp, mirC.data(), L.gtab + sizeof(int4) * gtab.size() - L.rgrp,
+    put(mirC, L.rgrp, L.zit, zit.data(), sizeof(ZItem) * zit.size());
+    TCHECK(hipMemcpyAsync(w + L.rgrp, mirC.data(),
+                          (zit.empty() ? L.gtab + sizeof(int4) * gtab.size() : L.zit + sizeof(ZItem) * zit.size()) -
+                              L.rgrp,
                           hipMemcpyHostToDevice, st));
     ANode* danodes = (ANode*)(w + L.anodes);
     int4* datab = (int4*)(w + L.atab);
@@ -670,6 +770,16 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     int4* dgtab = (int4*)(w + L.gtab);
     hipLaunchKernelGGL(k_tri_assemble, dim3((unsigned)atab.size()), dim3(TA_T), 0, st, danodes, datab, ta);
     TCHECK(hipGetLastError());
+    // the parents' z rows (after the assembly, which reads this depth's z
+    // from the same buffer), on the host before the product below ends
+    if (!zit.empty()) {
+      hipLaunchKernelGGL(k_zrows, dim3((unsigned)zit.size()), dim3(ZT), 0, st, (const ZItem*)(w + L.zit), Qc, ldc,
+                         (const double*)ta.V, zl);
+      TCHECK(hipGetLastError());
+      TCHECK(hipMemcpyAsync(hzr.data(), zl, 8 * n, hipMemcpyDeviceToHost, st));
+      TCHECK(hipEventRecord(fin.ev, st));
+      zpending = true;
+    }
     // 5. Q = diag(Q1, Q2) V for every merge
     hipLaunchKernelGGL(k_dgemm, dim3((unsigned)gtab.size()), dim3(GNT), 0, st, dgdesc, dgtab);
     TCHECK(hipGetLastError());
