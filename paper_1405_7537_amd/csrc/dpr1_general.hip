@@ -266,6 +266,7 @@ static int front_end(const double* d, const double* zdev, const std::vector<doub
   // (sigma_k, mu_k, ||x_k||) from which k_assemble evaluates the vectors
   std::vector<double> lamr(m), mur(m), xnr(m);
   std::vector<int32_t> sir(m);
+  std::vector<char> mir;
   if (m > 0) {
     double* ddr = (double*)(w + L.dr);
     double* dzr = (double*)(w + L.zr);
@@ -274,20 +275,25 @@ static int front_end(const double* d, const double* zdev, const std::vector<doub
     double* dmu = (double*)(w + L.mu);
     double* dxn = (double*)(w + L.xn);
     int32_t* dinf = (int32_t*)(w + L.inf);
-    GCHECK(hipMemcpyAsync(ddr, rd.data(), 8 * m, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync(dzr, rz.data(), 8 * m, hipMemcpyHostToDevice, st));
+    // the inputs [dr, zr] and the outputs [lamr, inf] are contiguous in the
+    // workspace: one copy each way through a host mirror
+    mir.resize(std::max(L.zr + 8 * m - L.dr, L.inf + 4 - L.lamr));
+    memcpy(mir.data(), rd.data(), 8 * m);
+    memcpy(mir.data() + (L.zr - L.dr), rz.data(), 8 * m);
+    GCHECK(hipMemcpyAsync(ddr, mir.data(), L.zr + 8 * m - L.dr, hipMemcpyHostToDevice, st));
     const int rc = dpr1_eig(ddr, dzr, rho, m, dlr, nullptr, m, V ? dsi : nullptr, V ? dmu : nullptr,
                             V ? dxn : nullptr, dinf, nullptr, opts, w + L.solver, dpr1_workspace_size(m), stream);
     if (rc != DPR1_OK) return rc;
     int32_t hinf = 0;
-    GCHECK(hipMemcpyAsync(lamr.data(), dlr, 8 * m, hipMemcpyDeviceToHost, st));
-    if (V) {
-      GCHECK(hipMemcpyAsync(sir.data(), dsi, 4 * m, hipMemcpyDeviceToHost, st));
-      GCHECK(hipMemcpyAsync(mur.data(), dmu, 8 * m, hipMemcpyDeviceToHost, st));
-      GCHECK(hipMemcpyAsync(xnr.data(), dxn, 8 * m, hipMemcpyDeviceToHost, st));
-    }
-    GCHECK(hipMemcpyAsync(&hinf, dinf, 4, hipMemcpyDeviceToHost, st));
+    GCHECK(hipMemcpyAsync(mir.data(), dlr, L.inf + 4 - L.lamr, hipMemcpyDeviceToHost, st));
     GCHECK(hipStreamSynchronize(st));
+    memcpy(lamr.data(), mir.data(), 8 * m);
+    if (V) {
+      memcpy(sir.data(), mir.data() + (L.sidx - L.lamr), 4 * m);
+      memcpy(mur.data(), mir.data() + (L.mu - L.lamr), 8 * m);
+      memcpy(xnr.data(), mir.data() + (L.xn - L.lamr), 8 * m);
+    }
+    memcpy(&hinf, mir.data() + (L.inf - L.lamr), 4);
     if (hinf != DPR1_INFO_OK) return set_info(info, hinf, st);
   }
   {
@@ -329,16 +335,20 @@ static int front_end(const double* d, const double* zdev, const std::vector<doub
     a.cic = (double*)(w + L.cic);
     a.cub = (double*)(w + L.cub);
     a.V = V;
-    GCHECK(hipMemcpyAsync((void*)a.rgrp, rgrp.data(), 4 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.rpos, rpos.data(), 4 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.ru, ru.data(), 8 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.ckind, ckind.data(), 4 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.cidx, cidx.data(), 4 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.ct, ct.data(), 4 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.csig, csig.data(), 8 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.cmu, cmu.data(), 8 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.cic, cic.data(), 8 * n, hipMemcpyHostToDevice, st));
-    GCHECK(hipMemcpyAsync((void*)a.cub, cub.data(), 8 * n, hipMemcpyHostToDevice, st));
+    // the ten column tables [rgrp, cub] are contiguous: one copy
+    mir.resize(L.cub + 8 * n - L.rgrp);
+    auto put = [&](size_t off, const void* src, size_t bytes) { memcpy(mir.data() + (off - L.rgrp), src, bytes); };
+    put(L.rgrp, rgrp.data(), 4 * n);
+    put(L.rpos, rpos.data(), 4 * n);
+    put(L.ru, ru.data(), 8 * n);
+    put(L.ckind, ckind.data(), 4 * n);
+    put(L.cidx, cidx.data(), 4 * n);
+    put(L.ct, ct.data(), 4 * n);
+    put(L.csig, csig.data(), 8 * n);
+    put(L.cmu, cmu.data(), 8 * n);
+    put(L.cic, cic.data(), 8 * n);
+    put(L.cub, cub.data(), 8 * n);
+    GCHECK(hipMemcpyAsync(w + L.rgrp, mir.data(), mir.size(), hipMemcpyHostToDevice, st));
     const int64_t rows = ASM_T * ASM_R;
     const int64_t rtiles = (n + rows - 1) / rows;
     // about 512 blocks, each looping over every gy-th column group: the grid's
