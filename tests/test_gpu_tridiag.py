@@ -216,3 +216,30 @@ def test_glued_wilkinson_large(D, orc, nb, glue):
     assert orth <= 1e-12 and res <= 1e-12
     lo, Qo = orc.tridiag_eig(a, b)
     assert np.max(np.abs(lam - lo)) <= 1e-12 * nt
+
+
+def test_side_stream_and_repeat_bitwise(D):
+    """The driver overlaps each depth's host work and DPR1 solves (on the library's second stream)
+    with the product of the depth below on the caller's stream.  Called on a side stream, with the
+    default stream busy on other work meanwhile, and twice in a row with one workspace, it gives
+    the same bits as a plain call: every cross-stream dependency is waited for."""
+    import torch
+    n = 3000
+    a_h, b_h = W.tridiagonal(n, 17)
+    a = torch.as_tensor(a_h, device="cuda")
+    b = torch.as_tensor(b_h, device="cuda")
+    print(f"[tridiag] side stream n={n}", flush=True)
+    r0 = D.tridiag_eig(a, b)
+    lam0, Q0 = r0.lam.clone(), r0.Q.clone()
+    r1 = D.tridiag_eig(a, b, work=r0.work)
+    assert torch.equal(r1.lam, lam0) and torch.equal(r1.Q, Q0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    busy = torch.randn(4096, 4096, dtype=torch.float64, device="cuda")
+    for _ in range(4):  # queued on the default stream, running during the call below
+        busy = (busy @ busy.t()) * 1e-3
+    with torch.cuda.stream(s):
+        r2 = D.tridiag_eig(a, b)
+        lam2, Q2 = r2.lam.clone(), r2.Q.clone()
+    torch.cuda.synchronize()
+    assert torch.equal(lam2, lam0) and torch.equal(Q2, Q0)
