@@ -339,7 +339,7 @@ static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct TLayout {
-  size_t Qw, Vw, zl, dl, rd, rz, lamr, mur, xnr, sidx, infop, rhop, offsp, rgrp, rpos, ru, ckind, cidx, ct,
+  size_t Qw, Vw, rd, rz, lamr, mur, xnr, sidx, infop, rhop, offsp, zl, dl, rgrp, rpos, ru, ckind, cidx, ct,
       csig, cmu, cic, cub, anodes, atab, gdesc, gtab, zit, solver, total;
   int64_t maxV, maxAsm, maxTiles, maxNodes, maxZ;
   size_t solver_bytes;
@@ -379,8 +379,6 @@ static TLayout tlayout(int64_t n, const std::vector<Node>& nodes, int maxd) {
   size_t o = 0;
   L.Qw = o; o = al(o + 8 * (size_t)n * n);
   L.Vw = o; o = al(o + 8 * (size_t)L.maxV);
-  L.zl = o; o = al(o + 8 * n);
-  L.dl = o; o = al(o + 8 * n);
   L.rd = o; o = al(o + 8 * n);
   L.rz = o; o = al(o + 8 * n);
   L.lamr = o; o = al(o + 8 * n);
@@ -390,6 +388,8 @@ static TLayout tlayout(int64_t n, const std::vector<Node>& nodes, int maxd) {
   L.infop = o; o = al(o + 4 * P);
   L.rhop = o; o = al(o + 8 * P);
   L.offsp = o; o = al(o + 8 * (P + 1));
+  L.zl = o; o = al(o + 8 * n);
+  L.dl = o; o = al(o + 8 * n);
   L.rgrp = o; o = al(o + 4 * n);
   L.rpos = o; o = al(o + 4 * n);
   L.ru = o; o = al(o + 8 * n);
@@ -544,11 +544,10 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
   dpr1_plan plan;
   // host mirrors of contiguous workspace regions, so that each region moves
   // in one copy per depth: the solver's inputs [rd, offsp], its outputs
-  // [lamr, infop], the merges' poles and z [zl, dl], and the assembly, GEMM
-  // and z-row arrays [rgrp, zit]
+  // [lamr, infop], and the merges' z and poles with the assembly, GEMM and
+  // z-row arrays [zl, zit]
   const int64_t P = std::max<int64_t>(L.maxNodes, 1);
-  std::vector<char> mirA(L.offsp + 8 * (P + 1) - L.rd), mirB(L.infop + 4 * P - L.lamr), mirZ(L.dl + 8 * n - L.zl),
-      mirC(L.solver - L.rgrp);
+  std::vector<char> mirA(L.offsp + 8 * (P + 1) - L.rd), mirB(L.infop + 4 * P - L.lamr), mirC(L.solver - L.zl);
   auto put = [](std::vector<char>& mir, size_t base, size_t off, const void* src, size_t bytes) {
     if (bytes) memcpy(mir.data() + (off - base), src, bytes);
   };
@@ -681,9 +680,8 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     }
 
     // 4. columns of every merge, the new eigenvalues, the assembly and GEMM tables
-    put(mirZ, L.zl, L.zl, hz.data(), 8 * n);     // z as reduced
-    put(mirZ, L.zl, L.dl, hpole.data(), 8 * n);  // the merges' poles (grouped)
-    TCHECK(hipMemcpyAsync(w + L.zl, mirZ.data(), mirZ.size(), hipMemcpyHostToDevice, st));
+    put(mirC, L.zl, L.zl, hz.data(), 8 * n);     // z as reduced
+    put(mirC, L.zl, L.dl, hpole.data(), 8 * n);  // the merges' poles (grouped)
     anodes.clear();
     atab.clear();
     gdesc.clear();
@@ -744,25 +742,24 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
         (int64_t)zit.size() > L.maxZ)
       return -10;
     hlam.swap(hnew);
-    TCHECK(hipMemcpyAsync(lambda, hlam.data(), 8 * n, hipMemcpyHostToDevice, st));
-    put(mirC, L.rgrp, L.rgrp, hgrp.data(), 4 * n);
-    put(mirC, L.rgrp, L.rpos, hpos.data(), 4 * n);
-    put(mirC, L.rgrp, L.ru, hru.data(), 8 * n);
-    put(mirC, L.rgrp, L.ckind, hkind.data(), 4 * n);
-    put(mirC, L.rgrp, L.cidx, hidx.data(), 4 * n);
-    put(mirC, L.rgrp, L.ct, hct.data(), 4 * n);
-    put(mirC, L.rgrp, L.csig, hsig.data(), 8 * n);
-    put(mirC, L.rgrp, L.cmu, hmu.data(), 8 * n);
-    put(mirC, L.rgrp, L.cic, hic.data(), 8 * n);
-    put(mirC, L.rgrp, L.cub, hub.data(), 8 * n);
-    put(mirC, L.rgrp, L.anodes, anodes.data(), sizeof(ANode) * anodes.size());
-    put(mirC, L.rgrp, L.atab, atab.data(), sizeof(int4) * atab.size());
-    put(mirC, L.rgrp, L.gdesc, gdesc.data(), sizeof(GDesc) * gdesc.size());
-    put(mirC, L.rgrp, L.gtab, gtab.data(), sizeof(int4) * gtab.size());
-    put(mirC, L.rgrp, L.zit, zit.data(), sizeof(ZItem) * zit.size());
-    TCHECK(hipMemcpyAsync(w + L.rgrp, mirC.data(),
+    put(mirC, L.zl, L.rgrp, hgrp.data(), 4 * n);
+    put(mirC, L.zl, L.rpos, hpos.data(), 4 * n);
+    put(mirC, L.zl, L.ru, hru.data(), 8 * n);
+    put(mirC, L.zl, L.ckind, hkind.data(), 4 * n);
+    put(mirC, L.zl, L.cidx, hidx.data(), 4 * n);
+    put(mirC, L.zl, L.ct, hct.data(), 4 * n);
+    put(mirC, L.zl, L.csig, hsig.data(), 8 * n);
+    put(mirC, L.zl, L.cmu, hmu.data(), 8 * n);
+    put(mirC, L.zl, L.cic, hic.data(), 8 * n);
+    put(mirC, L.zl, L.cub, hub.data(), 8 * n);
+    put(mirC, L.zl, L.anodes, anodes.data(), sizeof(ANode) * anodes.size());
+    put(mirC, L.zl, L.atab, atab.data(), sizeof(int4) * atab.size());
+    put(mirC, L.zl, L.gdesc, gdesc.data(), sizeof(GDesc) * gdesc.size());
+    put(mirC, L.zl, L.gtab, gtab.data(), sizeof(int4) * gtab.size());
+    put(mirC, L.zl, L.zit, zit.data(), sizeof(ZItem) * zit.size());
+    TCHECK(hipMemcpyAsync(w + L.zl, mirC.data(),
                           (zit.empty() ? L.gtab + sizeof(int4) * gtab.size() : L.zit + sizeof(ZItem) * zit.size()) -
-                              L.rgrp,
+                              L.zl,
                           hipMemcpyHostToDevice, st));
     ANode* danodes = (ANode*)(w + L.anodes);
     int4* datab = (int4*)(w + L.atab);
@@ -784,6 +781,8 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
     hipLaunchKernelGGL(k_dgemm, dim3((unsigned)gtab.size()), dim3(GNT), 0, st, dgdesc, dgtab);
     TCHECK(hipGetLastError());
   }
+  // the eigenvalues once, after the root merge (no kernel reads them)
+  if (!nodes.empty()) TCHECK(hipMemcpyAsync(lambda, hlam.data(), 8 * n, hipMemcpyHostToDevice, st));
   // tri_set_info waits for the stream: the host staging above must outlive
   // its copies
   return tri_set_info(info, DPR1_INFO_OK, st);
