@@ -524,8 +524,10 @@ int dpr1_tridiag_eig(const double* a, const double* b, int64_t n, double* lambda
   ta.cub = (double*)(w + L.cub);
   ta.V = (double*)(w + L.Vw);
 
-  // host staging, reused by every depth (each is rewritten only after the
-  // stream has been synchronised at the start of the next depth)
+  // host staging, reused by every depth: each buffer is rewritten only after
+  // the copies that use it have finished (the event waited for at the start of
+  // a depth follows the previous depth's copies on the caller's stream; the
+  // second stream is synchronised after each depth's solves)
   std::vector<int32_t> hgrp(n, 0), hpos(n, 0), hkind(n, 0), hidx(n, 0), hct(n, 0);
   std::vector<double> hz(n), hzr(n, 0.0), hru(n, 0.0), hsig(n, 0.0), hmu(n, 0.0), hic(n, 0.0), hub(n, 0.0);
   std::vector<ZItem> zit;
