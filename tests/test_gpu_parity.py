@@ -415,3 +415,66 @@ def test_overlapped_write_matches_sequential(D):
         for o in outs[1:]:
             for a, b in zip(outs[0], o):
                 assert torch.equal(a, b)
+
+
+def _sampled_columns(D, V_t, ks):
+    """Columns ks of a [n, n] column-major V (given as V.t(), rows = eigenvectors) on the host."""
+    import torch
+    return V_t[torch.as_tensor(ks, device=V_t.device)].cpu().numpy().T
+
+
+def test_index_range_beyond_2_32(D, orc):
+    """n = 70000 with the full V (39 GB): element indices k ldv + j pass 2^31 from column 30679 on
+    and 2^32 from column 61356 on, so every V address must be formed in 64 bits.  Sampled eigenpairs
+    (the first and last columns, both sides of each boundary, random ones) against the oracle to
+    the parity bar, for rho > 0 and for rho < 0 (reversed positions and columns)."""
+    import torch
+    n = 70000
+    d, z, rho = W.uniform(n, 23, zscale=1.0 / math.sqrt(n))
+    rng = np.random.default_rng(5)
+    ks = np.unique(np.concatenate([[0, 1, 30678, 30679, 61355, 61356, n - 2, n - 1],
+                                   rng.choice(n, 12, replace=False)])).astype(np.int64)
+    for sgn in (1.0, -1.0):
+        print(f"[parity] n={n} full V, rho sign {sgn:+.0f}", flush=True)
+        r = D.eig(d, z, sgn * rho)
+        lam = r.lam.cpu().numpy()
+        if sgn > 0:
+            lo, Vo, _ = orc.eig_some(d, z, rho, ks, vectors=True)
+        else:
+            # Sec. 1: D + rho z z^T with rho < 0 is minus the problem (-d reversed, z reversed, -rho);
+            # its eigenpair n-1-k gives lambda_k negated and v_k reversed and negated (the oracle's
+            # own convention for rho < 0)
+            lm, Vm, _ = orc.eig_some(-d[::-1], z[::-1], rho, n - 1 - ks, vectors=True)
+            lo, Vo = -lm, -Vm[::-1, :]
+        Vs = _sampled_columns(D, r.V.t(), ks)
+        el, ev = rel(lam[ks], lo), rel(Vs, Vo)
+        print(f"[parity] n={n} rho sign {sgn:+.0f}: max rel lam {el.max():.3e} V {ev.max():.3e}", flush=True)
+        assert el.max() <= LAM_TOL, (ks[np.argmax(el)], el.max())
+        assert ev.max() <= VEC_TOL, (np.unravel_index(np.argmax(ev), ev.shape), ev.max())
+        del r
+        torch.cuda.empty_cache()
+
+
+def test_batched_offsets_beyond_2_32(D, orc):
+    """A batch of 16 problems of order 17000: the packed V holds 4.6e9 elements (37 GB), so the
+    later problems' blocks start past 2^32.  The last eigenpairs of the first, a middle and the
+    last problem, and a few random ones of each, against the oracle element by element."""
+    import torch
+    nb, n = 16, 17000
+    d2, z2, rho2 = W.uniform_batch(nb, n, 29)
+    z2 = z2 / math.sqrt(n)
+    offs = np.arange(nb + 1, dtype=np.int64) * n
+    print(f"[parity] batch {nb} x n={n}: V {nb * n * n * 8 / 1e9:.1f} GB", flush=True)
+    b = D.eig_batched(d2.reshape(-1), z2.reshape(-1), rho2, offs)
+    lam_all = b.lam.cpu().numpy()
+    rng = np.random.default_rng(9)
+    for p in (0, nb // 2, nb - 1):
+        ks = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 6, replace=False)])).astype(np.int64)
+        lo, Vo, _ = orc.eig_some(d2[p], z2[p], rho2[p], ks, vectors=True)
+        Vs = _sampled_columns(D, b.vblock(p).t(), ks)
+        el, ev = rel(lam_all[p * n + ks], lo), rel(Vs, Vo)
+        print(f"[parity] batch problem {p} (V offset {p * n * n}): max rel lam {el.max():.3e} V {ev.max():.3e}",
+              flush=True)
+        assert el.max() <= LAM_TOL and ev.max() <= VEC_TOL, (p, el.max(), ev.max())
+    del b
+    torch.cuda.empty_cache()
