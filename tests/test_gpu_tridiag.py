@@ -243,3 +243,42 @@ def test_side_stream_and_repeat_bitwise(D):
         lam2, Q2 = r2.lam.clone(), r2.Q.clone()
     torch.cuda.synchronize()
     assert torch.equal(lam2, lam0) and torch.equal(Q2, Q0)
+
+
+def test_maximum_order_sampled(D):
+    """The largest order the driver takes, n = 65536 (Q and its second buffer 34 GB each, the root
+    merge a DPR1 problem of order 65536): 64 eigenvalues against LAPACK's bisection for the same
+    indices, the trace, and for 66 columns their inner products with every column of Q and the
+    residual T q - lambda q (properties that hold at any size)."""
+    import torch
+    from scipy.linalg import eigvalsh_tridiagonal
+    n = 65536
+    a, b = W.tridiagonal(n, 31)
+    print(f"[tridiag] maximum order n={n}", flush=True)
+    r = D.tridiag_eig(a, b)
+    lam_d = r.lam
+    lam = lam_d.cpu().numpy()
+    assert np.all(np.diff(lam) <= 0)
+    nt = max(abs(lam[0]), abs(lam[-1]))
+    eps = np.finfo(float).eps
+    rng = np.random.default_rng(3)
+    ks = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.choice(n, 59, replace=False)]))
+    ref = np.array([eigvalsh_tridiagonal(a, b, select="i", select_range=(n - 1 - k, n - 1 - k))[0] for k in ks])
+    el = np.max(np.abs(lam[ks] - ref)) / nt
+    tr = abs(float(np.sum(lam)) - float(np.sum(a))) / (n * nt)
+    cols = np.unique(np.concatenate([np.arange(0, n, 1024), [n - 1]]))
+    ci = torch.as_tensor(cols, device=r.Q.device)
+    Qs = r.Q[:, ci]                                        # [n, 65] sampled columns
+    G = Qs.T @ r.Q                                         # inner products with every column
+    G[torch.arange(cols.size, device=G.device), ci] -= 1.0
+    orth = G.abs().max().item()
+    ad = torch.as_tensor(a, device=Qs.device)
+    bd = torch.as_tensor(b, device=Qs.device)
+    TQ = ad[:, None] * Qs
+    TQ[:-1] += bd[:, None] * Qs[1:]
+    TQ[1:] += bd[:, None] * Qs[:-1]
+    res = (TQ - Qs * lam_d[ci][None, :]).abs().max().item() / nt
+    print(f"[tridiag] n={n}: lam {el:.2e} trace {tr:.2e} orth {orth:.2e} res {res:.2e}", flush=True)
+    assert el <= 1e-12 and tr <= 64 * eps and orth <= 1e-11 and res <= 1e-11
+    del r, G, Qs, TQ
+    torch.cuda.empty_cache()
