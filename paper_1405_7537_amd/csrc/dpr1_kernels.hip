@@ -2109,13 +2109,28 @@ static void fill_opts(const dpr1_opts* in, dpr1_opts* o) {
   }
 }
 
-static int pick_split(int64_t nblocks, int64_t nmax) {
-  // enough waves for 256 CUs x 16 (4 per SIMD at this kernel's register
-  // use), without slices shorter than 256 terms
-  int64_t w = (4096 + nblocks - 1) / std::max<int64_t>(nblocks, 1);
-  w = std::min<int64_t>(w, MAXW);
-  while (w > 1 && nmax / w < 256) --w;
-  return (int)std::max<int64_t>(w, 1);
+// The split when the options leave it open: the W that ends the launch
+// soonest, with a block of W waves taking time in proportion to its slice
+// n/W and each of the 256 CUs holding floor(4 occ / W) blocks at a time (a
+// block's waves stay on one CU, 4 occ wave slots per CU): minimise
+// ceil(nblocks / (256 floor(4 occ / W))) / W, the smaller W on a tie (fewer
+// partial sums), keeping slices of at least 256 terms.  (Filling the wave
+// slots alone is not enough: 423 blocks at W = 10 fit one block per CU and
+// take two rounds, 1.6 times longer than W = 8 in one.)
+static int pick_split(int64_t nblocks, int64_t nmax, int occ) {
+  int best = 1;
+  double bc = 1e300;
+  for (int w = 1; w <= MAXW; ++w) {
+    if (w > 1 && nmax / w < 256) break;
+    const int64_t per_cu = (4 * (int64_t)occ) / w;
+    if (per_cu < 1) break;
+    const double c = std::ceil((double)std::max<int64_t>(nblocks, 1) / (256.0 * (double)per_cu)) / w;
+    if (c < bc * (1.0 - 1e-9)) {
+      bc = c;
+      best = w;
+    }
+  }
+  return best;
 }
 
 // k_eig occupancy variant of the options: 4 (default), 6 or 8 waves per SIMD.
@@ -2487,7 +2502,7 @@ int dpr1_eig(const double* d, const double* z, double rho, int64_t n, double* la
   if (!occ_valid(o.waves_per_simd) || o.vwrite < 0 || o.vwrite > VEC_CHUNKS_MAX || o.mode_b < 0 || o.mode_b > 3)
     return -13;
   int64_t nblocks = (n + WAVE - 1) / WAVE;
-  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
+  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n, occ_of(o));
   return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
                       mu, xnorm, info, stats, o, W, nblocks, 0, 0, (hipStream_t)stream);
 }
@@ -2515,7 +2530,7 @@ int dpr1_eig_noalloc(const double* d, const double* z, double rho, int64_t n, do
   if (!work) return DPR1_EHIP;
   const Layout L = layout(1, n, 0);
   int64_t nblocks = (n + WAVE - 1) / WAVE;
-  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n);
+  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nblocks, n, occ_of(o));
   return launch_solve(L, (char*)work, 1, n, nullptr, n, d, z, nullptr, rho, lambda, V, nullptr, ldv, shift_idx,
                       mu, xnorm, info, stats, o, W, nblocks, 0, 0, (hipStream_t)stream,
                       /*aux_ok=*/false);
@@ -2563,7 +2578,7 @@ int dpr1_batched_plan(int64_t nprob, const int64_t* offs_host, const dpr1_opts* 
     for (int64_t k0 = 0; k0 < np; k0 += WAVE) items.push_back(make_int2(p, (int)k0));
   }
   int64_t nitems = (int64_t)items.size();
-  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nitems, nmax);
+  int W = o.split > 0 ? std::min(o.split, MAXW) : pick_split(nitems, nmax, occ_of(o));
   // blocks of the eigenvector kernel: (problem, first column, columns,
   // first row), largest problems first
   std::vector<int4> groups;
