@@ -134,7 +134,7 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_step / 1e3)
-    # The same solves with the eigenvector write after the eigenvalue kernel (opts.vwrite = 1),
+    # The same solves with the eigenvector write after the eigenvalue kernel (opts.vwrite = 1, the default),
     # timed with the library's events on the launch stream: the eigenvalue kernel is then one
     # launch (the roofline's duration) and the second phase (k_fixvec + k_fixout) writes V alone.
     seq = D.opts(root=args.root, split=base.split, main_passes=base.main_passes,
@@ -196,10 +196,11 @@ def main():
                     "ms": vec_ms, "GB/s": vec_gbs, "frac_hbm": vec_gbs / HBM_PEAK_GBS,
                     "ms_per_step_sequential": ms_seq,
                     "note": ("value is timed with the tuned write: " + (
-                        "after the eigenvalue kernel (opts.vwrite = 1), as here" if int(base.vwrite) == 1 else
-                        "the eigenvalue kernel in two chunks, the first chunk's columns written on a second "
-                        "stream while the second chunk is solved (opts.vwrite = 0); k_eig and the write are timed "
-                        "here with the write after the eigenvalue kernel, same launch shape"))},
+                        "after the eigenvalue kernel (opts.vwrite = 0), as here" if int(base.vwrite) <= 1 else
+                        f"the eigenvalue kernel in {int(base.vwrite)} chunks, each chunk's columns but the last "
+                        f"written on a second stream while the next chunk is solved (opts.vwrite = "
+                        f"{int(base.vwrite)}); k_eig and the write are timed here with the write after the "
+                        "eigenvalue kernel, same launch shape"))},
         "stats": st,
     }
 

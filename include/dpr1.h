@@ -19,9 +19,10 @@
  *    return (dpr1_eig_noalloc: a static device array of the library).
  *    Workspace contents need not be initialised.
  *  - All work is enqueued asynchronously on `stream` (a hipStream_t passed as
- *    void*; NULL = the default stream); dpr1_eig with eigenvectors forks part
- *    of its work to a second stream of the library and joins it back into
- *    `stream` through events before it returns (opts.vwrite).  No call
+ *    void*; NULL = the default stream); dpr1_eig with eigenvectors and
+ *    opts.vwrite >= 2 forks part of its work to a second stream of the
+ *    library and joins it back into `stream` through events before it
+ *    returns.  No call
  *    synchronises the host, so the launches may be captured into a hipGraph,
  *    except dpr1_batched_plan (it copies from host memory), the autotuners
  *    and dpr1_eig_general.
@@ -131,16 +132,16 @@ typedef struct dpr1_opts {
                           the flagged eigenpairs overlapped with the
                           eigenvector write                                 */
   int32_t vwrite;      /* eigenvectors of a single problem of order n >= 8192:
-                          0 (default) = 2; K = 2 .. 8: the eigenvalue
+                          0 (default) or 1: every column after the
+                          eigenvalue kernel, on `stream` only; K = 2 .. 8: the eigenvalue
                           kernel runs in K launches over consecutive chunks
                           of the eigenvalues, and each chunk's columns but
                           the last are written on a second stream (a library
                           stream per device, created on first use, default
-                          priority) while the next chunk is solved; 1 every
-                          column after the eigenvalue kernel, on `stream`
-                          only.  Results are the same bit for bit.  Other
-                          values are rejected.  dpr1_eig_noalloc always
-                          uses 1.                                          */
+                          priority) while the next chunk is solved.
+                          Results are the same bit for bit.  Other values
+                          are rejected.  dpr1_eig_noalloc always writes
+                          after the eigenvalue kernel.                     */
   int32_t remedy;      /* Sec. 2, Algorithm 1's last branch: 1 = where K_nu
                           of eq. (K0) exceeds knu_thr, recompute the
                           eigenpair by remedy (R1) -- the other neighbouring
@@ -244,7 +245,8 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
  * of the inner sum keeps at least 64 terms), the register budget
  * waves_per_simd in {4, 6, 8}, for the model iteration (root = 1) the pass
  * budget main_passes ({2, 3} single, {2, 3, 4} batched) and, for one problem
- * with eigenvectors at n >= 8192, the write vwrite in {0 (overlapped), 1}.  Each
+ * with eigenvectors at n >= 8192, the write vwrite in {0 (after the
+ * eigenvalue kernel), 2 (overlapped in two chunks)}.  Each
  * candidate is solved once untimed and then `reps` times (0 = 3) between two
  * events on `stream`; the fastest mean wins, ties keep the earlier candidate
  * (smaller W, then fewer waves, then the smaller budget), and a 6- or 8-wave

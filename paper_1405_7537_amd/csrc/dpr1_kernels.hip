@@ -1496,8 +1496,8 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
 constexpr int VEC_T = 256;
 constexpr int VEC_ROWS = 2048;
 constexpr int VEC_C_SINGLE = 32, VEC_C_BATCH = 64;
-// chunks of the overlapped single-problem solve (opts.vwrite)
-constexpr int VEC_CHUNKS_DEFAULT = 2, VEC_CHUNKS_MAX = 8;
+// most chunks of the overlapped single-problem solve (opts.vwrite)
+constexpr int VEC_CHUNKS_MAX = 8;
 
 // Arguments of the eigenvector writer.  Columns flagged in vflag belong to
 // eigenpairs that k_fix finishes; they are skipped here and written by
@@ -2394,14 +2394,17 @@ static int launch_solve(const Layout& L, char* w, int64_t nprob, int64_t N, cons
                        vb);
   };
 
-  // A single problem with eigenvectors: the eigenvalue kernel runs in K
-  // launches over consecutive chunks of its groups of 64 eigenvalues, and the
-  // columns of chunk c are written on a second stream while chunk c + 1 is
-  // solved, so that the HBM-bound stores overlap the ALU-bound sweeps; the
-  // last chunk's columns are written beside k_fix.  Flagged columns are left
-  // to k_fixout, as in the sequential path.
-  // (below 8192 eigenpairs the write is short and the fork costs more than it hides)
-  const int nchunks = o.vwrite == 0 ? VEC_CHUNKS_DEFAULT : o.vwrite;
+  // A single problem with eigenvectors and opts.vwrite = K >= 2: the
+  // eigenvalue kernel runs in K launches over consecutive chunks of its
+  // groups of 64 eigenvalues, and the columns of chunk c are written on a
+  // second stream while chunk c + 1 is solved, so that the HBM-bound stores
+  // overlap the ALU-bound sweeps; the last chunk's columns are written beside
+  // k_fix.  Flagged columns are left to k_fixout, as in the sequential path.
+  // The default (0 or 1) writes V after the eigenvalue kernel, which measured
+  // faster at every order tried (n = 8192 .. 65536) since the address-ordered
+  // writer; below 8192 eigenpairs the write is short and the fork costs more
+  // than it hides in any case.
+  const int nchunks = o.vwrite <= 1 ? 1 : o.vwrite;
   bool overlap = V && !persistent_grid && nchunks >= 2 && aux_ok && N >= 8192 && nitems >= nchunks;
   hipStream_t st2 = overlap ? aux_stream() : nullptr;
   if (overlap && !st2) overlap = false;
@@ -2640,9 +2643,9 @@ int dpr1_autotune(const double* d, const double* z, double rho, int64_t n, doubl
   const int nw = split_candidates(n, ws);
   const int passes[2] = {2, 3};
   const int np = o.root == 1 ? 2 : 1;
-  // with eigenvectors at n >= 8192 also the write: overlapped (0) or after
-  // the eigenvalue kernel (1)
-  const int vws[2] = {0, 1};
+  // with eigenvectors at n >= 8192 also the write: after the eigenvalue
+  // kernel (0) or overlapped in two chunks (2)
+  const int vws[2] = {0, 2};
   const int nv = (V && n >= 8192) ? 2 : 1;
   double best = INFINITY;
   int bw = ws[0], bp = o.main_passes, bo = 4, bv = o.vwrite;

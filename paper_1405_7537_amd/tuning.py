@@ -18,7 +18,7 @@ import tempfile
 
 import numpy as np
 
-VERSION = 3
+VERSION = 4
 
 
 def cache_path() -> str:

@@ -392,15 +392,15 @@ def test_extreme_range_is_exact_or_reported(D, orc):
 
 
 def test_overlapped_write_matches_sequential(D):
-    """The overlapped eigenvector write (default: two chunks, n >= 8192; vwrite = 3 and 8: that
-    many chunks) and the sequential one (vwrite = 1) give the same outputs bit for bit, also with
+    """The overlapped eigenvector write (vwrite = 2, 3 and 8: that many chunks, n >= 8192) and the
+    sequential one (vwrite = 1 and the default 0) give the same outputs bit for bit, also with
     rho < 0 and a padded leading dimension."""
     import torch
     for n, rho, pad in ((8192, 1.0, 0), (10000, -0.5, 3)):
         d, z, _ = W.uniform(n, 61)
         print(f"[parity] overlap vs sequential n={n} rho={rho} pad={pad}", flush=True)
         outs = []
-        for vw in (1, 0, 3, 8):
+        for vw in (1, 0, 2, 3, 8):
             # outputs poisoned first: a fresh allocation may hold the previous solve's results
             o = (torch.full((n,), float("nan"), dtype=torch.float64, device="cuda"),
                  torch.full((n, n + pad), float("nan"), dtype=torch.float64, device="cuda")[:, :n],

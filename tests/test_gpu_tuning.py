@@ -35,9 +35,9 @@ def test_autotune_single_problem(D, orc):
 
 
 def test_autotune_chooses_the_write(D, tmp_path):
-    """At n >= 8192 with eigenvectors the tuner also chooses the write (vwrite 0: overlapped, 1:
-    after the eigenvalue kernel); the cache keeps the choice, and the tuned solve gives the
-    outputs of the other write mode bit for bit."""
+    """At n >= 8192 with eigenvectors the tuner also chooses the write (vwrite 0: after the
+    eigenvalue kernel, 2: overlapped in two chunks); the cache keeps the choice, and the tuned
+    solve gives the outputs of the other write mode bit for bit."""
     import torch
     from paper_1405_7537_amd import tuning as T
     n = 8192
@@ -45,12 +45,13 @@ def test_autotune_chooses_the_write(D, tmp_path):
     path = str(tmp_path / "tuning.json")
     o, entry, hit = T.tuned_opts(d, z, rho, reps=1, path=path)
     print(f"[tuning] n={n}: {entry}", flush=True)
-    assert not hit and o.vwrite in (0, 1) and entry["vwrite"] == o.vwrite
+    assert not hit and o.vwrite in (0, 2) and entry["vwrite"] == o.vwrite
     o2, entry2, hit2 = T.tuned_opts(d, z, rho, reps=1, path=path)
     assert hit2 and (o2.split, o2.waves_per_simd, o2.main_passes, o2.vwrite) == (o.split, o.waves_per_simd,
                                                                                  o.main_passes, o.vwrite)
     r = D.eig(d, z, rho, opts=o)
-    other = D.opts(split=o.split, waves_per_simd=o.waves_per_simd, main_passes=o.main_passes, vwrite=1 - o.vwrite)
+    other = D.opts(split=o.split, waves_per_simd=o.waves_per_simd, main_passes=o.main_passes,
+                   vwrite=2 if o.vwrite == 0 else 0)
     r2 = D.eig(d, z, rho, opts=other)
     torch.cuda.synchronize()
     assert torch.equal(r.lam, r2.lam) and torch.equal(r.V, r2.V)
