@@ -251,7 +251,7 @@ int dpr1_eig_batched(const dpr1_plan* plan, const int64_t* offs, const double* d
  * events on `stream`; the fastest mean wins, ties keep the earlier candidate
  * (smaller W, then fewer waves, then the smaller budget), and a 6- or 8-wave
  * register budget (which spills part of the eigenvalue kernel's state) must
- * be 2 % faster than the best so far to be chosen.  Both calls run on
+ * be 4 % faster than the best so far to be chosen.  Both calls run on
  * the caller's data and buffers, leave a
  * valid solution in the outputs (that of the last candidate, equal to the
  * tuned one's within the parity bounds) and synchronise `stream`.
