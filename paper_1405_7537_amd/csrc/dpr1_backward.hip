@@ -79,14 +79,16 @@ struct GArgs {
 // the forward and the backward.  d_{i_k} and 1/||x_k|| come precomputed
 // (k_bwd_y); the quotient is the refined reciprocal with one residual
 // correction, as in the forward's eigenvector writer.
-__device__ __forceinline__ double v_elem(const GArgs& g, int64_t vo, int64_t j, int64_t k) {
-  const double den = (g.d[vo + j] - g.sig[vo + k]) - g.mu[vo + k];
-  const double zj = g.z[vo + j];
+__device__ __forceinline__ double v_from(double dj, double zj, double sk, double mk, double ik) {
+  const double den = (dj - sk) - mk;
   double r = __builtin_amdgcn_rcp(den);
   r = __builtin_fma(r, __builtin_fma(-den, r, 1.0), r);
   double q = zj * r;
   q = __builtin_fma(__builtin_fma(-q, den, zj), r, q);
-  return q * g.ixn[vo + k];
+  return q * ik;
+}
+__device__ __forceinline__ double v_elem(const GArgs& g, int64_t vo, int64_t j, int64_t k) {
+  return v_from(g.d[vo + j], g.z[vo + j], g.sig[vo + k], g.mu[vo + k], g.ixn[vo + k]);
 }
 
 // Column-major n x n matrices (V with ld = lda, V_bar with ld = ldb; a
@@ -96,9 +98,9 @@ __device__ __forceinline__ double v_elem(const GArgs& g, int64_t vo, int64_t j, 
 // problem run on one XCD and share its L2.
 // RV: V is not passed in; its elements are rebuilt by v_elem (a separate
 // instance, so that the path with V keeps its plain loads).
-// Two blocks per CU (66.5 KB of LDS each) are 4 waves per SIMD, which leaves
-// 128 VGPRs a lane: the bound asks for that budget (the instance that rebuilds
-// V^T spills a few registers to stay in it, still faster than one block per CU).
+// Two blocks per CU (66.5 KB of LDS each, 68 KB where V^T is rebuilt) are 4
+// waves per SIMD, which leaves 128 VGPRs a lane: the bound asks for that
+// budget.
 template <int EPI, bool RV>
 __global__ void __launch_bounds__(NT, 4) k_gemm(GArgs g) {
   const int64_t n = g.n;
@@ -146,18 +148,54 @@ __global__ void __launch_bounds__(NT, 4) k_gemm(GArgs g) {
   const double* pA = RV ? nullptr : (EPI == EPI_X ? A + ek + (m0 + em) * lda : A + (m0 + em) + ek * lda);
   const double* pB = EPI == EPI_X ? Bm + ek + (n0 + em) * ldb : Bm + (int64_t)ek * n + (n0 + em);
   double ra[PER], rb[PER];
+  // V^T rebuilt (EPI_X): the tile's columns k = m0 .. m0 + BM - 1 keep their
+  // (d_{i_k}, mu_k, 1/||x_k||) in LDS for the whole K loop, and a thread's
+  // elements of one K step share their row j, so d_j and z_j load once
+  __shared__ double colc[RV && EPI == EPI_X ? 3 : 1][RV && EPI == EPI_X ? BM : 1];
+  // V rebuilt (EPI_D): a thread's elements all lie in its row j = m0 + em
+  double djr = 0.0, zjr = 0.0;
+  if constexpr (RV && EPI == EPI_D) {
+    if (m0 + em < n) {
+      djr = g.d[vo + m0 + em];
+      zjr = g.z[vo + m0 + em];
+    }
+  }
+  if constexpr (RV && EPI == EPI_X) {
+    for (int t = tid; t < BM; t += NT) {
+      const int64_t gm = m0 + t;
+      const bool ok = gm < n;
+      colc[0][t] = ok ? g.sig[vo + gm] : 0.0;
+      colc[1][t] = ok ? g.mu[vo + gm] : 0.0;
+      colc[2][t] = ok ? g.ixn[vo + gm] : 0.0;
+    }
+    __syncthreads();
+  }
   auto gload = [&](int64_t k0) {
+    double dj = 0.0, zj = 0.0;
+    if constexpr (RV && EPI == EPI_X) {
+      const int64_t gk = k0 + ek;
+      if (gk < n) {
+        dj = g.d[vo + gk];
+        zj = g.z[vo + gk];
+      }
+    }
 #pragma unroll
     for (int e2 = 0; e2 < PER; ++e2) {
       if (EPI == EPI_X) {
         // A^T(m, k) = V[k + m lda] and V_bar(k, c) = V_bar[k + c ldb], contiguous along k
         const int64_t gk = k0 + ek, gm = m0 + em + STEP * e2, gc = n0 + em + STEP * e2;
-        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gk, gm) : pA[k0 + STEP * e2 * lda]) : 0.0;
+        const int ml = em + STEP * e2;
+        ra[e2] = (gm < n && gk < n)
+                     ? (RV ? v_from(dj, zj, colc[0][RV ? ml : 0], colc[1][RV ? ml : 0], colc[2][RV ? ml : 0])
+                           : pA[k0 + STEP * e2 * lda])
+                     : 0.0;
         rb[e2] = (gk < n && gc < n) ? pB[k0 + STEP * e2 * ldb] : 0.0;
       } else {
         // A(m, k) = V[m + k lda], contiguous along m; X(k, c) = X[k n + c] (row-major), contiguous along c
         const int64_t gk = k0 + ek + STEP * e2, gm = m0 + em, gc = n0 + em;
-        ra[e2] = (gm < n && gk < n) ? (RV ? v_elem(g, vo, gm, gk) : pA[(k0 + STEP * e2) * lda]) : 0.0;
+        ra[e2] = (gm < n && gk < n)
+                     ? (RV ? v_from(djr, zjr, g.sig[vo + gk], g.mu[vo + gk], g.ixn[vo + gk]) : pA[(k0 + STEP * e2) * lda])
+                     : 0.0;
         rb[e2] = (gk < n && gc < n) ? pB[(k0 + STEP * e2) * n] : 0.0;
       }
     }
