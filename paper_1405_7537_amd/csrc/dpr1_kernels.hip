@@ -1495,7 +1495,9 @@ __global__ void __launch_bounds__(256) k_out(const Meta* __restrict__ meta, int 
 // row) from a table built by the plan.
 constexpr int VEC_T = 256;
 constexpr int VEC_ROWS = 2048;
-constexpr int VEC_C_SINGLE = 32, VEC_C_BATCH = 64;
+// columns per block: 32 for a batch as for one problem (64 measured 4-7 %
+// slower on the 2048-problem mix and on 4 problems of n = 16384, 16 no faster)
+constexpr int VEC_C_SINGLE = 32, VEC_C_BATCH = 32;
 // most chunks of the overlapped single-problem solve (opts.vwrite)
 constexpr int VEC_CHUNKS_MAX = 8;
 
